@@ -1,0 +1,223 @@
+"""FP64 CPU oracle for the compressible Navier-Stokes right-hand side and RK3 step.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline
+leg of the benchmark may use it; the product library never does.  It is an
+independent implementation (plain C in cdns_oracle.c, padded ghost arrays,
+literal formulas of the paper) and shares no code with the GPU path.  Both
+sides receive the same seeded inputs from the `problems` package.
+
+Parity status: every operator is pinned by CPU tests against closed forms,
+invariants or exact solutions (see tests/test_oracle_*.py); the
+characteristic outflow boundary is pinned only by a behaviour check
+(acoustic pulse reflection), so it is "parity unpinned" against the paper.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cdns_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+T_CONV, T_PRES, T_VISC, T_FORCE, T_ALL = 1, 2, 4, 8, 15
+
+ORA_OK, ORA_EINVAL, ORA_ENOMEM, ORA_ESTATE, ORA_EUNSUP = 0, -1, -2, -4, -5
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-std=c11", "-fPIC", "-shared",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("lx", ctypes.c_double), ("lz", ctypes.c_double),
+        ("y_eta", ctypes.POINTER(ctypes.c_double)),
+        ("y_etaeta", ctypes.POINTER(ctypes.c_double)),
+        ("gamma", ctypes.c_double), ("Pr", ctypes.c_double), ("R_gas", ctypes.c_double),
+        ("mu_ref", ctypes.c_double), ("T_ref", ctypes.c_double), ("S_suth", ctypes.c_double),
+        ("viscous", ctypes.c_int32), ("sensor_mode", ctypes.c_int32),
+        ("theta_star", ctypes.c_double), ("sensor_eps", ctypes.c_double),
+        ("forcing", ctypes.c_int32), ("terms", ctypes.c_int32),
+        ("bc_kind", ctypes.c_int32 * 6),
+        ("bc_params", ctypes.POINTER(ctypes.c_double) * 6),
+        ("bc_nparams", ctypes.c_int32 * 6),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        pp = ctypes.POINTER(_Problem)
+        lib.ora_rhs.argtypes = [pp, dp, dp, dp, u8p, u8p, dp]
+        lib.ora_rhs.restype = ctypes.c_int
+        lib.ora_dt.argtypes = [pp, dp, ctypes.c_double, dp]
+        lib.ora_dt.restype = ctypes.c_int
+        lib.ora_advance.argtypes = [pp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
+        lib.ora_advance.restype = ctypes.c_int
+        lib.ora_rk_stage.argtypes = [ctypes.c_size_t, dp, dp, dp, ctypes.c_double, ctypes.c_int, dp]
+        lib.ora_rk_stage.restype = None
+        lib.ora_weno5.argtypes = [dp]
+        lib.ora_weno5.restype = ctypes.c_double
+        lib.ora_eigenvectors.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp]
+        lib.ora_eigenvectors.restype = None
+        lib.ora_totals.argtypes = [pp, dp, dp]
+        lib.ora_totals.restype = ctypes.c_int
+        lib.ora_num_threads.argtypes = []
+        lib.ora_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class _Marshalled:
+    """Keeps the numpy buffers alive while the C struct points into them."""
+
+    def __init__(self, pr, terms: int = T_ALL):
+        self.keep = []
+        s = _Problem()
+        s.nx, s.ny, s.nz = pr.nx, pr.ny, pr.nz
+        s.lx, s.lz = pr.lx, pr.lz
+        ye = np.ascontiguousarray(pr.y_eta, dtype=np.float64)
+        yee = np.ascontiguousarray(pr.y_etaeta, dtype=np.float64)
+        self.keep += [ye, yee]
+        s.y_eta, s.y_etaeta = _dptr(ye), _dptr(yee)
+        s.gamma, s.Pr, s.R_gas = pr.gamma, pr.Pr, pr.R_gas
+        s.mu_ref, s.T_ref, s.S_suth = pr.mu_ref, pr.T_ref, pr.S_suth
+        s.viscous = int(bool(pr.viscous))
+        s.sensor_mode = int(pr.sensor_mode)
+        s.theta_star, s.sensor_eps = pr.theta_star, pr.sensor_eps
+        s.forcing = int(bool(pr.forcing))
+        s.terms = int(terms)
+        for f, (kind, params) in enumerate(pr.bcs):
+            arr = np.ascontiguousarray(np.asarray(params, dtype=np.float64).ravel())
+            if arr.size == 0:
+                arr = np.zeros(1)
+                n = 0
+            else:
+                n = arr.size
+            self.keep.append(arr)
+            s.bc_kind[f] = int(kind)
+            s.bc_params[f] = _dptr(arr)
+            s.bc_nparams[f] = n
+        self.s = s
+
+
+def _check(st: int, what: str):
+    if st != ORA_OK:
+        raise OracleError(f"{what} failed with status {st}")
+
+
+def rhs(pr, w: Optional[np.ndarray] = None, terms: int = T_ALL, want_flags: bool = False):
+    """R(w) on the whole grid.  Returns R (5,nz,ny,nx); with want_flags also
+    (theta, node_flags, iface_flags, forcing)."""
+    lib = _load()
+    w = np.ascontiguousarray(pr.w0 if w is None else w, dtype=np.float64)
+    shp = (pr.nz, pr.ny, pr.nx)
+    r = np.zeros((5,) + shp)
+    theta = np.zeros(shp)
+    nfl = np.zeros(shp, dtype=np.uint8)
+    ifl = np.zeros(shp, dtype=np.uint8)
+    f = ctypes.c_double(0.0)
+    m = _Marshalled(pr, terms)
+    st = lib.ora_rhs(ctypes.byref(m.s), _dptr(w), _dptr(r), _dptr(theta),
+                     nfl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                     ifl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), ctypes.byref(f))
+    _check(st, "ora_rhs")
+    if want_flags:
+        return r, theta, nfl, ifl, f.value
+    return r
+
+
+def dt(pr, w: Optional[np.ndarray] = None, cfl: Optional[float] = None) -> float:
+    lib = _load()
+    w = np.ascontiguousarray(pr.w0 if w is None else w, dtype=np.float64)
+    out = ctypes.c_double(0.0)
+    m = _Marshalled(pr)
+    _check(lib.ora_dt(ctypes.byref(m.s), _dptr(w), float(pr.cfl if cfl is None else cfl),
+                      ctypes.byref(out)), "ora_dt")
+    return out.value
+
+
+def advance(pr, nsteps: int, w: Optional[np.ndarray] = None, cfl: Optional[float] = None,
+            dt_fixed: float = 0.0, return_dts: bool = False):
+    """Advance a copy of the state by nsteps RK3 steps."""
+    lib = _load()
+    w = np.array(pr.w0 if w is None else w, dtype=np.float64, copy=True, order="C")
+    dts = np.zeros(max(nsteps, 1))
+    m = _Marshalled(pr)
+    st = lib.ora_advance(ctypes.byref(m.s), _dptr(w), int(nsteps),
+                         float(pr.cfl if cfl is None else cfl), float(dt_fixed), _dptr(dts))
+    _check(st, "ora_advance")
+    if return_dts:
+        return w, dts[:nsteps]
+    return w
+
+
+def rk_stage(w: np.ndarray, r: np.ndarray, rprev: np.ndarray, dt_: float, stage: int) -> np.ndarray:
+    """One low-storage RK3 stage on flat float64 arrays."""
+    lib = _load()
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    rprev = np.ascontiguousarray(rprev, dtype=np.float64)
+    out = np.empty_like(w)
+    lib.ora_rk_stage(w.size, _dptr(w), _dptr(r), _dptr(rprev), float(dt_), int(stage), _dptr(out))
+    return out
+
+
+def weno5(v) -> float:
+    lib = _load()
+    a = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
+    assert a.size == 5
+    return lib.ora_weno5(_dptr(a))
+
+
+def eigenvectors(gamma: float, d: int, u: float, v: float, w: float, Ht: float):
+    """(R, L) in natural component order: R[component, wave], L[wave, component]."""
+    lib = _load()
+    R = np.zeros(25)
+    L = np.zeros(25)
+    lib.ora_eigenvectors(gamma, d, u, v, w, Ht, _dptr(R), _dptr(L))
+    return R.reshape(5, 5), L.reshape(5, 5)
+
+
+def totals(pr, w: np.ndarray) -> np.ndarray:
+    """Volume integrals: mass, momentum (3), total energy, kinetic energy."""
+    lib = _load()
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    out = np.zeros(6)
+    m = _Marshalled(pr)
+    _check(lib.ora_totals(ctypes.byref(m.s), _dptr(w), _dptr(out)), "ora_totals")
+    return out
+
+
+def num_threads() -> int:
+    return _load().ora_num_threads()

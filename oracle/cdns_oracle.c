@@ -1,0 +1,885 @@
+/*
+ * cdns_oracle.c -- plain, slow FP64 CPU reference of the compressible
+ * Navier-Stokes right-hand side and the low-storage RK3 step of
+ * "STREAmS: a high-fidelity accelerated solver for direct numerical
+ * simulation of compressible turbulent flows" (arXiv 2004.02276).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the GPU library.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -std=c11 -fPIC -shared -lm
+ * (no contraction to fused multiply-add, t^{3/2} as t*sqrt(t)).
+ *
+ * Data layout of the caller's arrays: w[5][nz][ny][nx], x fastest.
+ * Internally every field lives on a padded grid with a halo of H = 3 nodes
+ * on each side; ghost nodes are filled explicitly (x faces, then y faces over
+ * the x-extended range, then z faces over the x,y-extended range) and every
+ * operator then reads plain neighbours.  This is deliberately the most
+ * direct form of the discretisation, not a fast one.
+ *
+ * Parity status of each function is stated beside it; all are pinned by
+ * the CPU tests (closed forms, invariants, exact solutions, convergence).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define H 3
+
+enum { BC_PERIODIC = 0, BC_WALL_ISO = 1, BC_WALL_ADIA = 2, BC_DIRICHLET = 3,
+       BC_OUTFLOW = 4, BC_SHOCK_TOP = 5 };
+enum { T_CONV = 1, T_PRES = 2, T_VISC = 4, T_FORCE = 8, T_ALL = 15 };
+enum { ORA_OK = 0, ORA_EINVAL = -1, ORA_ENOMEM = -2, ORA_ESTATE = -4, ORA_EUNSUP = -5 };
+
+typedef struct {
+  int32_t nx, ny, nz;
+  double lx, lz;
+  const double* y_eta;     /* [ny] */
+  const double* y_etaeta;  /* [ny] */
+  double gamma, Pr, R_gas, mu_ref, T_ref, S_suth;
+  int32_t viscous, sensor_mode;
+  double theta_star, sensor_eps;
+  int32_t forcing;
+  int32_t terms;           /* bit mask of T_* (T_ALL for the full operator) */
+  int32_t bc_kind[6];
+  const double* bc_params[6];
+  int32_t bc_nparams[6];
+} ora_problem;
+
+/* Standard 4th-order central coefficients (Sec. 2.1): first derivative
+ * a_1 = 2/3, a_2 = -1/12; second derivative b_0 = -5/2, b_1 = 4/3,
+ * b_2 = -1/12. */
+static const double A1 = 2.0 / 3.0, A2 = -1.0 / 12.0;
+static const double B0 = -5.0 / 2.0, B1 = 4.0 / 3.0, B2 = -1.0 / 12.0;
+
+/* Wray's low-storage RK3 (Sec. 2.2, eq. RK).  The second alpha is printed
+ * with a plus sign; only -17/60 makes the scheme consistent (weights sum to
+ * one) and third-order, so that is the reading used. */
+static const double RK_ALPHA[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
+static const double RK_BETA[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
+
+typedef struct {
+  int nx, ny, nz, nxp, nyp, nzp;
+  size_t np;
+  double dx, dz, deta;
+  double cv, cp;
+} geom;
+
+static void make_geom(const ora_problem* P, geom* g) {
+  g->nx = P->nx; g->ny = P->ny; g->nz = P->nz;
+  g->nxp = P->nx + 2 * H; g->nyp = P->ny + 2 * H; g->nzp = P->nz + 2 * H;
+  g->np = (size_t)g->nxp * g->nyp * g->nzp;
+  g->dx = P->lx / P->nx; g->dz = P->lz / P->nz; g->deta = 1.0 / P->ny;
+  g->cv = P->R_gas / (P->gamma - 1.0);
+  g->cp = P->gamma * P->R_gas / (P->gamma - 1.0);
+}
+
+static inline size_t pidx(const geom* g, int i, int j, int k) {
+  return ((size_t)(k + H) * g->nyp + (size_t)(j + H)) * g->nxp + (size_t)(i + H);
+}
+static inline size_t uidx(const geom* g, int i, int j, int k) {
+  return ((size_t)k * g->ny + (size_t)j) * g->nx + (size_t)i;
+}
+
+/* ------------------------------------------------------------ thermodynamics
+ * Perfect gas (Sec. 2): E = c_v T + |u|^2/2, p = rho R T, H = E + p/rho;
+ * Sutherland viscosity mu = mu_ref t^{3/2} (1+S)/(t+S), t = T/T_ref;
+ * conductivity k = c_p mu / Pr. */
+typedef struct { double rho, u, v, w, p, T, Ht, mu; } prim_t;
+
+static prim_t to_prim(const ora_problem* P, const geom* g, const double q[5]) {
+  prim_t s;
+  s.rho = q[0];
+  s.u = q[1] / q[0];
+  s.v = q[2] / q[0];
+  s.w = q[3] / q[0];
+  double ke = 0.5 * (s.u * s.u + s.v * s.v + s.w * s.w);
+  double E = q[4] / q[0];
+  s.T = (E - ke) / g->cv;
+  s.p = s.rho * P->R_gas * s.T;
+  s.Ht = E + s.p / s.rho;
+  double t = s.T / P->T_ref;
+  s.mu = P->mu_ref * t * sqrt(t) * (1.0 + P->S_suth) / (t + P->S_suth);
+  return s;
+}
+
+static void from_prim(const ora_problem* P, double rho, double u, double v, double w,
+                      double p, double q[5]) {
+  q[0] = rho;
+  q[1] = rho * u;
+  q[2] = rho * v;
+  q[3] = rho * w;
+  q[4] = p / (P->gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w);
+}
+
+/* ------------------------------------------------------------ eigenvectors
+ * Right/left eigenvectors of the Euler flux Jacobian in direction d, written
+ * for components permuted so that the normal momentum comes first:
+ * (rho, rho u_n, rho u_t1, rho u_t2, rho E).  Inputs are the state's normal
+ * and tangential velocities, total enthalpy and sound speed.  Used for the
+ * Lax-Friedrichs characteristic splitting of Sec. 2.1. */
+static void eigvecs_perm(double gm1, double un, double ut1, double ut2, double Ht, double c,
+                         double Rm[5][5], double Lm[5][5]) {
+  double q2 = un * un + ut1 * ut1 + ut2 * ut2;
+  double b1 = gm1 / (c * c);
+  double b2 = 0.5 * q2 * b1;
+  /* columns of R */
+  double R_[5][5] = {
+      {1.0, 1.0, 0.0, 0.0, 1.0},
+      {un - c, un, 0.0, 0.0, un + c},
+      {ut1, ut1, 1.0, 0.0, ut1},
+      {ut2, ut2, 0.0, 1.0, ut2},
+      {Ht - un * c, 0.5 * q2, ut1, ut2, Ht + un * c}};
+  double L_[5][5] = {
+      {0.5 * (b2 + un / c), -0.5 * (b1 * un + 1.0 / c), -0.5 * b1 * ut1, -0.5 * b1 * ut2, 0.5 * b1},
+      {1.0 - b2, b1 * un, b1 * ut1, b1 * ut2, -b1},
+      {-ut1, 0.0, 1.0, 0.0, 0.0},
+      {-ut2, 0.0, 0.0, 1.0, 0.0},
+      {0.5 * (b2 - un / c), -0.5 * (b1 * un - 1.0 / c), -0.5 * b1 * ut1, -0.5 * b1 * ut2, 0.5 * b1}};
+  memcpy(Rm, R_, sizeof(R_));
+  memcpy(Lm, L_, sizeof(L_));
+}
+
+/* permutation: component index in permuted order -> natural component index */
+static void perm_of_dir(int d, int pm[5]) {
+  pm[0] = 0; pm[4] = 4;
+  if (d == 0) { pm[1] = 1; pm[2] = 2; pm[3] = 3; }
+  else if (d == 1) { pm[1] = 2; pm[2] = 3; pm[3] = 1; }
+  else { pm[1] = 3; pm[2] = 1; pm[3] = 2; }
+}
+
+/* exported for tests: eigenvectors in natural component order for direction d */
+void ora_eigenvectors(double gamma, int d, double u, double v, double w, double Ht,
+                      double* Rout, double* Lout) {
+  int pm[5];
+  perm_of_dir(d, pm);
+  double vel[3] = {u, v, w};
+  double un = vel[d], ut1 = vel[(d + 1) % 3], ut2 = vel[(d + 2) % 3];
+  double c = sqrt((gamma - 1.0) * (Ht - 0.5 * (u * u + v * v + w * w)));
+  double Rm[5][5], Lm[5][5];
+  eigvecs_perm(gamma - 1.0, un, ut1, ut2, Ht, c, Rm, Lm);
+  /* natural R[row=component][col=wave] ; natural L[row=wave][col=component] */
+  for (int a = 0; a < 5; ++a)
+    for (int b = 0; b < 5; ++b) {
+      Rout[pm[a] * 5 + b] = Rm[a][b];
+      Lout[b * 5 + pm[a]] = Lm[b][a];
+    }
+}
+
+/* ------------------------------------------------------------ WENO5-JS
+ * Jiang-Shu fifth-order reconstruction at the right face of the central
+ * cell of (v[-2], v[-1], v[0], v[1], v[2]) = v[0..4]; eps = 1e-6, power 2,
+ * linear weights (1/10, 6/10, 3/10).  (Sec. 2.1; order not stated in the
+ * paper, fifth order assumed.) */
+double ora_weno5(const double* v) {
+  double vm2 = v[0], vm1 = v[1], v0 = v[2], vp1 = v[3], vp2 = v[4];
+  double q0 = (2.0 * vm2 - 7.0 * vm1 + 11.0 * v0) / 6.0;
+  double q1 = (-vm1 + 5.0 * v0 + 2.0 * vp1) / 6.0;
+  double q2 = (2.0 * v0 + 5.0 * vp1 - vp2) / 6.0;
+  double t;
+  double s0 = 13.0 / 12.0 * (t = vm2 - 2.0 * vm1 + v0, t * t) + 0.25 * (t = vm2 - 4.0 * vm1 + 3.0 * v0, t * t);
+  double s1 = 13.0 / 12.0 * (t = vm1 - 2.0 * v0 + vp1, t * t) + 0.25 * (t = vm1 - vp1, t * t);
+  double s2 = 13.0 / 12.0 * (t = v0 - 2.0 * vp1 + vp2, t * t) + 0.25 * (t = 3.0 * v0 - 4.0 * vp1 + vp2, t * t);
+  const double eps = 1e-6;
+  double a0 = 0.1 / ((eps + s0) * (eps + s0));
+  double a1 = 0.6 / ((eps + s1) * (eps + s1));
+  double a2 = 0.3 / ((eps + s2) * (eps + s2));
+  double sum = a0 + a1 + a2;
+  return (a0 * q0 + a1 * q1 + a2 * q2) / sum;
+}
+
+/* ------------------------------------------------------------ ghost nodes */
+static int fill_ghosts(const ora_problem* P, const geom* g, double* W[5]) {
+  const int nx = g->nx, ny = g->ny, nz = g->nz;
+  int bad = 0;
+  /* x faces (interior j, k) */
+  for (int side = 0; side < 2; ++side) {
+    int kind = P->bc_kind[side];
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < ny; ++j) {
+        if (kind == BC_PERIODIC) {
+          for (int s = 1; s <= H; ++s) {
+            int gi = side == 0 ? -s : nx - 1 + s;
+            int si = side == 0 ? nx - s : s - 1;
+            for (int m = 0; m < 5; ++m) W[m][pidx(g, gi, j, k)] = W[m][pidx(g, si, j, k)];
+          }
+        } else if (kind == BC_DIRICHLET) {
+          const double* pr = P->bc_params[side];
+          double q[5];
+          from_prim(P, pr[0 * ny + j], pr[1 * ny + j], pr[2 * ny + j], pr[3 * ny + j],
+                    pr[4 * ny + j], q);
+          for (int s = 1; s <= H; ++s) {
+            int gi = side == 0 ? -s : nx - 1 + s;
+            for (int m = 0; m < 5; ++m) W[m][pidx(g, gi, j, k)] = q[m];
+          }
+        } else if (kind == BC_OUTFLOW) {
+          /* characteristic extrapolation: only waves leaving the domain are
+           * extrapolated from the two boundary nodes, incoming ones are held */
+          int ib = side == 0 ? 0 : nx - 1;
+          int ii = side == 0 ? 1 : nx - 2;
+          double qb[5], qi[5], dq[5];
+          for (int m = 0; m < 5; ++m) {
+            qb[m] = W[m][pidx(g, ib, j, k)];
+            qi[m] = W[m][pidx(g, ii, j, k)];
+            dq[m] = qb[m] - qi[m];
+          }
+          prim_t s0 = to_prim(P, g, qb);
+          double c = sqrt(P->gamma * s0.p / s0.rho);
+          double Rn[25], Ln[25];
+          ora_eigenvectors(P->gamma, 0, s0.u, s0.v, s0.w, s0.Ht, Rn, Ln);
+          double lam[5] = {s0.u - c, s0.u, s0.u, s0.u, s0.u + c};
+          double dv[5];
+          for (int a = 0; a < 5; ++a) {
+            double acc = 0.0;
+            for (int b = 0; b < 5; ++b) acc += Ln[a * 5 + b] * dq[b];
+            int outgoing = side == 0 ? (lam[a] < 0.0) : (lam[a] > 0.0);
+            dv[a] = outgoing ? acc : 0.0;
+          }
+          for (int s = 1; s <= H; ++s) {
+            int gi = side == 0 ? -s : nx - 1 + s;
+            for (int m = 0; m < 5; ++m) {
+              double acc = 0.0;
+              for (int a = 0; a < 5; ++a) acc += Rn[m * 5 + a] * dv[a];
+              W[m][pidx(g, gi, j, k)] = qb[m] + (double)s * acc;
+            }
+          }
+        } else {
+          return ORA_EUNSUP;
+        }
+      }
+  }
+  /* y faces over the x-extended range, interior k */
+  for (int side = 0; side < 2; ++side) {
+    int kind = P->bc_kind[2 + side];
+    for (int k = 0; k < nz; ++k)
+      for (int i = -H; i < nx + H; ++i) {
+        for (int s = 1; s <= H; ++s) {
+          int gj = side == 0 ? -s : ny - 1 + s;
+          double q[5];
+          if (kind == BC_PERIODIC) {
+            int sj = side == 0 ? ny - s : s - 1;
+            for (int m = 0; m < 5; ++m) q[m] = W[m][pidx(g, i, sj, k)];
+          } else if (kind == BC_WALL_ISO || kind == BC_WALL_ADIA) {
+            /* mirror about the wall, which lies half-way between node 0 and
+             * ghost -1 (staggered wall, Sec. 3.1): ghost s <-> interior s-1 */
+            int mj = side == 0 ? s - 1 : ny - s;
+            double qm[5];
+            for (int m = 0; m < 5; ++m) qm[m] = W[m][pidx(g, i, mj, k)];
+            prim_t sm = to_prim(P, g, qm);
+            double Tg = kind == BC_WALL_ISO ? 2.0 * P->bc_params[2 + side][0] - sm.T : sm.T;
+            if (!(Tg > 0.0)) bad = 1;
+            double rg = sm.p / (P->R_gas * Tg);
+            from_prim(P, rg, -sm.u, -sm.v, -sm.w, sm.p, q);
+          } else if (kind == BC_SHOCK_TOP) {
+            const double* pr = P->bc_params[2 + side];
+            int ish = (int)pr[0];
+            const double* st = i < ish ? pr + 1 : pr + 6;
+            from_prim(P, st[0], st[1], st[2], st[3], st[4], q);
+          } else {
+            return ORA_EUNSUP;
+          }
+          for (int m = 0; m < 5; ++m) W[m][pidx(g, i, gj, k)] = q[m];
+        }
+      }
+  }
+  /* z faces over the x,y-extended range: only periodic is accepted */
+  if (P->bc_kind[4] != BC_PERIODIC || P->bc_kind[5] != BC_PERIODIC) return ORA_EUNSUP;
+  for (int j = -H; j < ny + H; ++j)
+    for (int i = -H; i < nx + H; ++i)
+      for (int s = 1; s <= H; ++s)
+        for (int m = 0; m < 5; ++m) {
+          W[m][pidx(g, i, j, -s)] = W[m][pidx(g, i, j, nz - s)];
+          W[m][pidx(g, i, j, nz - 1 + s)] = W[m][pidx(g, i, j, s - 1)];
+        }
+  return bad ? ORA_ESTATE : ORA_OK;
+}
+
+static int validate(const ora_problem* P) {
+  if (P->nx < 4 || P->ny < 4 || P->nz < 4) return ORA_EINVAL;
+  for (int a = 0; a < 3; ++a) {
+    int k0 = P->bc_kind[2 * a], k1 = P->bc_kind[2 * a + 1];
+    if ((k0 == BC_PERIODIC) != (k1 == BC_PERIODIC)) return ORA_EINVAL;
+  }
+  for (int f = 0; f < 6; ++f) {
+    int k = P->bc_kind[f];
+    int ax = f / 2;
+    if (k == BC_PERIODIC) continue;
+    if (ax == 2) return ORA_EUNSUP;
+    if (ax == 0 && !(k == BC_DIRICHLET || k == BC_OUTFLOW)) return ORA_EUNSUP;
+    if (ax == 1 && !(k == BC_WALL_ISO || k == BC_WALL_ADIA || k == BC_SHOCK_TOP)) return ORA_EUNSUP;
+    if (k == BC_DIRICHLET && P->bc_nparams[f] != 5 * P->ny) return ORA_EINVAL;
+    if (k == BC_WALL_ISO && P->bc_nparams[f] != 1) return ORA_EINVAL;
+    if (k == BC_SHOCK_TOP && P->bc_nparams[f] != 11) return ORA_EINVAL;
+  }
+  if (P->sensor_mode < 0 || P->sensor_mode > 2) return ORA_EINVAL;
+  return ORA_OK;
+}
+
+/* ------------------------------------------------------------ work arrays */
+typedef struct {
+  geom g;
+  double* W[5];               /* padded conserved */
+  double *rho, *u, *v, *w, *p, *T, *Ht, *mu;   /* padded primitives */
+  unsigned char* nflag;       /* padded node flags */
+  unsigned char* iflag[3];    /* padded interface flags, interface i+1/2 at node i */
+} work_t;
+
+static void work_free(work_t* a) {
+  for (int m = 0; m < 5; ++m) free(a->W[m]);
+  free(a->rho); free(a->u); free(a->v); free(a->w); free(a->p); free(a->T); free(a->Ht);
+  free(a->mu); free(a->nflag);
+  for (int d = 0; d < 3; ++d) free(a->iflag[d]);
+}
+
+static int work_alloc(const ora_problem* P, work_t* a) {
+  memset(a, 0, sizeof(*a));
+  make_geom(P, &a->g);
+  size_t n = a->g.np;
+  int ok = 1;
+  for (int m = 0; m < 5; ++m) ok &= (a->W[m] = calloc(n, sizeof(double))) != NULL;
+  ok &= (a->rho = calloc(n, sizeof(double))) != NULL;
+  ok &= (a->u = calloc(n, sizeof(double))) != NULL;
+  ok &= (a->v = calloc(n, sizeof(double))) != NULL;
+  ok &= (a->w = calloc(n, sizeof(double))) != NULL;
+  ok &= (a->p = calloc(n, sizeof(double))) != NULL;
+  ok &= (a->T = calloc(n, sizeof(double))) != NULL;
+  ok &= (a->Ht = calloc(n, sizeof(double))) != NULL;
+  ok &= (a->mu = calloc(n, sizeof(double))) != NULL;
+  ok &= (a->nflag = calloc(n, 1)) != NULL;
+  for (int d = 0; d < 3; ++d) ok &= (a->iflag[d] = calloc(n, 1)) != NULL;
+  if (!ok) { work_free(a); return ORA_ENOMEM; }
+  return ORA_OK;
+}
+
+/* load state, fill ghosts, compute primitives everywhere */
+static int prepare(const ora_problem* P, const double* w, work_t* a) {
+  const geom* g = &a->g;
+  for (int m = 0; m < 5; ++m)
+    for (int k = 0; k < g->nz; ++k)
+      for (int j = 0; j < g->ny; ++j)
+        for (int i = 0; i < g->nx; ++i)
+          a->W[m][pidx(g, i, j, k)] = w[(size_t)m * g->nx * g->ny * g->nz + uidx(g, i, j, k)];
+  int st = fill_ghosts(P, g, a->W);
+  if (st == ORA_EUNSUP) return st;
+  int bad = st == ORA_ESTATE;
+#pragma omp parallel for reduction(| : bad)
+  for (int k = -H; k < g->nz + H; ++k)
+    for (int j = -H; j < g->ny + H; ++j)
+      for (int i = -H; i < g->nx + H; ++i) {
+        size_t q = pidx(g, i, j, k);
+        double s5[5] = {a->W[0][q], a->W[1][q], a->W[2][q], a->W[3][q], a->W[4][q]};
+        prim_t s = to_prim(P, g, s5);
+        a->rho[q] = s.rho; a->u[q] = s.u; a->v[q] = s.v; a->w[q] = s.w;
+        a->p[q] = s.p; a->T[q] = s.T; a->Ht[q] = s.Ht; a->mu[q] = s.mu;
+        if (!(s.rho > 0.0) || !(s.T > 0.0) || !(s.p > 0.0)) bad = 1;
+      }
+  return bad ? ORA_ESTATE : ORA_OK;
+}
+
+/* ------------------------------------------------------------ derivatives
+ * First and second derivatives, 4th order (Sec. 2.1).  The y direction uses
+ * the computational coordinate eta with the analytic metric:
+ * d/dy = (1/y_eta) d/deta,  d2/dy2 = (d2/deta2 - y_etaeta d/dy)/y_eta^2. */
+static inline double d1(const double* f, size_t q, size_t s, double inv) {
+  return inv * (A1 * (f[q + s] - f[q - s]) + A2 * (f[q + 2 * s] - f[q - 2 * s]));
+}
+static inline double d2(const double* f, size_t q, size_t s, double inv2) {
+  return inv2 * (B0 * f[q] + B1 * (f[q + s] + f[q - s]) + B2 * (f[q + 2 * s] + f[q - 2 * s]));
+}
+
+/* ------------------------------------------------------------ shock sensor
+ * Ducros sensor (Sec. 2.1, eq. sensor):
+ * theta = max(-div u / sqrt(div^2 + |curl u|^2 + eps_s), 0), with the
+ * regulariser eps_s = (u0/L0)^2 given per case (the printed form is read as
+ * a squared inverse time scale). */
+static void sensor_theta(const ora_problem* P, work_t* a, double* theta /* [N] or NULL */) {
+  const geom* g = &a->g;
+  size_t sx = 1, sy = (size_t)g->nxp, sz = (size_t)g->nxp * g->nyp;
+#pragma omp parallel for
+  for (int k = 0; k < g->nz; ++k)
+    for (int j = 0; j < g->ny; ++j) {
+      double iy = 1.0 / (g->deta * P->y_eta[j]);
+      for (int i = 0; i < g->nx; ++i) {
+        size_t q = pidx(g, i, j, k);
+        double ux = d1(a->u, q, sx, 1.0 / g->dx), uy = d1(a->u, q, sy, iy), uz = d1(a->u, q, sz, 1.0 / g->dz);
+        double vx = d1(a->v, q, sx, 1.0 / g->dx), vy = d1(a->v, q, sy, iy), vz = d1(a->v, q, sz, 1.0 / g->dz);
+        double wx = d1(a->w, q, sx, 1.0 / g->dx), wy = d1(a->w, q, sy, iy), wz = d1(a->w, q, sz, 1.0 / g->dz);
+        double div = ux + vy + wz;
+        double ox = wy - vz, oy = uz - wx, oz = vx - uy;
+        double den = sqrt(div * div + (ox * ox + oy * oy + oz * oz) + P->sensor_eps);
+        double th = -div / den;
+        if (th < 0.0) th = 0.0;
+        if (theta) theta[uidx(g, i, j, k)] = th;
+        a->nflag[q] = th > P->theta_star;
+      }
+    }
+}
+
+/* flags of ghost nodes: copies under periodicity, unflagged otherwise */
+static void wrap_flags(const ora_problem* P, work_t* a) {
+  const geom* g = &a->g;
+  int per[3] = {P->bc_kind[0] == BC_PERIODIC, P->bc_kind[2] == BC_PERIODIC,
+                P->bc_kind[4] == BC_PERIODIC};
+  for (int k = -H; k < g->nz + H; ++k)
+    for (int j = -H; j < g->ny + H; ++j)
+      for (int i = -H; i < g->nx + H; ++i) {
+        int ii = i, jj = j, kk = k, ghost = 0;
+        if (i < 0 || i >= g->nx) { if (per[0]) ii = (i + g->nx) % g->nx; else ghost = 1; }
+        if (j < 0 || j >= g->ny) { if (per[1]) jj = (j + g->ny) % g->ny; else ghost = 1; }
+        if (k < 0 || k >= g->nz) { if (per[2]) kk = (k + g->nz) % g->nz; else ghost = 1; }
+        if (ii == i && jj == j && kk == k) continue;
+        a->nflag[pidx(g, i, j, k)] = ghost ? 0 : a->nflag[pidx(g, ii, jj, kk)];
+      }
+}
+
+/* Interface flags: interface i+1/2 in direction d uses the shock-capturing
+ * flux when the sensor mode forces it everywhere, or when any of the nodes
+ * i-1, i, i+1, i+2 (the central stencil) is flagged.  The two boundary
+ * interfaces of a non-periodic direction (walls and open boundaries) always
+ * use the central flux. */
+static void interface_flags(const ora_problem* P, work_t* a) {
+  const geom* g = &a->g;
+  int n[3] = {g->nx, g->ny, g->nz};
+  size_t st[3] = {1, (size_t)g->nxp, (size_t)g->nxp * g->nyp};
+  for (int d = 0; d < 3; ++d) {
+    int per = P->bc_kind[2 * d] == BC_PERIODIC;
+    for (int k = 0; k < g->nz; ++k)
+      for (int j = 0; j < g->ny; ++j)
+        for (int i = 0; i < g->nx; ++i) {
+          int id[3] = {i, j, k};
+          size_t q = pidx(g, i, j, k);
+          unsigned char f = 0;
+          if (!per && id[d] == n[d] - 1) f = 0;
+          else if (P->sensor_mode == 2) f = 1;
+          else if (P->sensor_mode == 1)
+            f = a->nflag[q - st[d]] | a->nflag[q] | a->nflag[q + st[d]] | a->nflag[q + 2 * st[d]];
+          a->iflag[d][q] = f;
+        }
+  }
+}
+
+/* ------------------------------------------------------------ Euler fluxes
+ * Three-point average operator (Sec. 2.1, eq. avg_operator). */
+static inline double tavg(double Fa, double Fb, double Ga, double Gb, double Ha, double Hb) {
+  return 0.125 * (Fa + Fb) * (Ga + Gb) * (Ha + Hb);
+}
+
+/* Energy-preserving central flux of order 4 (L = 2) at interface i+1/2,
+ * node i at padded index q, stride s along the direction d (eq. encflux):
+ * f = 2 sum_{l=1}^{2} a_l sum_{m=0}^{l-1} avg(rho, u_n, phi)_{i-m,l}, with
+ * phi = 1, u, v, w, H.  The pressure term of the momentum equation is put
+ * in the same conservative form with two-point averages,
+ * 2 sum_l a_l sum_m (p_{i-m} + p_{i-m+l})/2.  Output in natural order;
+ * conv/pres select the two parts (both for the full operator). */
+static void central_flux(const work_t* a, size_t q, size_t s, int d, int conv, int pres,
+                         double f[5]) {
+  const double* un = d == 0 ? a->u : (d == 1 ? a->v : a->w);
+  const double* r = a->rho;
+  const double* phis[5] = {NULL, a->u, a->v, a->w, a->Ht};
+  /* pairs (i-m, i-m+l): (i,i+1) l=1 m=0; (i,i+2) l=2 m=0; (i-1,i+1) l=2 m=1 */
+  size_t pa[3] = {q, q, q - s};
+  size_t pb[3] = {q + s, q + 2 * s, q + s};
+  double al[3] = {A1, A2, A2};
+  for (int c = 0; c < 5; ++c) {
+    double acc = 0.0;
+    for (int t = 0; t < 3; ++t) {
+      double phia = c == 0 ? 1.0 : phis[c][pa[t]];
+      double phib = c == 0 ? 1.0 : phis[c][pb[t]];
+      acc += al[t] * tavg(r[pa[t]], r[pb[t]], un[pa[t]], un[pb[t]], phia, phib);
+    }
+    f[c] = conv ? 2.0 * acc : 0.0;
+  }
+  if (pres) {
+    double acc = 0.0;
+    for (int t = 0; t < 3; ++t) acc += al[t] * 0.5 * (a->p[pa[t]] + a->p[pb[t]]);
+    f[1 + d] += 2.0 * acc;
+  }
+}
+
+/* Shock-capturing flux at interface i+1/2 (Sec. 2.1): Lax-Friedrichs flux
+ * vector splitting of the characteristic fields, each split flux
+ * reconstructed with WENO5.  Eigenvectors at the Roe average of nodes i and
+ * i+1; splitting constant per field = max |eigenvalue| over the six stencil
+ * nodes i-2..i+3 (local Lax-Friedrichs). */
+static void weno_flux(const ora_problem* P, const work_t* a, size_t q, size_t s, int d,
+                      double f[5]) {
+  int pm[5];
+  perm_of_dir(d, pm);
+  const double* vel[3] = {a->u, a->v, a->w};
+  /* Roe average */
+  size_t qL = q, qR = q + s;
+  double sl = sqrt(a->rho[qL]), sr = sqrt(a->rho[qR]);
+  double uroe[3];
+  for (int c = 0; c < 3; ++c) uroe[c] = (sl * vel[c][qL] + sr * vel[c][qR]) / (sl + sr);
+  double Hroe = (sl * a->Ht[qL] + sr * a->Ht[qR]) / (sl + sr);
+  double q2 = uroe[0] * uroe[0] + uroe[1] * uroe[1] + uroe[2] * uroe[2];
+  double croe = sqrt((P->gamma - 1.0) * (Hroe - 0.5 * q2));
+  double Rm[5][5], Lm[5][5];
+  eigvecs_perm(P->gamma - 1.0, uroe[d], uroe[(d + 1) % 3], uroe[(d + 2) % 3], Hroe, croe, Rm, Lm);
+  /* stencil values */
+  double gp[6][5], gmn[6][5], alpha[5] = {0, 0, 0, 0, 0};
+  double vch[6][5], gch[6][5];
+  for (int t = 0; t < 6; ++t) {
+    size_t qs = q + (size_t)((long)(t - 2) * (long)s);
+    double wn[5], fn[5];
+    for (int c = 0; c < 5; ++c) wn[c] = a->W[pm[c]][qs];
+    double un = vel[d][qs];
+    double cs = sqrt(P->gamma * a->p[qs] / a->rho[qs]);
+    fn[0] = a->rho[qs] * un;
+    fn[1] = a->rho[qs] * un * un + a->p[qs];
+    fn[2] = a->rho[qs] * un * vel[(d + 1) % 3][qs];
+    fn[3] = a->rho[qs] * un * vel[(d + 2) % 3][qs];
+    fn[4] = un * (a->W[4][qs] + a->p[qs]);
+    double lam[5] = {fabs(un - cs), fabs(un), fabs(un), fabs(un), fabs(un + cs)};
+    for (int k = 0; k < 5; ++k) {
+      if (lam[k] > alpha[k]) alpha[k] = lam[k];
+      double av = 0.0, ag = 0.0;
+      for (int c = 0; c < 5; ++c) { av += Lm[k][c] * wn[c]; ag += Lm[k][c] * fn[c]; }
+      vch[t][k] = av;
+      gch[t][k] = ag;
+    }
+  }
+  double ghat[5];
+  for (int k = 0; k < 5; ++k) {
+    for (int t = 0; t < 6; ++t) {
+      gp[t][k] = 0.5 * (gch[t][k] + alpha[k] * vch[t][k]);
+      gmn[t][k] = 0.5 * (gch[t][k] - alpha[k] * vch[t][k]);
+    }
+    double sp[5] = {gp[0][k], gp[1][k], gp[2][k], gp[3][k], gp[4][k]};       /* i-2..i+2 */
+    double sm[5] = {gmn[5][k], gmn[4][k], gmn[3][k], gmn[2][k], gmn[1][k]};  /* i+3..i-1 */
+    ghat[k] = ora_weno5(sp) + ora_weno5(sm);
+  }
+  for (int c = 0; c < 5; ++c) {
+    double acc = 0.0;
+    for (int k = 0; k < 5; ++k) acc += Rm[c][k] * ghat[k];
+    f[pm[c]] = acc;
+  }
+}
+
+static void euler_terms(const ora_problem* P, work_t* a, double* r) {
+  const geom* g = &a->g;
+  int conv = (P->terms & T_CONV) != 0, pres = (P->terms & T_PRES) != 0;
+  size_t N = (size_t)g->nx * g->ny * g->nz;
+  size_t st[3] = {1, (size_t)g->nxp, (size_t)g->nxp * g->nyp};
+  int n[3] = {g->nx, g->ny, g->nz};
+  for (int d = 0; d < 3; ++d) {
+    int wall_lo = d == 1 && (P->bc_kind[2] == BC_WALL_ISO || P->bc_kind[2] == BC_WALL_ADIA);
+    int wall_hi = d == 1 && (P->bc_kind[3] == BC_WALL_ISO || P->bc_kind[3] == BC_WALL_ADIA);
+    /* lines along d */
+    int o1 = (d + 1) % 3, o2 = (d + 2) % 3;
+#pragma omp parallel for collapse(2)
+    for (int b2 = 0; b2 < n[o2]; ++b2)
+      for (int b1 = 0; b1 < n[o1]; ++b1) {
+        double (*F)[5] = malloc(sizeof(double[5]) * (size_t)(n[d] + 1));
+        for (int ii = -1; ii < n[d]; ++ii) {
+          int id[3];
+          id[d] = ii; id[o1] = b1; id[o2] = b2;
+          size_t q = pidx(g, id[0], id[1], id[2]);
+          double f[5];
+          int boundary = (ii == -1) || (ii == n[d] - 1);
+          int use_weno = 0;
+          if (P->sensor_mode > 0 && ii >= 0) use_weno = a->iflag[d][q];
+          if (P->sensor_mode > 0 && ii == -1) {
+            /* interface -1/2 is the periodic image of n-1/2 */
+            int idw[3] = {id[0], id[1], id[2]};
+            idw[d] = n[d] - 1;
+            use_weno = a->iflag[d][pidx(g, idw[0], idw[1], idw[2])];
+          }
+          (void)boundary;
+          if (use_weno) weno_flux(P, a, q, st[d], d, f);
+          else central_flux(a, q, st[d], d, conv, pres, f);
+          if ((ii == -1 && wall_lo) || (ii == n[d] - 1 && wall_hi)) {
+            /* staggered wall: convective fluxes vanish, only pressure acts */
+            double fp[5];
+            central_flux(a, q, st[d], d, 0, pres, fp);
+            for (int c = 0; c < 5; ++c) f[c] = fp[c];
+          }
+          for (int c = 0; c < 5; ++c) F[ii + 1][c] = f[c];
+        }
+        for (int ii = 0; ii < n[d]; ++ii) {
+          int id[3];
+          id[d] = ii; id[o1] = b1; id[o2] = b2;
+          double delta = d == 0 ? g->dx : (d == 2 ? g->dz : g->deta * P->y_eta[id[1]]);
+          size_t u = uidx(g, id[0], id[1], id[2]);
+          for (int c = 0; c < 5; ++c) r[(size_t)c * N + u] -= (F[ii + 1][c] - F[ii][c]) / delta;
+        }
+        free(F);
+      }
+  }
+}
+
+/* ------------------------------------------------------------ viscous terms
+ * Laplacian form (Sec. 2.1): d/dx_j (mu du/dx_j) = dmu/dx_j du/dx_j +
+ * mu d2u/dx_j2 with 4th-order first and second derivatives; the stress
+ * divergence expands to
+ *   F_i = mu (lap u_i + (1/3) d_i div) + d_j mu (d_j u_i + d_i u_j) - (2/3) d_i mu div,
+ * the energy equation receives u_i F_i + sigma_ij d_j u_i (the work of the
+ * stresses) plus k lap T + d_j k d_j T (heat conduction, k = c_p mu/Pr).
+ * Mixed derivatives are first derivatives of first derivatives:
+ * d_x d_y f = D_y(D_x f), d_x d_z f = D_z(D_x f), d_y d_z f = D_z(D_y f). */
+static void viscous_terms(const ora_problem* P, work_t* a, double* r) {
+  const geom* g = &a->g;
+  size_t N = (size_t)g->nx * g->ny * g->nz;
+  size_t sx = 1, sy = (size_t)g->nxp, sz = (size_t)g->nxp * g->nyp;
+  double ix = 1.0 / g->dx, iz = 1.0 / g->dz;
+  double ix2 = ix * ix, iz2 = iz * iz, ie2 = 1.0 / (g->deta * g->deta);
+  double kfac = g->cp / P->Pr;
+#pragma omp parallel for
+  for (int k = 0; k < g->nz; ++k)
+    for (int j = 0; j < g->ny; ++j) {
+      double ye = P->y_eta[j], yee = P->y_etaeta[j];
+      double iy = 1.0 / (g->deta * ye);
+      for (int i = 0; i < g->nx; ++i) {
+        size_t q = pidx(g, i, j, k);
+        const double* fld[4] = {a->u, a->v, a->w, a->T};
+        double gx[4], gy[4], gz[4], lap[4];
+        for (int f = 0; f < 4; ++f) {
+          gx[f] = d1(fld[f], q, sx, ix);
+          gy[f] = d1(fld[f], q, sy, iy);
+          gz[f] = d1(fld[f], q, sz, iz);
+          double fxx = d2(fld[f], q, sx, ix2);
+          double fyy = (d2(fld[f], q, sy, ie2) - yee * gy[f]) / (ye * ye);
+          double fzz = d2(fld[f], q, sz, iz2);
+          lap[f] = fxx + fyy + fzz;
+        }
+        double uxx = d2(a->u, q, sx, ix2);
+        double vyy = (d2(a->v, q, sy, ie2) - yee * gy[1]) / (ye * ye);
+        double wzz = d2(a->w, q, sz, iz2);
+        /* mixed derivatives as compositions of first derivatives */
+        double ux_at[5], vx_at[5], ux_z[5], wx_z[5], vy_z[5], wy_z[5];
+        for (int l = -2; l <= 2; ++l) {
+          size_t qy = q + (size_t)((long)l * (long)sy);
+          ux_at[l + 2] = d1(a->u, qy, sx, ix);
+          vx_at[l + 2] = d1(a->v, qy, sx, ix);
+          size_t qz = q + (size_t)((long)l * (long)sz);
+          ux_z[l + 2] = d1(a->u, qz, sx, ix);
+          wx_z[l + 2] = d1(a->w, qz, sx, ix);
+          vy_z[l + 2] = d1(a->v, qz, sy, iy);
+          wy_z[l + 2] = d1(a->w, qz, sy, iy);
+        }
+#define D1ARR(arr, inv) ((inv) * (A1 * ((arr)[3] - (arr)[1]) + A2 * ((arr)[4] - (arr)[0])))
+        double uxy = D1ARR(ux_at, iy), vxy = D1ARR(vx_at, iy);
+        double uxz = D1ARR(ux_z, iz), wxz = D1ARR(wx_z, iz);
+        double vyz = D1ARR(vy_z, iz), wyz = D1ARR(wy_z, iz);
+#undef D1ARR
+        double mux = d1(a->mu, q, sx, ix), muy = d1(a->mu, q, sy, iy), muz = d1(a->mu, q, sz, iz);
+        double mu = a->mu[q];
+        double ux = gx[0], uy = gy[0], uz = gz[0];
+        double vx = gx[1], vy = gy[1], vz = gz[1];
+        double wx = gx[2], wy = gy[2], wz = gz[2];
+        double div = ux + vy + wz;
+        double ddx = uxx + vxy + wxz;  /* d/dx div */
+        double ddy = uxy + vyy + wyz;  /* d/dy div */
+        double ddz = uxz + vyz + wzz;  /* d/dz div */
+        double Fx = mu * (lap[0] + ddx / 3.0) + mux * (ux + ux) + muy * (uy + vx) + muz * (uz + wx)
+                    - 2.0 / 3.0 * mux * div;
+        double Fy = mu * (lap[1] + ddy / 3.0) + mux * (vx + uy) + muy * (vy + vy) + muz * (vz + wy)
+                    - 2.0 / 3.0 * muy * div;
+        double Fz = mu * (lap[2] + ddz / 3.0) + mux * (wx + uz) + muy * (wy + vz) + muz * (wz + wz)
+                    - 2.0 / 3.0 * muz * div;
+        /* sigma_ij d_j u_i */
+        double sxx = mu * (2.0 * ux - 2.0 / 3.0 * div);
+        double syy = mu * (2.0 * vy - 2.0 / 3.0 * div);
+        double szz = mu * (2.0 * wz - 2.0 / 3.0 * div);
+        double sxy = mu * (uy + vx), sxz = mu * (uz + wx), syz = mu * (vz + wy);
+        double phi = sxx * ux + syy * vy + szz * wz + sxy * (uy + vx) + sxz * (uz + wx) + syz * (vz + wy);
+        double kk = kfac * mu;
+        double heat = kk * lap[3] + kfac * (mux * gx[3] + muy * gy[3] + muz * gz[3]);
+        size_t uq = uidx(g, i, j, k);
+        double uu = a->u[q], vv = a->v[q], ww = a->w[q];
+        r[1 * N + uq] += Fx;
+        r[2 * N + uq] += Fy;
+        r[3 * N + uq] += Fz;
+        r[4 * N + uq] += uu * Fx + vv * Fy + ww * Fz + phi + heat;
+      }
+    }
+}
+
+/* ------------------------------------------------------------ bulk forcing
+ * Constant mass flow (Sec. 2): a uniform streamwise body force f chosen so
+ * that the volume integral of the streamwise momentum residual vanishes,
+ * f = -sum(R_rhou dV)/sum(dV) with dV proportional to y_eta; its power f u
+ * enters the energy equation.  Applied at every stage evaluation.  The sum
+ * runs in a fixed serial order. */
+static double apply_forcing(const ora_problem* P, const work_t* a, double* r) {
+  const geom* g = &a->g;
+  size_t N = (size_t)g->nx * g->ny * g->nz;
+  double num = 0.0, den = 0.0;
+  for (int k = 0; k < g->nz; ++k)
+    for (int j = 0; j < g->ny; ++j)
+      for (int i = 0; i < g->nx; ++i) {
+        num += r[1 * N + uidx(g, i, j, k)] * P->y_eta[j];
+        den += P->y_eta[j];
+      }
+  double f = -num / den;
+  for (int k = 0; k < g->nz; ++k)
+    for (int j = 0; j < g->ny; ++j)
+      for (int i = 0; i < g->nx; ++i) {
+        size_t u = uidx(g, i, j, k);
+        r[1 * N + u] += f;
+        r[4 * N + u] += f * a->u[pidx(g, i, j, k)];
+      }
+  return f;
+}
+
+/* ------------------------------------------------------------ entry points */
+static int rhs_core(const ora_problem* P, const double* w, double* r, double* theta,
+                    unsigned char* nflags, unsigned char* iflags, double* fout) {
+  int st = validate(P);
+  if (st) return st;
+  work_t a;
+  if (work_alloc(P, &a)) return ORA_ENOMEM;
+  st = prepare(P, w, &a);
+  if (st) { work_free(&a); return st; }
+  const geom* g = &a.g;
+  size_t N = (size_t)g->nx * g->ny * g->nz;
+  if (P->sensor_mode == 1) {
+    sensor_theta(P, &a, theta);
+    wrap_flags(P, &a);
+  } else if (theta) {
+    memset(theta, 0, N * sizeof(double));
+  }
+  interface_flags(P, &a);
+  if (nflags || iflags)
+    for (int k = 0; k < g->nz; ++k)
+      for (int j = 0; j < g->ny; ++j)
+        for (int i = 0; i < g->nx; ++i) {
+          size_t q = pidx(g, i, j, k), u = uidx(g, i, j, k);
+          if (nflags) nflags[u] = a.nflag[q];
+          if (iflags)
+            iflags[u] = (unsigned char)(a.iflag[0][q] | (a.iflag[1][q] << 1) | (a.iflag[2][q] << 2));
+        }
+  memset(r, 0, 5 * N * sizeof(double));
+  euler_terms(P, &a, r);
+  if (P->viscous && (P->terms & T_VISC)) viscous_terms(P, &a, r);
+  double f = 0.0;
+  if (P->forcing && (P->terms & T_FORCE)) f = apply_forcing(P, &a, r);
+  if (fout) *fout = f;
+  work_free(&a);
+  return ORA_OK;
+}
+
+/* Full right-hand side R(w) of the semi-discrete system dw/dt = R(w)
+ * (Sec. 2.2).  theta (node sensor values), nflags (node flags) and iflags
+ * (bit d set when interface i+1/2 in direction d is shock-capturing) are
+ * optional outputs; forcing_out receives the bulk force. */
+int ora_rhs(const ora_problem* P, const double* w, double* r, double* theta,
+            unsigned char* nflags, unsigned char* iflags, double* forcing_out) {
+  return rhs_core(P, w, r, theta, nflags, iflags, forcing_out);
+}
+
+/* Time step (the paper gives no rule): dt = CFL * min(1/max_i sum_d (|u_d|+c)/dx_d,
+ * 2.5/max_i [max(4/3, gamma/Pr) (mu/rho) (16/3) sum_d dx_d^-2]); 2.5 is about
+ * the real-axis stability bound of the RK3 scheme and 16/3 the largest
+ * magnitude of the 4th-order second-derivative symbol. */
+int ora_dt(const ora_problem* P, const double* w, double cfl, double* dt_out) {
+  int st = validate(P);
+  if (st) return st;
+  geom g;
+  make_geom(P, &g);
+  size_t N = (size_t)g.nx * g.ny * g.nz;
+  double cmax = 0.0, vmax = 0.0;
+  double vf = 4.0 / 3.0 > P->gamma / P->Pr ? 4.0 / 3.0 : P->gamma / P->Pr;
+  for (int k = 0; k < g.nz; ++k)
+    for (int j = 0; j < g.ny; ++j) {
+      double dy = g.deta * P->y_eta[j];
+      for (int i = 0; i < g.nx; ++i) {
+        size_t u = uidx(&g, i, j, k);
+        double q[5] = {w[u], w[N + u], w[2 * N + u], w[3 * N + u], w[4 * N + u]};
+        prim_t s = to_prim(P, &g, q);
+        double c = sqrt(P->gamma * s.p / s.rho);
+        double conv = (fabs(s.u) + c) / g.dx + (fabs(s.v) + c) / dy + (fabs(s.w) + c) / g.dz;
+        if (conv > cmax) cmax = conv;
+        if (P->viscous) {
+          double vis = vf * (s.mu / s.rho) * (1.0 / (g.dx * g.dx) + 1.0 / (dy * dy) + 1.0 / (g.dz * g.dz));
+          if (vis > vmax) vmax = vis;
+        }
+      }
+    }
+  double dt = 1.0 / cmax;
+  if (P->viscous && vmax > 0.0) {
+    double dv = 2.5 / (16.0 / 3.0 * vmax);
+    if (dv < dt) dt = dv;
+  }
+  *dt_out = cfl * dt;
+  return ORA_OK;
+}
+
+/* One low-storage stage: out = w + dt (alpha_l rprev + beta_l r). */
+void ora_rk_stage(size_t n, const double* w, const double* r, const double* rprev, double dt,
+                  int l, double* out) {
+  for (size_t i = 0; i < n; ++i) {
+    double acc = RK_BETA[l] * r[i];
+    if (l > 0) acc += RK_ALPHA[l] * rprev[i];
+    out[i] = w[i] + dt * acc;
+  }
+}
+
+/* Advance nsteps RK3 steps in place.  dt_fixed > 0 overrides the CFL rule;
+ * otherwise dt is taken from the state at the start of each step.  dts (if
+ * not NULL, length nsteps) receives the steps used. */
+int ora_advance(const ora_problem* P, double* w, int nsteps, double cfl, double dt_fixed,
+                double* dts) {
+  int st = validate(P);
+  if (st) return st;
+  size_t N = (size_t)P->nx * P->ny * P->nz, n5 = 5 * N;
+  double* r = malloc(n5 * sizeof(double));
+  double* rp = malloc(n5 * sizeof(double));
+  double* ws = malloc(n5 * sizeof(double));
+  if (!r || !rp || !ws) { free(r); free(rp); free(ws); return ORA_ENOMEM; }
+  for (int step = 0; step < nsteps && st == ORA_OK; ++step) {
+    double dt = dt_fixed;
+    if (!(dt_fixed > 0.0)) {
+      st = ora_dt(P, w, cfl, &dt);
+      if (st) break;
+    }
+    if (dts) dts[step] = dt;
+    for (int l = 0; l < 3; ++l) {
+      st = rhs_core(P, w, r, NULL, NULL, NULL, NULL);
+      if (st) break;
+      ora_rk_stage(n5, w, r, rp, dt, l, ws);
+      memcpy(w, ws, n5 * sizeof(double));
+      double* t = rp; rp = r; r = t;
+    }
+  }
+  free(r); free(rp); free(ws);
+  return st;
+}
+
+/* Volume-weighted totals (dV = dx dz deta y_eta): mass, momentum x,y,z,
+ * total energy and kinetic energy. */
+int ora_totals(const ora_problem* P, const double* w, double* out6) {
+  geom g;
+  make_geom(P, &g);
+  size_t N = (size_t)g.nx * g.ny * g.nz;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = 0; k < g.nz; ++k)
+    for (int j = 0; j < g.ny; ++j) {
+      double dv = g.dx * g.dz * g.deta * P->y_eta[j];
+      for (int i = 0; i < g.nx; ++i) {
+        size_t u = uidx(&g, i, j, k);
+        for (int m = 0; m < 5; ++m) acc[m] += w[m * N + u] * dv;
+        acc[5] += 0.5 * (w[N + u] * w[N + u] + w[2 * N + u] * w[2 * N + u] + w[3 * N + u] * w[3 * N + u])
+                  / w[u] * dv;
+      }
+    }
+  for (int m = 0; m < 6; ++m) out6[m] = acc[m];
+  return ORA_OK;
+}
+
+int ora_num_threads(void) {
+  int n = 1;
+#ifdef _OPENMP
+#pragma omp parallel
+  {
+#pragma omp single
+    n = omp_get_num_threads();
+  }
+#endif
+  return n;
+}
