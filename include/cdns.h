@@ -1,0 +1,216 @@
+/*
+ * cdns.h -- C ABI of the MI355X library for the right-hand side and
+ * low-storage RK3 step of the compressible Navier-Stokes equations as
+ * discretised in "STREAmS: a high-fidelity accelerated solver for direct
+ * numerical simulation of compressible turbulent flows" (arXiv 2004.02276).
+ *
+ * Equations (Sec. 2, eqs. mass/momentum/energy): conservation of mass,
+ * momentum and total energy of a perfect heat-conducting gas with Newtonian
+ * stresses, Fourier heat flux, Sutherland viscosity, k = c_p mu / Pr, and an
+ * optional streamwise body force f with power f u (constant mass flow).
+ * Convective terms (Sec. 2.1, eqs. num_flux, avg_operator, encflux): fourth
+ * order kinetic-energy-preserving central flux in split form, replaced at
+ * interfaces flagged by the Ducros sensor (eq. sensor) with WENO
+ * reconstruction of Lax-Friedrichs-split characteristic fluxes.  Viscous
+ * terms in Laplacian form with fourth-order formulas.  Time integration
+ * (Sec. 2.2, eq. RK): Wray's three-stage low-storage scheme.
+ *
+ * Conventions
+ *  - Every function returns a cdns_status; nothing aborts or throws across
+ *    the ABI.  On error the context's message is available from
+ *    cdns_last_error().
+ *  - Device memory is owned by the caller (allocated, e.g., by PyTorch).
+ *    The library never frees caller memory and calls no device allocator
+ *    on the stepping path.
+ *  - State layout: double w[5][nz][ny][nx] (x fastest) holding
+ *    (rho, rho u, rho v, rho w, rho E); same layout for right-hand sides.
+ *  - Non-dimensional variables: the gas constant R_gas sets the reference
+ *    Mach number (R = 1/(gamma M^2) with unit reference density,
+ *    velocity and temperature); c_v = R/(gamma-1), c_p = gamma R/(gamma-1).
+ *  - Grid: x and z uniform (dx = lx/nx, dz = lz/nz); y given by the metric
+ *    of a mapping y(eta) sampled at the nodes, d_eta = 1/ny.  With walls
+ *    the nodes sit at eta_j = (j+1/2)/ny so the walls fall half-way
+ *    between the last node and the first ghost (staggered wall, Sec. 3.1).
+ *  - All work is enqueued on the hip stream given at creation and is
+ *    asynchronous, except cdns_diagnostics() and cdns_get_theta(), which
+ *    synchronise that stream.
+ */
+#ifndef CDNS_H
+#define CDNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cdns_status;
+enum {
+  CDNS_OK = 0,
+  CDNS_EINVAL = -1,  /* invalid argument or unsupported combination of values */
+  CDNS_ENOMEM = -2,  /* workspace too small */
+  CDNS_EHIP = -3,    /* a HIP runtime call failed */
+  CDNS_ESTATE = -4,  /* device detected a non-finite or non-positive state */
+  CDNS_EUNSUP = -5,  /* boundary condition not supported on that face */
+  CDNS_EBUSY = -6    /* batch full / slot in use */
+};
+
+/* Arithmetic of the flux evaluation.  CDNS_FP32_FLUX evaluates the central
+ * and shock-capturing fluxes and the viscous terms in single precision; the
+ * stored state, the RK accumulation, the shock sensor and every reduction
+ * stay double precision. */
+enum { CDNS_FP64 = 0, CDNS_FP32_FLUX = 1 };
+
+/* Shock sensor mode: central flux only; hybrid (sensor-driven switch);
+ * shock-capturing flux at every interior interface. */
+enum { CDNS_SENSOR_OFF = 0, CDNS_SENSOR_HYBRID = 1, CDNS_SENSOR_WENO_ALL = 2 };
+
+/* Boundary conditions (faces 0..5 = x-, x+, y-, y+, z-, z+).  Ghost nodes
+ * (3 per face) are filled x faces first, then y faces over the x-extended
+ * range; z must be periodic.
+ *  PERIODIC        both faces of an axis; no parameters.
+ *  WALL_ISOTHERMAL y faces; params[0] = wall temperature T_w.  No-slip
+ *                  staggered wall: ghost s mirrors interior node s-1 with
+ *                  u -> -u, p -> p, T -> 2 T_w - T; the wall interface
+ *                  carries no convective flux, only pressure (Sec. 3.1).
+ *  WALL_ADIABATIC  y faces; as above with T -> T.
+ *  DIRICHLET       x faces; params = primitive profile (rho,u,v,w,p) as
+ *                  5 rows of ny values (row-major [5][ny]) imposed at the
+ *                  ghost nodes (inflow).
+ *  OUTFLOW_CHAR    x faces; characteristic extrapolation: the wave
+ *                  amplitudes of (w_b - w_{b-1}) travelling out of the
+ *                  domain are extrapolated linearly, incoming ones are held
+ *                  (Sec. 3.2: non-reflecting treatment by characteristic
+ *                  decomposition normal to the boundary; the exact form is a
+ *                  reading, the paper gives no formula).
+ *  SHOCK_TOP       y faces; params = {i_shock, rho1,u1,v1,w1,p1,
+ *                  rho2,u2,v2,w2,p2}: ghost nodes take state 1 for
+ *                  i < i_shock and state 2 otherwise (imposed inviscid
+ *                  oblique-shock solution, Sec. 3.3). */
+enum {
+  CDNS_BC_PERIODIC = 0,
+  CDNS_BC_WALL_ISOTHERMAL = 1,
+  CDNS_BC_WALL_ADIABATIC = 2,
+  CDNS_BC_DIRICHLET = 3,
+  CDNS_BC_OUTFLOW_CHAR = 4,
+  CDNS_BC_SHOCK_TOP = 5
+};
+
+typedef struct {
+  int32_t nx, ny, nz;         /* interior nodes, each >= 4 */
+  double lx, lz;              /* periodic lengths / extents of the uniform axes */
+  const double* y_eta;        /* host array [ny]: dy/deta at the nodes (copied) */
+  const double* y_etaeta;     /* host array [ny]: d2y/deta2 at the nodes (copied) */
+} cdns_grid;
+
+typedef struct {
+  double gamma;               /* ratio of specific heats */
+  double Pr;                  /* Prandtl number */
+  double R_gas;               /* gas constant */
+  double mu_ref, T_ref, S_suth; /* Sutherland: mu = mu_ref t^1.5 (1+S)/(t+S), t = T/T_ref */
+  int32_t viscous;            /* 0: Euler equations, 1: Navier-Stokes */
+  int32_t sensor_mode;        /* CDNS_SENSOR_* */
+  double theta_star;          /* node flag when theta > theta_star */
+  double sensor_eps;          /* regulariser of the sensor denominator, (u0/L0)^2 */
+  int32_t forcing;            /* constant streamwise mass flow (bulk force f) */
+} cdns_phys;
+
+/* Diagnostics (volume integrals use dV = dx dz d_eta y_eta). */
+typedef struct {
+  double dt;                  /* last time step used */
+  double time;                /* accumulated time */
+  double mass, mom[3], energy, kinetic;
+  double rho_min, p_min, mach_max;
+  double forcing_f;           /* bulk force of the last stage evaluated */
+  double weno_frac[3];        /* shock-capturing share of interfaces, last stage */
+  int64_t step;               /* completed RK steps */
+  int64_t nonfinite;          /* non-finite conserved values */
+  int32_t status;             /* device status bits (0 = healthy) */
+} cdns_diag;
+
+typedef struct cdns_ctx cdns_ctx;
+typedef struct cdns_batch cdns_batch;
+
+/* Bytes of device workspace cdns_create needs for this grid and precision.
+ * Returns 0 for an invalid grid. */
+size_t cdns_workspace_bytes(const cdns_grid* grid, int32_t precision);
+
+/* Create a solver instance.  state_dev: caller-owned device array
+ * [5][nz][ny][nx] holding w^n; it is read and updated in place by the
+ * stepping calls.  workspace_dev: caller-owned device memory of at least
+ * cdns_workspace_bytes() bytes, 256-byte aligned, used for stage states,
+ * residual registers, ghost planes, flags, lists and reductions.
+ * hip_stream: a hipStream_t (NULL = default stream).  All faces start
+ * periodic.  On success *out receives the context. */
+cdns_status cdns_create(const cdns_grid* grid, const cdns_phys* phys, int32_t precision,
+                        double* state_dev, void* workspace_dev, size_t workspace_bytes,
+                        void* hip_stream, cdns_ctx** out);
+
+/* Set the boundary condition of one face (CDNS_BC_*, see above).  params
+ * is a host array of nparams doubles (copied).  Both faces of an axis must
+ * be periodic or both non-periodic; combinations not listed above return
+ * CDNS_EUNSUP.  Call before stepping. */
+cdns_status cdns_set_bc(cdns_ctx* ctx, int32_t face, int32_t kind, const double* params,
+                        int64_t nparams);
+
+/* Tile shape of the fused right-hand-side kernel: (tile_x, tile_y) must be
+ * one of the compiled variants (64x4, 32x8, 64x2, 128x2), kz >= 1 planes per
+ * block.  Results do not depend on the choice. */
+cdns_status cdns_set_tiling(cdns_ctx* ctx, int32_t tile_x, int32_t tile_y, int32_t kz);
+
+/* Full right-hand side R(w) of dw/dt = R(w) (Sec. 2.2) for the device
+ * array w_dev [5][nz][ny][nx], written to r_dev (same layout), including
+ * boundary conditions, sensor switching and bulk forcing. */
+cdns_status cdns_rhs(cdns_ctx* ctx, const double* w_dev, double* r_dev);
+
+/* One RK3 step of the state.  dt_fixed > 0 sets the step; otherwise
+ * dt = cfl * min(1/max sum_d (|u_d|+c)/dx_d, 2.5/max[max(4/3,gamma/Pr)
+ * (mu/rho)(16/3) sum_d dx_d^-2]) is computed on the device from w^n. */
+cdns_status cdns_rk_step(cdns_ctx* ctx, double cfl, double dt_fixed);
+
+/* n RK3 steps, replayed from one captured HIP graph per step. */
+cdns_status cdns_advance_n(cdns_ctx* ctx, int32_t n, double cfl, double dt_fixed);
+
+/* Volume integrals, extrema and status of the current state; synchronises
+ * the stream.  Returns CDNS_ESTATE if the device flagged a bad state. */
+cdns_status cdns_diagnostics(cdns_ctx* ctx, cdns_diag* out);
+
+/* Test hooks: node sensor value theta, node flags and interface flags
+ * (bit d: interface i+1/2 in direction d is shock-capturing) of the last
+ * right-hand side evaluated by cdns_rhs (device arrays [nz][ny][nx]).
+ * theta_dev may be NULL. */
+cdns_status cdns_export_sensor(cdns_ctx* ctx, double* theta_dev, uint8_t* nflags_dev,
+                               uint8_t* iflags_dev);
+
+/* Last error message of the context (valid until the next call on it). */
+const char* cdns_last_error(const cdns_ctx* ctx);
+
+/* Destroy the context (does not free caller memory). */
+cdns_status cdns_destroy(cdns_ctx* ctx);
+
+/* ---------------------------------------------------------------- batching
+ * Many independent instances advanced together: every stage phase is one
+ * kernel launch over a device work table of (instance, tile) items for all
+ * attached instances; the stage sequence is captured once as a HIP graph
+ * and replayed, membership changes only rewrite the table.  Each instance
+ * keeps its own time step, forcing and reductions (fixed order per
+ * instance), so its results do not depend on what else is attached. */
+cdns_status cdns_batch_create(int32_t max_slots, void* workspace_dev, size_t workspace_bytes,
+                              void* hip_stream, cdns_batch** out);
+size_t cdns_batch_workspace_bytes(int32_t max_slots);
+cdns_status cdns_batch_attach(cdns_batch* b, cdns_ctx* ctx, int32_t* slot);
+cdns_status cdns_batch_detach(cdns_batch* b, int32_t slot);
+/* nsteps RK3 steps of every attached instance; each uses its own cfl /
+ * dt_fixed as given to cdns_batch_set_step. */
+cdns_status cdns_batch_set_step(cdns_batch* b, int32_t slot, double cfl, double dt_fixed);
+cdns_status cdns_batch_step(cdns_batch* b, int32_t nsteps);
+cdns_status cdns_batch_destroy(cdns_batch* b);
+
+/* Library version string. */
+const char* cdns_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CDNS_H */

@@ -1,0 +1,512 @@
+// cdns_api.hip -- host side of the C ABI declared in include/cdns.h:
+// argument validation, workspace carving, stage sequencing, HIP graph
+// capture of whole RK steps, diagnostics and the batched runner.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cdns.h"
+#include "cdns_internal.h"
+
+using cdns::Desc;
+
+struct cdns_ctx {
+  Desc D;
+  hipStream_t stream = nullptr;     // caller's stream (work is enqueued here)
+  hipStream_t cap = nullptr;        // private stream used only for graph capture
+  std::string err;
+  int precision = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::vector<double> h_yeta, h_yetaeta, h_iy, h_iye2;
+  std::vector<double> h_bcp[6];
+  double* bcp_dev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  size_t bcp_cap = 0;
+  size_t part_cap = 0;
+  hipGraphExec_t gexec = nullptr;
+  double g_cfl = -1.0, g_dt = -1.0;
+  bool last_rhs_valid = false;
+  int batch_refs = 0;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t metric, bcp, w1, w2, ra, rb, nflag, iflag, theta, fw, list, count, gx, gy, part, red,
+      redd, scal, status, diag, total;
+  size_t bcp_cap, part_cap;
+};
+
+bool grid_ok(const cdns_grid* g) {
+  return g && g->nx >= 4 && g->ny >= 4 && g->nz >= 4 && g->lx > 0 && g->lz > 0 && g->y_eta &&
+         g->y_etaeta && (long long)g->nx * g->ny * g->nz < (1LL << 31);
+}
+
+Layout layout_of(const cdns_grid* g) {
+  Layout L{};
+  const size_t nx = g->nx, ny = g->ny, nz = g->nz;
+  const size_t N = nx * ny * nz;
+  const size_t nxg = nx + 2 * cdns::kHalo;
+  L.bcp_cap = std::max<size_t>(16, 5 * std::max(nx, ny));
+  // largest number of fused-kernel blocks over the compiled tile shapes (kz >= 1)
+  L.part_cap = ((nx + 31) / 32) * ((ny + 1) / 2) * nz;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.metric = take(4 * ny * sizeof(double));
+  L.bcp = take(6 * L.bcp_cap * sizeof(double));
+  L.w1 = take(5 * N * sizeof(double));
+  L.w2 = take(5 * N * sizeof(double));
+  L.ra = take(5 * N * sizeof(double));
+  L.rb = take(5 * N * sizeof(double));
+  L.nflag = take(N);
+  L.iflag = take(N);
+  L.theta = take(N * sizeof(double));
+  L.fw = take(3 * 5 * N * sizeof(double));
+  L.list = take(3 * N * sizeof(int));
+  L.count = take(4 * sizeof(unsigned));
+  L.gx = take(2 * 5 * cdns::kHalo * nz * ny * sizeof(double));
+  L.gy = take(2 * 5 * cdns::kHalo * nz * nxg * sizeof(double));
+  L.part = take(L.part_cap * sizeof(double));
+  L.red = take(2 * cdns::kRedBlocks * sizeof(double));
+  L.redd = take((size_t)cdns::DG_COUNT * cdns::kRedBlocks * sizeof(double));
+  L.scal = take(cdns::SC_COUNT * sizeof(double));
+  L.status = take(sizeof(unsigned) * 4);
+  L.diag = take(cdns::DG_COUNT * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+cdns_status fail(cdns_ctx* c, cdns_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+cdns_status hip_fail(cdns_ctx* c, hipError_t e, const char* what) {
+  return fail(c, CDNS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void invalidate_graph(cdns_ctx* c) {
+  if (c->gexec) {
+    hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+}
+
+void set_tiling_desc(Desc& D, int tx, int ty, int kz) {
+  D.tile_x = tx;
+  D.tile_y = ty;
+  D.kz = kz < 1 ? 1 : (kz > D.nz ? D.nz : kz);
+  D.tiles_x = (D.nx + tx - 1) / tx;
+  D.tiles_y = (D.ny + ty - 1) / ty;
+  D.zchunks = (D.nz + D.kz - 1) / D.kz;
+  D.npart = D.tiles_x * D.tiles_y * D.zchunks;
+}
+
+// Default tiling: enough blocks to fill 256 CUs at least twice.
+void default_tiling(Desc& D) {
+  int tx = 64, ty = 4;
+  int kz = 16;
+  long long tiles = (long long)((D.nx + tx - 1) / tx) * ((D.ny + ty - 1) / ty);
+  while (kz > 4 && tiles * ((D.nz + kz - 1) / kz) < 1024) kz /= 2;
+  set_tiling_desc(D, tx, ty, kz);
+}
+
+// Enqueue the right-hand-side phases of one stage (ghosts .. forcing sum).
+hipError_t enqueue_rhs_phases(const Desc& D, int stage, bool export_theta, hipStream_t st) {
+  hipError_t e;
+  if (D.sensor_mode > 0 && (e = cdns::launch_stage_begin(D, st)) != hipSuccess) return e;
+  if ((e = cdns::launch_ghosts(D, stage, st)) != hipSuccess) return e;
+  if (D.sensor_mode == 1 && (e = cdns::launch_sensor(D, stage, export_theta, st)) != hipSuccess)
+    return e;
+  if (D.sensor_mode > 0) {
+    if ((e = cdns::launch_iflags(D, st)) != hipSuccess) return e;
+    if ((e = cdns::launch_weno(D, stage, st)) != hipSuccess) return e;
+  }
+  if ((e = cdns::launch_rhs(D, stage, st)) != hipSuccess) return e;
+  if (D.forcing && (e = cdns::launch_force(D, st)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+hipError_t enqueue_step(const Desc& D, hipStream_t st) {
+  hipError_t e;
+  if ((e = cdns::launch_dt(D, st)) != hipSuccess) return e;
+  for (int stage = 0; stage < 3; ++stage) {
+    if ((e = enqueue_rhs_phases(D, stage, false, st)) != hipSuccess) return e;
+    if ((e = cdns::launch_rk(D, stage, st)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cdns_version(void) { return "cdns 0.1 (gfx950)"; }
+
+size_t cdns_workspace_bytes(const cdns_grid* grid, int32_t precision) {
+  if (!grid_ok(grid) || (precision != CDNS_FP64 && precision != CDNS_FP32_FLUX)) return 0;
+  return layout_of(grid).total;
+}
+
+cdns_status cdns_create(const cdns_grid* grid, const cdns_phys* phys, int32_t precision,
+                        double* state_dev, void* workspace_dev, size_t workspace_bytes,
+                        void* hip_stream, cdns_ctx** out) {
+  if (!out) return CDNS_EINVAL;
+  *out = nullptr;
+  if (!grid_ok(grid) || !phys || !state_dev || !workspace_dev) return CDNS_EINVAL;
+  if (precision != CDNS_FP64 && precision != CDNS_FP32_FLUX) return CDNS_EINVAL;
+  if (!(phys->gamma > 1.0) || !(phys->R_gas > 0.0) || !(phys->Pr > 0.0) || !(phys->T_ref > 0.0) ||
+      !(phys->mu_ref >= 0.0) || !(phys->S_suth >= 0.0) || phys->sensor_mode < 0 ||
+      phys->sensor_mode > 2 || !(phys->sensor_eps >= 0.0))
+    return CDNS_EINVAL;
+  if (((uintptr_t)workspace_dev) % kAlign != 0) return CDNS_EINVAL;
+  Layout L = layout_of(grid);
+  if (workspace_bytes < L.total) return CDNS_ENOMEM;
+  for (int j = 0; j < grid->ny; ++j)
+    if (!(grid->y_eta[j] > 0.0)) return CDNS_EINVAL;
+
+  cdns_ctx* c = new cdns_ctx();
+  c->stream = (hipStream_t)hip_stream;
+  c->precision = precision;
+  c->ws = (char*)workspace_dev;
+  c->ws_bytes = workspace_bytes;
+  c->bcp_cap = L.bcp_cap;
+  c->part_cap = L.part_cap;
+  Desc& D = c->D;
+  std::memset(&D, 0, sizeof(D));
+  const int nx = grid->nx, ny = grid->ny, nz = grid->nz;
+  D.nx = nx; D.ny = ny; D.nz = nz;
+  D.nxg = nx + 2 * cdns::kHalo;
+  D.N = (long long)nx * ny * nz;
+  D.dx = grid->lx / nx;
+  D.dz = grid->lz / nz;
+  D.deta = 1.0 / ny;
+  D.idx = 1.0 / D.dx;
+  D.idz = 1.0 / D.dz;
+  D.ideta = 1.0 / D.deta;
+  D.idx2 = D.idx * D.idx;
+  D.idz2 = D.idz * D.idz;
+  D.ideta2 = D.ideta * D.ideta;
+  c->h_yeta.assign(grid->y_eta, grid->y_eta + ny);
+  c->h_yetaeta.assign(grid->y_etaeta, grid->y_etaeta + ny);
+  c->h_iy.resize(ny);
+  c->h_iye2.resize(ny);
+  double ysum = 0.0;
+  for (int j = 0; j < ny; ++j) {
+    c->h_iy[j] = 1.0 / (D.deta * c->h_yeta[j]);
+    c->h_iye2[j] = 1.0 / (c->h_yeta[j] * c->h_yeta[j]);
+    ysum += c->h_yeta[j];
+  }
+  D.vol_den = ysum * (double)nx * (double)nz;
+  D.gamma = phys->gamma;
+  D.gm1 = phys->gamma - 1.0;
+  D.R = phys->R_gas;
+  D.cv = phys->R_gas / (phys->gamma - 1.0);
+  D.icv = 1.0 / D.cv;
+  D.cp = phys->gamma * phys->R_gas / (phys->gamma - 1.0);
+  D.Pr = phys->Pr;
+  D.mu_ref = phys->mu_ref;
+  D.iTref = 1.0 / phys->T_ref;
+  D.S = phys->S_suth;
+  D.muc = phys->mu_ref * (1.0 + phys->S_suth);
+  D.kfac = D.cp / phys->Pr;
+  D.vfac = std::max(4.0 / 3.0, phys->gamma / phys->Pr);
+  D.theta_star = phys->theta_star;
+  D.eps_s = phys->sensor_eps;
+  D.viscous = phys->viscous ? 1 : 0;
+  D.sensor_mode = phys->sensor_mode;
+  D.forcing = phys->forcing ? 1 : 0;
+  D.precision = precision;
+  D.per_x = 1;
+  D.per_y = 1;
+  for (int f = 0; f < 6; ++f) D.bc[f] = cdns::BC_PERIODIC;
+
+  char* ws = c->ws;
+  double* metric = (double*)(ws + L.metric);
+  D.y_eta = metric;
+  D.y_etaeta = metric + ny;
+  D.iy = metric + 2 * ny;
+  D.iye2 = metric + 3 * ny;
+  for (int f = 0; f < 6; ++f) {
+    c->bcp_dev[f] = (double*)(ws + L.bcp) + (size_t)f * L.bcp_cap;
+    D.bcp[f] = c->bcp_dev[f];
+  }
+  double* w1 = (double*)(ws + L.w1);
+  double* w2 = (double*)(ws + L.w2);
+  double* ra = (double*)(ws + L.ra);
+  double* rb = (double*)(ws + L.rb);
+  D.win[0] = state_dev; D.wout[0] = w1; D.rcur[0] = ra; D.rprev[0] = nullptr;
+  D.win[1] = w1; D.wout[1] = w2; D.rcur[1] = rb; D.rprev[1] = ra;
+  D.win[2] = w2; D.wout[2] = state_dev; D.rcur[2] = ra; D.rprev[2] = rb;
+  D.win[3] = state_dev; D.wout[3] = nullptr; D.rcur[3] = ra; D.rprev[3] = nullptr;
+  D.nflag = (uint8_t*)(ws + L.nflag);
+  D.iflag = (uint8_t*)(ws + L.iflag);
+  D.theta = (double*)(ws + L.theta);
+  for (int d = 0; d < 3; ++d) {
+    D.Fw[d] = (double*)(ws + L.fw) + (size_t)d * 5 * D.N;
+    D.list[d] = (int*)(ws + L.list) + (size_t)d * D.N;
+  }
+  D.count = (unsigned*)(ws + L.count);
+  const size_t gxs = (size_t)5 * cdns::kHalo * nz * ny;
+  const size_t gys = (size_t)5 * cdns::kHalo * nz * D.nxg;
+  D.gx[0] = (double*)(ws + L.gx);
+  D.gx[1] = D.gx[0] + gxs;
+  D.gy[0] = (double*)(ws + L.gy);
+  D.gy[1] = D.gy[0] + gys;
+  D.part = (double*)(ws + L.part);
+  D.red = (double*)(ws + L.red);
+  D.redd = (double*)(ws + L.redd);
+  D.scal = (double*)(ws + L.scal);
+  D.status = (unsigned*)(ws + L.status);
+  D.diag = (double*)(ws + L.diag);
+  default_tiling(D);
+  D.cfl = 0.8;
+  D.dt_fixed = 0.0;
+
+  hipError_t e;
+  if ((e = hipMemcpyAsync(metric, c->h_yeta.data(), ny * sizeof(double), hipMemcpyHostToDevice,
+                          c->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(metric + ny, c->h_yetaeta.data(), ny * sizeof(double),
+                          hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(metric + 2 * ny, c->h_iy.data(), ny * sizeof(double),
+                          hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(metric + 3 * ny, c->h_iye2.data(), ny * sizeof(double),
+                          hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
+      (e = hipMemsetAsync(ws + L.count, 0, align_up(4 * sizeof(unsigned)), c->stream)) != hipSuccess ||
+      (e = hipMemsetAsync(ws + L.scal, 0, cdns::SC_COUNT * sizeof(double), c->stream)) != hipSuccess ||
+      (e = hipMemsetAsync(ws + L.status, 0, 4 * sizeof(unsigned), c->stream)) != hipSuccess ||
+      (e = hipMemsetAsync(ws + L.iflag, 0, D.N, c->stream)) != hipSuccess ||
+      (e = hipMemsetAsync(ws + L.nflag, 0, D.N, c->stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
+    delete c;
+    return CDNS_EHIP;
+  }
+  if ((e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking)) != hipSuccess) {
+    delete c;
+    return CDNS_EHIP;
+  }
+  *out = c;
+  return CDNS_OK;
+}
+
+cdns_status cdns_set_bc(cdns_ctx* c, int32_t face, int32_t kind, const double* params,
+                        int64_t nparams) {
+  if (!c) return CDNS_EINVAL;
+  if (face < 0 || face > 5) return fail(c, CDNS_EINVAL, "face out of range");
+  if (kind < 0 || kind > 5) return fail(c, CDNS_EINVAL, "unknown boundary kind");
+  if (nparams < 0 || (nparams > 0 && !params)) return fail(c, CDNS_EINVAL, "bad parameters");
+  const int ax = face / 2;
+  Desc& D = c->D;
+  if (kind != cdns::BC_PERIODIC) {
+    if (ax == 2) return fail(c, CDNS_EUNSUP, "z faces must be periodic");
+    if (ax == 0 && !(kind == cdns::BC_DIRICHLET || kind == cdns::BC_OUTFLOW))
+      return fail(c, CDNS_EUNSUP, "x faces accept periodic, Dirichlet or characteristic outflow");
+    if (ax == 1 && !(kind == cdns::BC_WALL_ISO || kind == cdns::BC_WALL_ADIA ||
+                     kind == cdns::BC_SHOCK_TOP))
+      return fail(c, CDNS_EUNSUP, "y faces accept periodic, walls or an imposed shock state");
+    if (kind == cdns::BC_DIRICHLET && nparams != 5LL * D.ny)
+      return fail(c, CDNS_EINVAL, "Dirichlet profile needs 5*ny values");
+    if (kind == cdns::BC_WALL_ISO && (nparams != 1 || !(params[0] > 0.0)))
+      return fail(c, CDNS_EINVAL, "isothermal wall needs one positive temperature");
+    if (kind == cdns::BC_SHOCK_TOP && nparams != 11)
+      return fail(c, CDNS_EINVAL, "shock state needs 11 values");
+  }
+  if ((size_t)nparams > c->bcp_cap) return fail(c, CDNS_EINVAL, "too many parameters");
+  c->h_bcp[face].assign(params, params + nparams);
+  if (nparams > 0) {
+    hipError_t e = hipMemcpyAsync(c->bcp_dev[face], c->h_bcp[face].data(),
+                                  nparams * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "sync");
+  }
+  D.bc[face] = kind;
+  D.per_x = D.bc[0] == cdns::BC_PERIODIC && D.bc[1] == cdns::BC_PERIODIC;
+  D.per_y = D.bc[2] == cdns::BC_PERIODIC && D.bc[3] == cdns::BC_PERIODIC;
+  D.wall_lo = D.bc[2] == cdns::BC_WALL_ISO || D.bc[2] == cdns::BC_WALL_ADIA;
+  D.wall_hi = D.bc[3] == cdns::BC_WALL_ISO || D.bc[3] == cdns::BC_WALL_ADIA;
+  invalidate_graph(c);
+  return CDNS_OK;
+}
+
+static cdns_status check_bcs(cdns_ctx* c) {
+  const Desc& D = c->D;
+  for (int a = 0; a < 3; ++a) {
+    const bool p0 = D.bc[2 * a] == cdns::BC_PERIODIC, p1 = D.bc[2 * a + 1] == cdns::BC_PERIODIC;
+    if (p0 != p1) return fail(c, CDNS_EINVAL, "both faces of an axis must be periodic or neither");
+  }
+  return CDNS_OK;
+}
+
+cdns_status cdns_set_tiling(cdns_ctx* c, int32_t tx, int32_t ty, int32_t kz) {
+  if (!c) return CDNS_EINVAL;
+  if (!cdns::rhs_tile_supported(tx, ty) || kz < 1)
+    return fail(c, CDNS_EINVAL, "unsupported tile shape");
+  Desc t = c->D;
+  set_tiling_desc(t, tx, ty, kz);
+  if ((size_t)t.npart > c->part_cap) return fail(c, CDNS_EINVAL, "too many tiles");
+  c->D = t;
+  invalidate_graph(c);
+  return CDNS_OK;
+}
+
+cdns_status cdns_rhs(cdns_ctx* c, const double* w_dev, double* r_dev) {
+  if (!c || !w_dev || !r_dev) return c ? fail(c, CDNS_EINVAL, "null array") : CDNS_EINVAL;
+  cdns_status s = check_bcs(c);
+  if (s) return s;
+  Desc D = c->D;
+  D.win[3] = w_dev;
+  D.rcur[3] = r_dev;
+  hipError_t e = enqueue_rhs_phases(D, 3, true, c->stream);
+  if (e == hipSuccess && D.forcing) e = cdns::launch_apply_force(D, 3, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "rhs launch");
+  c->last_rhs_valid = true;
+  return CDNS_OK;
+}
+
+cdns_status cdns_rk_step(cdns_ctx* c, double cfl, double dt_fixed) {
+  if (!c) return CDNS_EINVAL;
+  if (!(dt_fixed > 0.0) && !(cfl > 0.0)) return fail(c, CDNS_EINVAL, "need cfl > 0 or dt > 0");
+  cdns_status s = check_bcs(c);
+  if (s) return s;
+  Desc D = c->D;
+  D.cfl = cfl;
+  D.dt_fixed = dt_fixed > 0.0 ? dt_fixed : 0.0;
+  hipError_t e = enqueue_step(D, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "step launch");
+  return CDNS_OK;
+}
+
+cdns_status cdns_advance_n(cdns_ctx* c, int32_t n, double cfl, double dt_fixed) {
+  if (!c) return CDNS_EINVAL;
+  if (n < 0) return fail(c, CDNS_EINVAL, "negative step count");
+  if (!(dt_fixed > 0.0) && !(cfl > 0.0)) return fail(c, CDNS_EINVAL, "need cfl > 0 or dt > 0");
+  cdns_status s = check_bcs(c);
+  if (s) return s;
+  if (n == 0) return CDNS_OK;
+  const double dtf = dt_fixed > 0.0 ? dt_fixed : 0.0;
+  hipError_t e;
+  if (!c->gexec || c->g_cfl != cfl || c->g_dt != dtf) {
+    invalidate_graph(c);
+    Desc D = c->D;
+    D.cfl = cfl;
+    D.dt_fixed = dtf;
+    hipGraph_t g = nullptr;
+    if ((e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return hip_fail(c, e, "begin capture");
+    hipError_t le = enqueue_step(D, c->cap);
+    e = hipStreamEndCapture(c->cap, &g);
+    if (le != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      return hip_fail(c, le, "capture launch");
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "end capture");
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      c->gexec = nullptr;
+      return hip_fail(c, e, "graph instantiate");
+    }
+    c->g_cfl = cfl;
+    c->g_dt = dtf;
+  }
+  for (int s2 = 0; s2 < n; ++s2) {
+    if ((e = hipGraphLaunch(c->gexec, c->stream)) != hipSuccess)
+      return hip_fail(c, e, "graph launch");
+  }
+  return CDNS_OK;
+}
+
+cdns_status cdns_diagnostics(cdns_ctx* c, cdns_diag* out) {
+  if (!c || !out) return c ? fail(c, CDNS_EINVAL, "null output") : CDNS_EINVAL;
+  Desc D = c->D;
+  hipError_t e = cdns::launch_diag(D, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "diag launch");
+  double dg[cdns::DG_COUNT], sc[cdns::SC_COUNT];
+  unsigned st[4], cnt[4];
+  if ((e = hipMemcpyAsync(dg, D.diag, sizeof(dg), hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(sc, D.scal, sizeof(sc), hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(st, D.status, sizeof(st), hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(cnt, D.count, sizeof(cnt), hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+    return hip_fail(c, e, "diag copy");
+  std::memset(out, 0, sizeof(*out));
+  out->dt = sc[cdns::SC_DT];
+  out->time = sc[cdns::SC_TIME];
+  out->step = (int64_t)llround(sc[cdns::SC_STEP]);
+  out->forcing_f = sc[cdns::SC_FORCE];
+  out->mass = dg[cdns::DG_MASS];
+  out->mom[0] = dg[cdns::DG_MX];
+  out->mom[1] = dg[cdns::DG_MY];
+  out->mom[2] = dg[cdns::DG_MZ];
+  out->energy = dg[cdns::DG_E];
+  out->kinetic = dg[cdns::DG_K];
+  out->rho_min = dg[cdns::DG_RHOMIN];
+  out->p_min = dg[cdns::DG_PMIN];
+  out->mach_max = dg[cdns::DG_MACHMAX];
+  out->nonfinite = (int64_t)llround(dg[cdns::DG_NONFINITE]);
+  const double nif[3] = {(double)(D.per_x ? D.nx : D.nx - 1) * D.ny * D.nz,
+                         (double)D.nx * (D.per_y ? D.ny : D.ny - 1) * D.nz, (double)D.N};
+  for (int d = 0; d < 3; ++d) out->weno_frac[d] = D.sensor_mode > 0 ? cnt[d] / nif[d] : 0.0;
+  out->status = (int32_t)st[0];
+  if (st[0] != 0 || out->nonfinite != 0) return fail(c, CDNS_ESTATE, "device flagged a bad state");
+  return CDNS_OK;
+}
+
+cdns_status cdns_export_sensor(cdns_ctx* c, double* theta_dev, uint8_t* nflags_dev,
+                               uint8_t* iflags_dev) {
+  if (!c) return CDNS_EINVAL;
+  if (!c->last_rhs_valid) return fail(c, CDNS_EINVAL, "no right-hand side evaluated yet");
+  const Desc& D = c->D;
+  hipError_t e = hipSuccess;
+  if (theta_dev && D.sensor_mode == 1)
+    e = hipMemcpyAsync(theta_dev, D.theta, D.N * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+  else if (theta_dev)
+    e = hipMemsetAsync(theta_dev, 0, D.N * sizeof(double), c->stream);
+  if (e == hipSuccess && nflags_dev) {
+    if (D.sensor_mode == 1)
+      e = hipMemcpyAsync(nflags_dev, D.nflag, D.N, hipMemcpyDeviceToDevice, c->stream);
+    else
+      e = hipMemsetAsync(nflags_dev, 0, D.N, c->stream);
+  }
+  if (e == hipSuccess && iflags_dev) {
+    if (D.sensor_mode > 0)
+      e = hipMemcpyAsync(iflags_dev, D.iflag, D.N, hipMemcpyDeviceToDevice, c->stream);
+    else
+      e = hipMemsetAsync(iflags_dev, 0, D.N, c->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "export");
+  return CDNS_OK;
+}
+
+const char* cdns_last_error(const cdns_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+cdns_status cdns_destroy(cdns_ctx* c) {
+  if (!c) return CDNS_EINVAL;
+  if (c->batch_refs > 0) return fail(c, CDNS_EBUSY, "context attached to a batch");
+  invalidate_graph(c);
+  if (c->cap) hipStreamDestroy(c->cap);
+  delete c;
+  return CDNS_OK;
+}
+
+}  // extern "C"
+
+// Accessors used by the batched runner (cdns_batch.hip).
+namespace cdns {
+const Desc& ctx_desc(const cdns_ctx* c) { return c->D; }
+int& ctx_batch_refs(cdns_ctx* c) { return c->batch_refs; }
+hipStream_t ctx_stream(const cdns_ctx* c) { return c->stream; }
+}  // namespace cdns

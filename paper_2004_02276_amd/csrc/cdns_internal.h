@@ -1,0 +1,100 @@
+// cdns_internal.h -- device descriptor of one solver instance and the host
+// launchers of the HIP kernels (library-internal, not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace cdns {
+
+constexpr int kHalo = 3;          // ghost depth (WENO5 stencil i-2..i+3)
+constexpr int kRedBlocks = 1024;  // partial-sum slots of the generic reductions
+
+// Boundary kinds (same values as the C ABI).
+enum { BC_PERIODIC = 0, BC_WALL_ISO = 1, BC_WALL_ADIA = 2, BC_DIRICHLET = 3,
+       BC_OUTFLOW = 4, BC_SHOCK_TOP = 5 };
+
+// Device status bits.
+enum { ST_BAD_STATE = 1u, ST_BAD_GHOST = 2u };
+
+// Scalar slots in Desc::scal.
+enum { SC_DT = 0, SC_FORCE = 1, SC_TIME = 2, SC_STEP = 3, SC_COUNT = 8 };
+
+// Diagnostics slots in Desc::diag.
+enum { DG_MASS = 0, DG_MX, DG_MY, DG_MZ, DG_E, DG_K, DG_RHOMIN, DG_PMIN, DG_MACHMAX,
+       DG_NONFINITE, DG_COUNT = 16 };
+
+// Everything a kernel needs about one instance.  Passed by value as a kernel
+// argument for single-instance launches and stored in a device array for
+// batched launches.
+struct Desc {
+  int nx, ny, nz, nxg;            // nxg = nx + 2*kHalo (row length of y ghost planes)
+  long long N;                    // nx*ny*nz
+  double dx, dz, deta;
+  double idx, idz, ideta, idx2, idz2, ideta2;
+  const double* y_eta;            // [ny]
+  const double* y_etaeta;         // [ny]
+  const double* iy;               // [ny] 1/(deta*y_eta)
+  const double* iye2;             // [ny] 1/y_eta^2
+  double gamma, gm1, R, cv, icv, cp, Pr, mu_ref, iTref, S, muc, kfac;
+  double theta_star, eps_s, vol_den;
+  double vfac;                    // max(4/3, gamma/Pr) for the viscous time-step bound
+  int viscous, sensor_mode, forcing, precision;
+  int per_x, per_y;
+  int bc[6];
+  const double* bcp[6];
+  int wall_lo, wall_hi;
+  // stage buffers: index 0..2 = RK stages, 3 = standalone right-hand side
+  const double* win[4];
+  double* wout[4];
+  double* rcur[4];
+  const double* rprev[4];
+  // work arrays
+  uint8_t* nflag;                 // [N]
+  uint8_t* iflag;                 // [N] bit d: interface i+1/2 along d is shock-capturing
+  double* theta;                  // [N] optional sensor export (may be null)
+  double* Fw[3];                  // [5][N] shock-capturing interface fluxes per direction
+  int* list[3];                   // [N] compacted interface lists per direction
+  unsigned* count;                // [4] list lengths
+  double* gx[2];                  // [5][3][nz][ny] x-face ghost planes
+  double* gy[2];                  // [5][3][nz][nxg] y-face ghost planes
+  double* part;                   // [npart] right-hand-side block partial sums (forcing)
+  int npart;
+  double* red;                    // [2*kRedBlocks] generic reduction partials
+  double* redd;                   // [DG_COUNT*kRedBlocks] diagnostics partials
+  double* scal;                   // [SC_COUNT]
+  unsigned* status;               // [1]
+  double* diag;                   // [DG_COUNT]
+  // launch geometry of the fused right-hand-side kernel
+  int tile_x, tile_y, kz, tiles_x, tiles_y, zchunks;
+  // stepping
+  double cfl, dt_fixed;
+};
+
+// Host launchers (cdns_kernels.hip).  All enqueue on `st`.
+hipError_t launch_stage_begin(const Desc& D, hipStream_t st);
+hipError_t launch_ghosts(const Desc& D, int stage, hipStream_t st);
+hipError_t launch_sensor(const Desc& D, int stage, bool export_theta, hipStream_t st);
+hipError_t launch_iflags(const Desc& D, hipStream_t st);
+hipError_t launch_weno(const Desc& D, int stage, hipStream_t st);
+hipError_t launch_rhs(const Desc& D, int stage, hipStream_t st);
+hipError_t launch_force(const Desc& D, hipStream_t st);
+hipError_t launch_apply_force(const Desc& D, int stage, hipStream_t st);
+hipError_t launch_rk(const Desc& D, int stage, hipStream_t st);
+hipError_t launch_dt(const Desc& D, hipStream_t st);
+hipError_t launch_diag(const Desc& D, hipStream_t st);
+bool rhs_tile_supported(int tx, int ty);
+int rhs_blocks(const Desc& D);
+
+// Batched launchers: one launch per phase over every instance in the device
+// array `descs` (n instances); `work` lists (instance, tile) items of the
+// fused right-hand-side kernel.
+struct WorkItem { int inst, tile; };
+hipError_t launch_batch_phase(int phase, const Desc* descs_dev, int ninst, int stage,
+                              const WorkItem* work, int nwork, int tile_x, int tile_y,
+                              int precision, int persistent_blocks, hipStream_t st);
+enum { PH_BEGIN = 0, PH_GHOST_X, PH_GHOST_Y, PH_SENSOR, PH_IFLAGS, PH_WENO, PH_RHS, PH_FORCE,
+       PH_RK, PH_DT_PART, PH_DT_FINAL, PH_COUNT };
+
+}  // namespace cdns

@@ -1,0 +1,1136 @@
+// cdns_kernels.hip -- HIP kernels (gfx950) for the right-hand side and the
+// low-storage RK3 step of the compressible Navier-Stokes equations following
+// Sec. 2 of "STREAmS" (arXiv 2004.02276).
+//
+// Per stage (all on one stream, no host synchronisation):
+//   ghosts   x-face then y-face ghost planes of non-periodic faces
+//   sensor   Ducros sensor in FP64 with the node flag theta > theta*
+//   iflags   interface flags (OR over the central stencil) and compaction
+//            into one list of interfaces per direction
+//   weno     Lax-Friedrichs characteristic WENO5 flux on the listed
+//            interfaces, stored densely per interface
+//   rhs      fused central convective + pressure flux in x, y, z and
+//            Laplacian-form viscous/heat terms, 2.5-D tiling: an (x,y) tile
+//            with a 2-node halo is staged in LDS plane by plane while each
+//            thread keeps its own z column in registers
+//   force    bulk force from the per-block partial sums (fixed order)
+//   rk       w' = w + dt (alpha R_prev + beta R), forcing applied here
+//
+// State layout: w[5][nz][ny][nx] (x fastest); every kernel reads and writes
+// x-contiguous rows, so a wavefront touches 512 contiguous bytes per field.
+#include <hip/hip_runtime.h>
+
+#include "cdns_internal.h"
+
+namespace cdns {
+
+// Fourth-order central coefficients (Sec. 2.1).
+#define CA1 (2.0 / 3.0)
+#define CA2 (-1.0 / 12.0)
+#define CB0 (-5.0 / 2.0)
+#define CB1 (4.0 / 3.0)
+#define CB2 (-1.0 / 12.0)
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+__device__ __forceinline__ size_t nidx(const Desc& D, int i, int j, int k) {
+  return ((size_t)k * D.ny + (size_t)j) * D.nx + (size_t)i;
+}
+
+// Conserved variables at any node index (interior, periodic image or ghost
+// plane).  Resolution order follows the ghost fill order: z (periodic), then
+// y ghost planes (which already hold the x-extended range), then x.
+__device__ __forceinline__ void load_node(const Desc& D, const double* __restrict__ w, int i,
+                                          int j, int k, double q[5]) {
+  k = wrapi(k, D.nz);
+  if (j < 0 || j >= D.ny) {
+    if (D.per_y) {
+      j = wrapi(j, D.ny);
+    } else {
+      const int side = j < 0 ? 0 : 1;
+      int s = j < 0 ? -j : j - D.ny + 1;
+      s = s > kHalo ? kHalo : s;
+      int ii = i < -kHalo ? -kHalo : (i > D.nx + kHalo - 1 ? D.nx + kHalo - 1 : i);
+      const double* g = D.gy[side];
+      const size_t mst = (size_t)kHalo * D.nz * D.nxg;
+      const size_t b = ((size_t)(s - 1) * D.nz + k) * D.nxg + (size_t)(ii + kHalo);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) q[m] = g[m * mst + b];
+      return;
+    }
+  }
+  if (i < 0 || i >= D.nx) {
+    if (D.per_x) {
+      i = wrapi(i, D.nx);
+    } else {
+      const int side = i < 0 ? 0 : 1;
+      int s = i < 0 ? -i : i - D.nx + 1;
+      s = s > kHalo ? kHalo : s;
+      const double* g = D.gx[side];
+      const size_t mst = (size_t)kHalo * D.nz * D.ny;
+      const size_t b = ((size_t)(s - 1) * D.nz + k) * D.ny + (size_t)j;
+#pragma unroll
+      for (int m = 0; m < 5; ++m) q[m] = g[m * mst + b];
+      return;
+    }
+  }
+  const size_t b = nidx(D, i, j, k);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) q[m] = w[(size_t)m * D.N + b];
+}
+
+// Primitive variables in the flux arithmetic F.
+template <typename F>
+struct PV {
+  F r, u, v, w, p, h, t, mu;
+};
+
+template <typename F>
+__device__ __forceinline__ void to_prim(const Desc& D, const double q[5], PV<F>& s) {
+  const F r = (F)q[0];
+  const F ir = F(1) / r;
+  s.r = r;
+  s.u = (F)q[1] * ir;
+  s.v = (F)q[2] * ir;
+  s.w = (F)q[3] * ir;
+  const F E = (F)q[4] * ir;
+  const F ke = F(0.5) * (s.u * s.u + s.v * s.v + s.w * s.w);
+  s.t = (E - ke) * (F)D.icv;
+  s.p = r * (F)D.R * s.t;
+  s.h = E + s.p * ir;
+  const F tt = s.t * (F)D.iTref;
+  s.mu = (F)D.muc * tt * sqrt(tt) / (tt + (F)D.S);
+}
+
+// Energy-preserving central flux (eq. encflux with L = 2) at the interface
+// between nodes b and c of the four consecutive nodes a, b, c, d along
+// direction DIR; pressure in the same conservative form.
+template <typename F, int DIR>
+__device__ __forceinline__ void central_flux(const PV<F>& a, const PV<F>& b, const PV<F>& c,
+                                             const PV<F>& d, F f[5]) {
+  const F na = DIR == 0 ? a.u : (DIR == 1 ? a.v : a.w);
+  const F nb = DIR == 0 ? b.u : (DIR == 1 ? b.v : b.w);
+  const F nc = DIR == 0 ? c.u : (DIR == 1 ? c.v : c.w);
+  const F nd = DIR == 0 ? d.u : (DIR == 1 ? d.v : d.w);
+  const F c1 = F(0.25 * CA1) * ((b.r + c.r) * (nb + nc));
+  const F c2 = F(0.25 * CA2) * ((b.r + d.r) * (nb + nd));
+  const F c3 = F(0.25 * CA2) * ((a.r + c.r) * (na + nc));
+  f[0] = F(2) * (c1 + c2 + c3);
+  f[1] = c1 * (b.u + c.u) + c2 * (b.u + d.u) + c3 * (a.u + c.u);
+  f[2] = c1 * (b.v + c.v) + c2 * (b.v + d.v) + c3 * (a.v + c.v);
+  f[3] = c1 * (b.w + c.w) + c2 * (b.w + d.w) + c3 * (a.w + c.w);
+  f[4] = c1 * (b.h + c.h) + c2 * (b.h + d.h) + c3 * (a.h + c.h);
+  f[1 + DIR] += F(CA1) * (b.p + c.p) + F(CA2) * ((b.p + d.p) + (a.p + c.p));
+}
+
+// Pressure-only flux at a staggered wall (convective fluxes vanish there).
+template <typename F, int DIR>
+__device__ __forceinline__ void wall_flux(const PV<F>& a, const PV<F>& b, const PV<F>& c,
+                                          const PV<F>& d, F f[5]) {
+  f[0] = f[1] = f[2] = f[3] = f[4] = F(0);
+  f[1 + DIR] = F(CA1) * (b.p + c.p) + F(CA2) * ((b.p + d.p) + (a.p + c.p));
+}
+
+// WENO5 (Jiang-Shu) at the right face of v0 from (v-2, v-1, v0, v1, v2).
+template <typename F>
+__device__ __forceinline__ F weno5(F vm2, F vm1, F v0, F vp1, F vp2) {
+  const F q0 = (F(2) * vm2 - F(7) * vm1 + F(11) * v0) * F(1.0 / 6.0);
+  const F q1 = (-vm1 + F(5) * v0 + F(2) * vp1) * F(1.0 / 6.0);
+  const F q2 = (F(2) * v0 + F(5) * vp1 - vp2) * F(1.0 / 6.0);
+  const F d0 = vm2 - F(2) * vm1 + v0, e0 = vm2 - F(4) * vm1 + F(3) * v0;
+  const F d1 = vm1 - F(2) * v0 + vp1, e1 = vm1 - vp1;
+  const F d2 = v0 - F(2) * vp1 + vp2, e2 = F(3) * v0 - F(4) * vp1 + vp2;
+  const F eps = F(1e-6);
+  const F s0 = eps + F(13.0 / 12.0) * d0 * d0 + F(0.25) * e0 * e0;
+  const F s1 = eps + F(13.0 / 12.0) * d1 * d1 + F(0.25) * e1 * e1;
+  const F s2 = eps + F(13.0 / 12.0) * d2 * d2 + F(0.25) * e2 * e2;
+  const F a0 = F(0.1) / (s0 * s0);
+  const F a1 = F(0.6) / (s1 * s1);
+  const F a2 = F(0.3) / (s2 * s2);
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+}
+
+// Lax-Friedrichs split characteristic WENO5 flux at interface i+1/2 along
+// DIR from the conserved states of nodes i-2..i+3 (Sec. 2.1).  Eigenvectors
+// at the Roe average of nodes i, i+1; splitting constant per field from the
+// largest |eigenvalue| over the six nodes.
+template <typename F, int DIR>
+__device__ void weno_flux(const Desc& D, const double qd[6][5], F out[5]) {
+  constexpr int PN = 1 + DIR, P1 = 1 + (DIR + 1) % 3, P2 = 1 + (DIR + 2) % 3;
+  const F gm1 = (F)D.gm1, gam = (F)D.gamma;
+  F wq[6][5], fq[6][5], hs[6], un_s[6], t1_s[6], t2_s[6];
+  F am0 = F(0), am1 = F(0), am4 = F(0);
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const F r = (F)qd[s][0];
+    const F ir = F(1) / r;
+    const F mn = (F)qd[s][PN], m1 = (F)qd[s][P1], m2 = (F)qd[s][P2], E = (F)qd[s][4];
+    const F un = mn * ir, t1 = m1 * ir, t2 = m2 * ir;
+    const F p = gm1 * (E - F(0.5) * r * (un * un + t1 * t1 + t2 * t2));
+    const F c = sqrt(gam * p * ir);
+    wq[s][0] = r; wq[s][1] = mn; wq[s][2] = m1; wq[s][3] = m2; wq[s][4] = E;
+    fq[s][0] = mn;
+    fq[s][1] = mn * un + p;
+    fq[s][2] = mn * t1;
+    fq[s][3] = mn * t2;
+    fq[s][4] = un * (E + p);
+    hs[s] = (E + p) * ir;
+    un_s[s] = un; t1_s[s] = t1; t2_s[s] = t2;
+    am0 = fmax(am0, fabs(un - c));
+    am1 = fmax(am1, fabs(un));
+    am4 = fmax(am4, fabs(un + c));
+  }
+  // Roe average of nodes i (s=2) and i+1 (s=3)
+  const F sl = sqrt(wq[2][0]), sr = sqrt(wq[3][0]);
+  const F iw = F(1) / (sl + sr);
+  const F ur = (sl * un_s[2] + sr * un_s[3]) * iw;
+  const F vr = (sl * t1_s[2] + sr * t1_s[3]) * iw;
+  const F wr = (sl * t2_s[2] + sr * t2_s[3]) * iw;
+  const F Hr = (sl * hs[2] + sr * hs[3]) * iw;
+  const F q2 = ur * ur + vr * vr + wr * wr;
+  const F cr = sqrt(gm1 * (Hr - F(0.5) * q2));
+  const F ic = F(1) / cr;
+  const F b1 = gm1 * ic * ic;
+  const F b2 = F(0.5) * q2 * b1;
+  // left eigenvectors (rows), permuted component order (rho, m_n, m_t1, m_t2, E)
+  const F L[5][5] = {
+      {F(0.5) * (b2 + ur * ic), F(-0.5) * (b1 * ur + ic), F(-0.5) * b1 * vr, F(-0.5) * b1 * wr, F(0.5) * b1},
+      {F(1) - b2, b1 * ur, b1 * vr, b1 * wr, -b1},
+      {-vr, F(0), F(1), F(0), F(0)},
+      {-wr, F(0), F(0), F(1), F(0)},
+      {F(0.5) * (b2 - ur * ic), F(-0.5) * (b1 * ur - ic), F(-0.5) * b1 * vr, F(-0.5) * b1 * wr, F(0.5) * b1}};
+  const F alpha[5] = {am0, am1, am1, am1, am4};
+  F gh[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    F gp[6], gmi[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      F v = F(0), g = F(0);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        v += L[k][c] * wq[s][c];
+        g += L[k][c] * fq[s][c];
+      }
+      gp[s] = F(0.5) * (g + alpha[k] * v);
+      gmi[s] = F(0.5) * (g - alpha[k] * v);
+    }
+    gh[k] = weno5<F>(gp[0], gp[1], gp[2], gp[3], gp[4]) +
+            weno5<F>(gmi[5], gmi[4], gmi[3], gmi[2], gmi[1]);
+  }
+  // right eigenvectors applied to the reconstructed characteristic flux
+  const F f0 = gh[0] + gh[1] + gh[4];
+  const F f1 = (ur - cr) * gh[0] + ur * gh[1] + (ur + cr) * gh[4];
+  const F f2 = vr * (gh[0] + gh[1] + gh[4]) + gh[2];
+  const F f3 = wr * (gh[0] + gh[1] + gh[4]) + gh[3];
+  const F f4 = (Hr - ur * cr) * gh[0] + F(0.5) * q2 * gh[1] + vr * gh[2] + wr * gh[3] +
+               (Hr + ur * cr) * gh[4];
+  out[0] = f0;
+  out[PN] = f1;
+  out[P1] = f2;
+  out[P2] = f3;
+  out[4] = f4;
+}
+
+// ------------------------------------------------------------------ stage begin
+__global__ void k_stage_begin(Desc D) {
+  if (threadIdx.x < 4) D.count[threadIdx.x] = 0u;
+}
+
+// ------------------------------------------------------------------ ghost planes
+__device__ __forceinline__ void from_prim(const Desc& D, double r, double u, double v, double w,
+                                          double p, double q[5]) {
+  q[0] = r;
+  q[1] = r * u;
+  q[2] = r * v;
+  q[3] = r * w;
+  q[4] = p / D.gm1 + 0.5 * r * (u * u + v * v + w * w);
+}
+
+__device__ void ghost_x_body(const Desc& D, const double* __restrict__ w, long long t) {
+  // t over 2 * ny * nz (side, k, j)
+  const long long per_side = (long long)D.ny * D.nz;
+  const int side = (int)(t / per_side);
+  const long long r = t - side * per_side;
+  const int k = (int)(r / D.ny), j = (int)(r - (long long)k * D.ny);
+  const int kind = D.bc[side];
+  double* g = D.gx[side];
+  const size_t mst = (size_t)kHalo * D.nz * D.ny;
+  double gq[kHalo][5];
+  if (kind == BC_DIRICHLET) {
+    const double* pr = D.bcp[side];
+    double q[5];
+    from_prim(D, pr[j], pr[D.ny + j], pr[2 * D.ny + j], pr[3 * D.ny + j], pr[4 * D.ny + j], q);
+    for (int s = 0; s < kHalo; ++s)
+      for (int m = 0; m < 5; ++m) gq[s][m] = q[m];
+  } else {  // characteristic outflow
+    const int ib = side == 0 ? 0 : D.nx - 1;
+    const int ii = side == 0 ? 1 : D.nx - 2;
+    double qb[5], qi[5];
+    const size_t nb = nidx(D, ib, j, k), ni = nidx(D, ii, j, k);
+    for (int m = 0; m < 5; ++m) {
+      qb[m] = w[(size_t)m * D.N + nb];
+      qi[m] = w[(size_t)m * D.N + ni];
+    }
+    const double r = qb[0], ir = 1.0 / r;
+    const double u = qb[1] * ir, v = qb[2] * ir, ww = qb[3] * ir;
+    const double p = D.gm1 * (qb[4] - 0.5 * r * (u * u + v * v + ww * ww));
+    const double c = sqrt(D.gamma * p * ir);
+    const double H = (qb[4] + p) * ir;
+    const double q2 = u * u + v * v + ww * ww;
+    const double ic = 1.0 / c, b1 = D.gm1 * ic * ic, b2 = 0.5 * q2 * b1;
+    double dq[5];
+    for (int m = 0; m < 5; ++m) dq[m] = qb[m] - qi[m];
+    // characteristic amplitudes (x direction, natural component order)
+    double a0 = 0.5 * (b2 + u * ic) * dq[0] - 0.5 * (b1 * u + ic) * dq[1] - 0.5 * b1 * v * dq[2] -
+                0.5 * b1 * ww * dq[3] + 0.5 * b1 * dq[4];
+    double a1 = (1.0 - b2) * dq[0] + b1 * u * dq[1] + b1 * v * dq[2] + b1 * ww * dq[3] - b1 * dq[4];
+    double a2 = -v * dq[0] + dq[2];
+    double a3 = -ww * dq[0] + dq[3];
+    double a4 = 0.5 * (b2 - u * ic) * dq[0] - 0.5 * (b1 * u - ic) * dq[1] - 0.5 * b1 * v * dq[2] -
+                0.5 * b1 * ww * dq[3] + 0.5 * b1 * dq[4];
+    const double lam0 = u - c, lam1 = u, lam4 = u + c;
+    const bool hi = side == 1;
+    if (!(hi ? lam0 > 0.0 : lam0 < 0.0)) a0 = 0.0;
+    if (!(hi ? lam1 > 0.0 : lam1 < 0.0)) { a1 = 0.0; a2 = 0.0; a3 = 0.0; }
+    if (!(hi ? lam4 > 0.0 : lam4 < 0.0)) a4 = 0.0;
+    double dr[5];
+    dr[0] = a0 + a1 + a4;
+    dr[1] = (u - c) * a0 + u * a1 + (u + c) * a4;
+    dr[2] = v * (a0 + a1 + a4) + a2;
+    dr[3] = ww * (a0 + a1 + a4) + a3;
+    dr[4] = (H - u * c) * a0 + 0.5 * q2 * a1 + v * a2 + ww * a3 + (H + u * c) * a4;
+    for (int s = 0; s < kHalo; ++s)
+      for (int m = 0; m < 5; ++m) gq[s][m] = qb[m] + (double)(s + 1) * dr[m];
+  }
+  for (int s = 0; s < kHalo; ++s)
+    for (int m = 0; m < 5; ++m)
+      g[m * mst + ((size_t)s * D.nz + k) * D.ny + j] = gq[s][m];
+}
+
+__device__ void ghost_y_body(const Desc& D, const double* __restrict__ w, long long t) {
+  // t over 2 * nz * nxg (side, k, ii)
+  const long long per_side = (long long)D.nz * D.nxg;
+  const int side = (int)(t / per_side);
+  const long long r = t - side * per_side;
+  const int k = (int)(r / D.nxg);
+  const int i = (int)(r - (long long)k * D.nxg) - kHalo;
+  const int kind = D.bc[2 + side];
+  double* g = D.gy[side];
+  const size_t mst = (size_t)kHalo * D.nz * D.nxg;
+  for (int s = 1; s <= kHalo; ++s) {
+    double q[5];
+    if (kind == BC_WALL_ISO || kind == BC_WALL_ADIA) {
+      const int mj = side == 0 ? s - 1 : D.ny - s;
+      double qm[5];
+      load_node(D, w, i, mj, k, qm);
+      const double rr = qm[0], ir = 1.0 / rr;
+      const double u = qm[1] * ir, v = qm[2] * ir, ww = qm[3] * ir;
+      const double T = (qm[4] * ir - 0.5 * (u * u + v * v + ww * ww)) * D.icv;
+      const double p = rr * D.R * T;
+      const double Tg = kind == BC_WALL_ISO ? 2.0 * D.bcp[2 + side][0] - T : T;
+      if (!(Tg > 0.0)) atomicOr(D.status, (unsigned)ST_BAD_GHOST);
+      from_prim(D, p / (D.R * Tg), -u, -v, -ww, p, q);
+    } else {  // imposed shock state
+      const double* pr = D.bcp[2 + side];
+      const int ish = (int)pr[0];
+      const double* st = i < ish ? pr + 1 : pr + 6;
+      from_prim(D, st[0], st[1], st[2], st[3], st[4], q);
+    }
+    for (int m = 0; m < 5; ++m)
+      g[m * mst + ((size_t)(s - 1) * D.nz + k) * D.nxg + (size_t)(i + kHalo)] = q[m];
+  }
+}
+
+__global__ void k_ghost_x(Desc D, int stage) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < 2LL * D.ny * D.nz) ghost_x_body(D, D.win[stage], t);
+}
+__global__ void k_ghost_y(Desc D, int stage) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < 2LL * D.nz * D.nxg) ghost_y_body(D, D.win[stage], t);
+}
+
+// ------------------------------------------------------------------ sensor
+// Ducros sensor (eq. sensor), FP64, operations in the order of the
+// definition and without contraction, so that the flag decision is
+// reproducible: theta = max(-div / sqrt(div^2 + |curl|^2 + eps), 0).
+__device__ __forceinline__ double vel_at(const Desc& D, const double* __restrict__ w, int i, int j,
+                                         int k, int comp) {
+  double q[5];
+  load_node(D, w, i, j, k, q);
+  return q[comp] / q[0];
+}
+
+__device__ void sensor_body(const Desc& D, const double* __restrict__ w, long long n,
+                            bool export_theta) {
+#pragma clang fp contract(off)
+  const int i = (int)(n % D.nx);
+  const long long r = n / D.nx;
+  const int j = (int)(r % D.ny), k = (int)(r / D.ny);
+  double g[3][3];  // g[c][d] = d u_c / d x_d
+  const double inv[3] = {D.idx, D.iy[j], D.idz};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int di = d == 0, dj = d == 1, dk = d == 2;
+      const double fp1 = vel_at(D, w, i + di, j + dj, k + dk, 1 + c);
+      const double fm1 = vel_at(D, w, i - di, j - dj, k - dk, 1 + c);
+      const double fp2 = vel_at(D, w, i + 2 * di, j + 2 * dj, k + 2 * dk, 1 + c);
+      const double fm2 = vel_at(D, w, i - 2 * di, j - 2 * dj, k - 2 * dk, 1 + c);
+      g[c][d] = inv[d] * (CA1 * (fp1 - fm1) + CA2 * (fp2 - fm2));
+    }
+  }
+  const double div = g[0][0] + g[1][1] + g[2][2];
+  const double ox = g[2][1] - g[1][2], oy = g[0][2] - g[2][0], oz = g[1][0] - g[0][1];
+  const double den = sqrt(div * div + (ox * ox + oy * oy + oz * oz) + D.eps_s);
+  double th = -div / den;
+  if (th < 0.0) th = 0.0;
+  D.nflag[n] = th > D.theta_star ? 1 : 0;
+  if (export_theta) D.theta[n] = th;
+}
+
+__global__ void k_sensor(Desc D, int stage, int export_theta) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < D.N) sensor_body(D, D.win[stage], n, export_theta != 0);
+}
+
+// ------------------------------------------------------------------ interface flags + lists
+__device__ __forceinline__ uint8_t node_flag(const Desc& D, int i, int j, int k) {
+  if (i < 0 || i >= D.nx) {
+    if (!D.per_x) return 0;
+    i = wrapi(i, D.nx);
+  }
+  if (j < 0 || j >= D.ny) {
+    if (!D.per_y) return 0;
+    j = wrapi(j, D.ny);
+  }
+  k = wrapi(k, D.nz);
+  return D.nflag[nidx(D, i, j, k)];
+}
+
+__device__ void iflags_body(const Desc& D, long long n, bool in) {
+  uint8_t f = 0;
+  if (in) {
+    const int i = (int)(n % D.nx);
+    const long long r = n / D.nx;
+    const int j = (int)(r % D.ny), k = (int)(r / D.ny);
+    const int id[3] = {i, j, k};
+    const int nd[3] = {D.nx, D.ny, D.nz};
+    const int per[3] = {D.per_x, D.per_y, 1};
+    for (int d = 0; d < 3; ++d) {
+      if (!per[d] && id[d] == nd[d] - 1) continue;  // boundary interface: central
+      uint8_t b;
+      if (D.sensor_mode == 2) {
+        b = 1;
+      } else {
+        const int di = d == 0, dj = d == 1, dk = d == 2;
+        b = node_flag(D, i - di, j - dj, k - dk) | node_flag(D, i, j, k) |
+            node_flag(D, i + di, j + dj, k + dk) | node_flag(D, i + 2 * di, j + 2 * dj, k + 2 * dk);
+      }
+      f |= (uint8_t)(b << d);
+    }
+    D.iflag[n] = f;
+  }
+  // wave-aggregated append to the per-direction lists
+  for (int d = 0; d < 3; ++d) {
+    const bool b = in && ((f >> d) & 1);
+    const unsigned long long mask = __ballot(b);
+    if (mask == 0ull) continue;
+    const int leader = __ffsll((long long)mask) - 1;
+    const int lane = __lane_id();
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(&D.count[d], (unsigned)__popcll(mask));
+    base = __shfl(base, leader);
+    if (b) {
+      const unsigned rank = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+      D.list[d][base + rank] = (int)n;
+    }
+  }
+}
+
+__global__ void k_iflags(Desc D) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  iflags_body(D, n, n < D.N);
+}
+
+// ------------------------------------------------------------------ WENO on lists
+template <typename F, int DIR>
+__device__ void weno_entry(const Desc& D, const double* __restrict__ w, int n) {
+  const int i = n % D.nx;
+  const int r = n / D.nx;
+  const int j = r % D.ny, k = r / D.ny;
+  double q[6][5];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int o = s - 2;
+    load_node(D, w, i + (DIR == 0 ? o : 0), j + (DIR == 1 ? o : 0), k + (DIR == 2 ? o : 0), q[s]);
+  }
+  F f[5];
+  weno_flux<F, DIR>(D, q, f);
+  double* out = D.Fw[DIR];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) out[(size_t)m * D.N + n] = (double)f[m];
+}
+
+template <typename F>
+__global__ void __launch_bounds__(256) k_weno(Desc D, int stage) {
+  const int dir = blockIdx.y;
+  const unsigned cnt = D.count[dir];
+  const double* w = D.win[stage];
+  for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x) {
+    const int n = D.list[dir][e];
+    if (dir == 0) weno_entry<F, 0>(D, w, n);
+    else if (dir == 1) weno_entry<F, 1>(D, w, n);
+    else weno_entry<F, 2>(D, w, n);
+  }
+}
+
+// ------------------------------------------------------------------ fused right-hand side
+// Quantity slots in the LDS plane.
+enum { QR = 0, QU, QV, QW, QP, QH, QT, QM, NQ };
+
+template <typename F, int TX, int TY>
+struct RhsSmem {
+  F q[NQ][TY + 4][TX + 4];
+  double red[TX * TY / 64];
+};
+
+template <typename F>
+__device__ __forceinline__ F d1c(F m2, F m1, F p1, F p2, F inv) {
+  return inv * (F(CA1) * (p1 - m1) + F(CA2) * (p2 - m2));
+}
+template <typename F>
+__device__ __forceinline__ F d2c(F m2, F m1, F c, F p1, F p2, F inv2) {
+  return inv2 * (F(CB0) * c + F(CB1) * (p1 + m1) + F(CB2) * (p2 + m2));
+}
+
+template <typename F, int TX, int TY>
+__device__ __forceinline__ void lds_prim(const RhsSmem<F, TX, TY>& S, int ly, int lx, PV<F>& s) {
+  s.r = S.q[QR][ly][lx]; s.u = S.q[QU][ly][lx]; s.v = S.q[QV][ly][lx]; s.w = S.q[QW][ly][lx];
+  s.p = S.q[QP][ly][lx]; s.h = S.q[QH][ly][lx]; s.t = S.q[QT][ly][lx]; s.mu = S.q[QM][ly][lx];
+}
+
+template <typename F, int TX, int TY>
+__device__ __forceinline__ void lds_store(RhsSmem<F, TX, TY>& S, int ly, int lx, const PV<F>& s) {
+  S.q[QR][ly][lx] = s.r; S.q[QU][ly][lx] = s.u; S.q[QV][ly][lx] = s.v; S.q[QW][ly][lx] = s.w;
+  S.q[QP][ly][lx] = s.p; S.q[QH][ly][lx] = s.h; S.q[QT][ly][lx] = s.t; S.q[QM][ly][lx] = s.mu;
+}
+
+// One block of the fused kernel: tile (tile index lb) of the instance D.
+template <typename F, int TX, int TY>
+__device__ void rhs_body(const Desc& D, int stage, int lb, RhsSmem<F, TX, TY>& S) {
+  constexpr int LX = TX + 4, LY = TY + 4;
+  constexpr int NT = TX * TY;
+  constexpr int NH = LX * LY - TX * TY;
+  const int tid = threadIdx.x;
+  const int tx = tid % TX, ty = tid / TX;
+  const int txi = lb % D.tiles_x;
+  const int rem = lb / D.tiles_x;
+  const int tyi = rem % D.tiles_y;
+  const int zc = rem / D.tiles_y;
+  const int i0 = txi * TX, j0 = tyi * TY;
+  const int kb = zc * D.kz;
+  const int ke = min(kb + D.kz, D.nz);
+  const int i = i0 + tx, j = j0 + ty;
+  const bool valid = i < D.nx && j < D.ny;
+  const bool col_in = valid;
+  const bool tile_in = i0 >= 2 && i0 + TX + 2 <= D.nx && j0 >= 2 && j0 + TY + 2 <= D.ny;
+  const double* __restrict__ w = D.win[stage];
+  double* __restrict__ R = D.rcur[stage];
+  const size_t N = (size_t)D.N;
+  const int jc = j < D.ny ? j : D.ny - 1;
+  const F idx = (F)D.idx, idz = (F)D.idz, idx2 = (F)D.idx2, idz2 = (F)D.idz2;
+  const F iy = (F)D.iy[jc], iye2 = (F)D.iye2[jc], yee = (F)D.y_etaeta[jc];
+  const F ideta2 = (F)D.ideta2;
+  const F kfac = (F)D.kfac;
+  const bool visc = D.viscous != 0;
+  const bool hybrid = D.sensor_mode != 0;
+  const bool wall_lo = D.wall_lo && j == 0;
+  const bool wall_hi = D.wall_hi && j == D.ny - 1;
+
+  // own-column register window, slots 0..4 = planes c-2..c+2
+  PV<F> win[5];
+  // deferred mixed-derivative windows (planes c-4..c)
+  F Sw[5], Tw[5], Qw[5];
+  double Ra2[5], Ra1[5], Ra0[5];
+  F Fzm[5];
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    win[s] = PV<F>{F(0), F(0), F(0), F(0), F(0), F(0), F(0), F(0)};
+    Sw[s] = Tw[s] = Qw[s] = F(0);
+    Ra2[s] = Ra1[s] = Ra0[s] = 0.0;
+    Fzm[s] = F(0);
+  }
+  double fsum = 0.0;
+
+  auto load_col = [&](int plane, PV<F>& s) {
+    double q[5];
+    if (col_in) {
+      const size_t b = nidx(D, i, j, wrapi(plane, D.nz));
+#pragma unroll
+      for (int m = 0; m < 5; ++m) q[m] = w[(size_t)m * N + b];
+    } else {
+      load_node(D, w, i, j, plane, q);
+    }
+    to_prim<F>(D, q, s);
+  };
+
+  load_col(kb - 2, win[3]);
+  load_col(kb - 1, win[4]);
+
+  for (int c = kb - 2; c <= ke + 1; ++c) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) win[s] = win[s + 1];
+    load_col(c + 2, win[4]);
+    // stage plane c into LDS: interior from the window, halo cooperatively
+    lds_store<F, TX, TY>(S, ty + 2, tx + 2, win[2]);
+    {
+      const int kk = wrapi(c, D.nz);
+      for (int h = tid; h < NH; h += NT) {
+        int lx, ly;
+        if (h < 2 * LX) {
+          ly = h / LX; lx = h - ly * LX;
+        } else if (h < 4 * LX) {
+          const int hh = h - 2 * LX;
+          ly = TY + 2 + hh / LX; lx = hh - (hh / LX) * LX;
+        } else {
+          const int hh = h - 4 * LX;
+          ly = 2 + hh / 4;
+          const int cc = hh & 3;
+          lx = cc < 2 ? cc : TX + cc;
+        }
+        const int gi = i0 - 2 + lx, gj = j0 - 2 + ly;
+        double q[5];
+        if (tile_in) {
+          const size_t b = nidx(D, gi, gj, kk);
+#pragma unroll
+          for (int m = 0; m < 5; ++m) q[m] = w[(size_t)m * N + b];
+        } else {
+          load_node(D, w, gi, gj, kk, q);
+        }
+        PV<F> s;
+        to_prim<F>(D, q, s);
+        lds_store<F, TX, TY>(S, ly, lx, s);
+      }
+    }
+    __syncthreads();
+    const int ly = ty + 2, lx = tx + 2;
+    // in-plane first derivatives feeding the z-mixed terms
+#pragma unroll
+    for (int s = 0; s < 4; ++s) { Sw[s] = Sw[s + 1]; Tw[s] = Tw[s + 1]; Qw[s] = Qw[s + 1]; }
+    if (visc) {
+      const F wx = d1c<F>(S.q[QW][ly][lx - 2], S.q[QW][ly][lx - 1], S.q[QW][ly][lx + 1], S.q[QW][ly][lx + 2], idx);
+      const F wy = d1c<F>(S.q[QW][ly - 2][lx], S.q[QW][ly - 1][lx], S.q[QW][ly + 1][lx], S.q[QW][ly + 2][lx], iy);
+      const F ux = d1c<F>(S.q[QU][ly][lx - 2], S.q[QU][ly][lx - 1], S.q[QU][ly][lx + 1], S.q[QU][ly][lx + 2], idx);
+      const F vy = d1c<F>(S.q[QV][ly - 2][lx], S.q[QV][ly - 1][lx], S.q[QV][ly + 1][lx], S.q[QV][ly + 2][lx], iy);
+      Sw[4] = wx; Tw[4] = wy; Qw[4] = ux + vy;
+    }
+    // z-direction interface flux at c+1/2 (own column)
+    F Fzp[5] = {F(0), F(0), F(0), F(0), F(0)};
+    if (c >= kb - 1 && c < ke && valid) {
+      bool wz = false;
+      size_t nc = 0;
+      if (hybrid) {
+        nc = nidx(D, i, j, wrapi(c, D.nz));
+        wz = (D.iflag[nc] >> 2) & 1;
+      }
+      if (wz) {
+#pragma unroll
+        for (int m = 0; m < 5; ++m) Fzp[m] = (F)D.Fw[2][(size_t)m * N + nc];
+      } else {
+        central_flux<F, 2>(win[1], win[2], win[3], win[4], Fzp);
+      }
+    }
+    if (c >= kb && c < ke && valid) {
+      PV<F> cN[5];  // x-neighbours i-2..i+2
+      PV<F> cM[5];  // y-neighbours j-2..j+2
+#pragma unroll
+      for (int o = 0; o < 5; ++o) {
+        lds_prim<F, TX, TY>(S, ly, lx - 2 + o, cN[o]);
+        lds_prim<F, TX, TY>(S, ly - 2 + o, lx, cM[o]);
+      }
+      F fxr[5], fxl[5], fyr[5], fyl[5];
+      central_flux<F, 0>(cN[1], cN[2], cN[3], cN[4], fxr);
+      central_flux<F, 0>(cN[0], cN[1], cN[2], cN[3], fxl);
+      if (wall_hi) wall_flux<F, 1>(cM[1], cM[2], cM[3], cM[4], fyr);
+      else central_flux<F, 1>(cM[1], cM[2], cM[3], cM[4], fyr);
+      if (wall_lo) wall_flux<F, 1>(cM[0], cM[1], cM[2], cM[3], fyl);
+      else central_flux<F, 1>(cM[0], cM[1], cM[2], cM[3], fyl);
+      if (hybrid) {
+        const size_t n0 = nidx(D, i, j, c);
+        const uint8_t f0 = D.iflag[n0];
+        if (f0 & 1) {
+#pragma unroll
+          for (int m = 0; m < 5; ++m) fxr[m] = (F)D.Fw[0][(size_t)m * N + n0];
+        }
+        if (f0 & 2) {
+#pragma unroll
+          for (int m = 0; m < 5; ++m) fyr[m] = (F)D.Fw[1][(size_t)m * N + n0];
+        }
+        if (i > 0 || D.per_x) {
+          const size_t nl = nidx(D, i > 0 ? i - 1 : D.nx - 1, j, c);
+          if (D.iflag[nl] & 1) {
+#pragma unroll
+            for (int m = 0; m < 5; ++m) fxl[m] = (F)D.Fw[0][(size_t)m * N + nl];
+          }
+        }
+        if (j > 0 || D.per_y) {
+          const size_t nl = nidx(D, i, j > 0 ? j - 1 : D.ny - 1, c);
+          if (D.iflag[nl] & 2) {
+#pragma unroll
+            for (int m = 0; m < 5; ++m) fyl[m] = (F)D.Fw[1][(size_t)m * N + nl];
+          }
+        }
+      }
+      const double didx = D.idx, diy = D.iy[j], didz = D.idz;
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        Ra0[m] = -((double)(fxr[m] - fxl[m]) * didx + (double)(fyr[m] - fyl[m]) * diy +
+                   (double)(Fzp[m] - Fzm[m]) * didz);
+      }
+      if (visc) {
+        const PV<F>& o = win[2];
+        // first derivatives
+        const F ux = d1c<F>(cN[0].u, cN[1].u, cN[3].u, cN[4].u, idx);
+        const F vx = d1c<F>(cN[0].v, cN[1].v, cN[3].v, cN[4].v, idx);
+        const F wx = d1c<F>(cN[0].w, cN[1].w, cN[3].w, cN[4].w, idx);
+        const F Tx = d1c<F>(cN[0].t, cN[1].t, cN[3].t, cN[4].t, idx);
+        const F mx = d1c<F>(cN[0].mu, cN[1].mu, cN[3].mu, cN[4].mu, idx);
+        const F uy = d1c<F>(cM[0].u, cM[1].u, cM[3].u, cM[4].u, iy);
+        const F vy = d1c<F>(cM[0].v, cM[1].v, cM[3].v, cM[4].v, iy);
+        const F wy = d1c<F>(cM[0].w, cM[1].w, cM[3].w, cM[4].w, iy);
+        const F Ty = d1c<F>(cM[0].t, cM[1].t, cM[3].t, cM[4].t, iy);
+        const F my = d1c<F>(cM[0].mu, cM[1].mu, cM[3].mu, cM[4].mu, iy);
+        const F uz = d1c<F>(win[0].u, win[1].u, win[3].u, win[4].u, idz);
+        const F vz = d1c<F>(win[0].v, win[1].v, win[3].v, win[4].v, idz);
+        const F wz = d1c<F>(win[0].w, win[1].w, win[3].w, win[4].w, idz);
+        const F Tz = d1c<F>(win[0].t, win[1].t, win[3].t, win[4].t, idz);
+        const F mz = d1c<F>(win[0].mu, win[1].mu, win[3].mu, win[4].mu, idz);
+        // second derivatives
+        const F uxx = d2c<F>(cN[0].u, cN[1].u, o.u, cN[3].u, cN[4].u, idx2);
+        const F vxx = d2c<F>(cN[0].v, cN[1].v, o.v, cN[3].v, cN[4].v, idx2);
+        const F wxx = d2c<F>(cN[0].w, cN[1].w, o.w, cN[3].w, cN[4].w, idx2);
+        const F Txx = d2c<F>(cN[0].t, cN[1].t, o.t, cN[3].t, cN[4].t, idx2);
+        const F uyy = (d2c<F>(cM[0].u, cM[1].u, o.u, cM[3].u, cM[4].u, ideta2) - yee * uy) * iye2;
+        const F vyy = (d2c<F>(cM[0].v, cM[1].v, o.v, cM[3].v, cM[4].v, ideta2) - yee * vy) * iye2;
+        const F wyy = (d2c<F>(cM[0].w, cM[1].w, o.w, cM[3].w, cM[4].w, ideta2) - yee * wy) * iye2;
+        const F Tyy = (d2c<F>(cM[0].t, cM[1].t, o.t, cM[3].t, cM[4].t, ideta2) - yee * Ty) * iye2;
+        const F uzz = d2c<F>(win[0].u, win[1].u, o.u, win[3].u, win[4].u, idz2);
+        const F vzz = d2c<F>(win[0].v, win[1].v, o.v, win[3].v, win[4].v, idz2);
+        const F wzz = d2c<F>(win[0].w, win[1].w, o.w, win[3].w, win[4].w, idz2);
+        const F Tzz = d2c<F>(win[0].t, win[1].t, o.t, win[3].t, win[4].t, idz2);
+        // in-plane mixed derivatives: d_y (d_x f) with the metric at j
+        F uxr[5], vxr[5];
+#pragma unroll
+        for (int dy = -2; dy <= 2; ++dy) {
+          if (dy == 0) { uxr[2] = ux; vxr[2] = vx; continue; }
+          uxr[dy + 2] = d1c<F>(S.q[QU][ly + dy][lx - 2], S.q[QU][ly + dy][lx - 1],
+                               S.q[QU][ly + dy][lx + 1], S.q[QU][ly + dy][lx + 2], idx);
+          vxr[dy + 2] = d1c<F>(S.q[QV][ly + dy][lx - 2], S.q[QV][ly + dy][lx - 1],
+                               S.q[QV][ly + dy][lx + 1], S.q[QV][ly + dy][lx + 2], idx);
+        }
+        const F uxy = d1c<F>(uxr[0], uxr[1], uxr[3], uxr[4], iy);
+        const F vxy = d1c<F>(vxr[0], vxr[1], vxr[3], vxr[4], iy);
+        const F mu = o.mu;
+        const F div = ux + vy + wz;
+        const F third = F(1.0 / 3.0), twoth = F(2.0 / 3.0);
+        // everything except the z-mixed parts (added two planes later)
+        const F Fx = mu * (uxx + uyy + uzz + third * (uxx + vxy)) + mx * (ux + ux) +
+                     my * (uy + vx) + mz * (uz + wx) - twoth * mx * div;
+        const F Fy = mu * (vxx + vyy + vzz + third * (uxy + vyy)) + mx * (vx + uy) +
+                     my * (vy + vy) + mz * (vz + wy) - twoth * my * div;
+        const F Fz = mu * (wxx + wyy + wzz + third * wzz) + mx * (wx + uz) + my * (wy + vz) +
+                     mz * (wz + wz) - twoth * mz * div;
+        const F sxy = uy + vx, sxz = uz + wx, syz = vz + wy;
+        const F phi = mu * (F(2) * (ux * ux + vy * vy + wz * wz) + sxy * sxy + sxz * sxz + syz * syz -
+                            twoth * div * div);
+        const F heat = kfac * (mu * (Txx + Tyy + Tzz) + mx * Tx + my * Ty + mz * Tz);
+        Ra0[1] += (double)Fx;
+        Ra0[2] += (double)Fy;
+        Ra0[3] += (double)Fz;
+        Ra0[4] += (double)(o.u * Fx + o.v * Fy + o.w * Fz + phi + heat);
+      }
+    }
+    if (c >= kb - 1 && c < ke) {
+#pragma unroll
+      for (int m = 0; m < 5; ++m) Fzm[m] = Fzp[m];
+    }
+    // finish plane c-2: z-mixed viscous parts, store, forcing partial sum
+    if (c >= kb + 2 && valid) {
+      const int m2 = c - 2;
+      if (visc) {
+        const F dS = d1c<F>(Sw[0], Sw[1], Sw[3], Sw[4], idz);  // d_x d_z w
+        const F dT = d1c<F>(Tw[0], Tw[1], Tw[3], Tw[4], idz);  // d_y d_z w
+        const F dQ = d1c<F>(Qw[0], Qw[1], Qw[3], Qw[4], idz);  // d_z (d_x u + d_y v)
+        const PV<F>& o2 = win[0];
+        const F t3 = F(1.0 / 3.0) * o2.mu;
+        const F ax = t3 * dS, ay = t3 * dT, az = t3 * dQ;
+        Ra2[1] += (double)ax;
+        Ra2[2] += (double)ay;
+        Ra2[3] += (double)az;
+        Ra2[4] += (double)(o2.u * ax + o2.v * ay + o2.w * az);
+      }
+      const size_t no = nidx(D, i, j, m2);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) R[(size_t)m * N + no] = Ra2[m];
+      fsum += Ra2[1] * D.y_eta[j];
+    }
+#pragma unroll
+    for (int m = 0; m < 5; ++m) { Ra2[m] = Ra1[m]; Ra1[m] = Ra0[m]; Ra0[m] = 0.0; }
+    __syncthreads();
+  }
+  // block partial sum of R_rhou dV (fixed order)
+  if (D.forcing) {
+    double v = fsum;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+    if ((tid & 63) == 0) S.red[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int q = 0; q < NT / 64; ++q) t += S.red[q];
+      D.part[lb] = t;
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ int xcd_swizzle(int b, int nb) {
+  // consecutive logical tiles land on the same XCD (blocks are dealt
+  // round-robin over the 8 XCDs), so neighbouring tiles share an L2
+  return (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+}
+
+template <typename F, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY) k_rhs(Desc D, int stage) {
+  __shared__ RhsSmem<F, TX, TY> S;
+  const int lb = xcd_swizzle(blockIdx.x, gridDim.x);
+  rhs_body<F, TX, TY>(D, stage, lb, S);
+}
+
+// ------------------------------------------------------------------ reductions
+template <int NT>
+__device__ double block_sum(double v, double* sm) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < NT / 64; ++q) t += sm[q];
+  __syncthreads();
+  return t;
+}
+
+template <int NT>
+__device__ double block_max(double v, double* sm) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off));
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = sm[0];
+  if (threadIdx.x == 0)
+    for (int q = 1; q < NT / 64; ++q) t = fmax(t, sm[q]);
+  __syncthreads();
+  return t;
+}
+
+template <int NT>
+__device__ double block_min(double v, double* sm) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_down(v, off));
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = sm[0];
+  if (threadIdx.x == 0)
+    for (int q = 1; q < NT / 64; ++q) t = fmin(t, sm[q]);
+  __syncthreads();
+  return t;
+}
+
+__device__ void force_body(const Desc& D, double* sm) {
+  double v = 0.0;
+  for (int q = threadIdx.x; q < D.npart; q += 256) v += D.part[q];
+  const double t = block_sum<256>(v, sm);
+  if (threadIdx.x == 0) D.scal[SC_FORCE] = -t / D.vol_den;
+}
+
+__global__ void __launch_bounds__(256) k_force(Desc D) {
+  __shared__ double sm[4];
+  force_body(D, sm);
+}
+
+__global__ void k_apply_force(Desc D, int stage) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= D.N) return;
+  const double f = D.scal[SC_FORCE];
+  const double* w = D.win[stage];
+  double* R = D.rcur[stage];
+  R[D.N + n] += f;
+  R[4 * D.N + n] += f * (w[D.N + n] / w[n]);
+}
+
+// ------------------------------------------------------------------ RK3 update
+__device__ __forceinline__ void rk_point(const Desc& D, int stage, long long n) {
+  const double alpha = stage == 0 ? 0.0 : (stage == 1 ? -17.0 / 60.0 : -5.0 / 12.0);
+  const double beta = stage == 0 ? 8.0 / 15.0 : (stage == 1 ? 5.0 / 12.0 : 3.0 / 4.0);
+  const double* __restrict__ w = D.win[stage];
+  double* __restrict__ wo = D.wout[stage];
+  double* __restrict__ R = D.rcur[stage];
+  const double* __restrict__ Rp = D.rprev[stage];
+  const size_t N = (size_t)D.N;
+  const double dt = D.scal[SC_DT];
+  double q[5], r[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    q[m] = w[m * N + n];
+    r[m] = R[m * N + n];
+  }
+  if (D.forcing) {
+    const double f = D.scal[SC_FORCE];
+    r[1] += f;
+    r[4] += f * (q[1] / q[0]);
+    if (stage < 2) {
+      R[1 * N + n] = r[1];
+      R[4 * N + n] = r[4];
+    }
+  }
+  double o[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    double acc = beta * r[m];
+    if (stage > 0) acc += alpha * Rp[m * N + n];
+    o[m] = q[m] + dt * acc;
+    wo[m * N + n] = o[m];
+  }
+  const double ke = 0.5 * (o[1] * o[1] + o[2] * o[2] + o[3] * o[3]) / o[0];
+  const double pe = o[4] - ke;
+  if (!(o[0] > 0.0) || !(pe > 0.0) || !(fabs(o[4]) < 1e300)) atomicOr(D.status, (unsigned)ST_BAD_STATE);
+}
+
+__global__ void k_rk(Desc D, int stage) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < D.N) rk_point(D, stage, n);
+}
+
+// ------------------------------------------------------------------ time step
+__device__ void dt_part_body(const Desc& D, int b, int nb, double* sm) {
+  const double* w = D.win[0];
+  const size_t N = (size_t)D.N;
+  double cm = 0.0, vm = 0.0;
+  for (long long n = (long long)b * 256 + threadIdx.x; n < D.N; n += (long long)nb * 256) {
+    const int j = (int)((n / D.nx) % D.ny);
+    const double r = w[n], ir = 1.0 / r;
+    const double u = w[N + n] * ir, v = w[2 * N + n] * ir, ww = w[3 * N + n] * ir;
+    const double T = (w[4 * N + n] * ir - 0.5 * (u * u + v * v + ww * ww)) * D.icv;
+    const double p = r * D.R * T;
+    const double c = sqrt(D.gamma * p * ir);
+    const double dy = D.deta * D.y_eta[j];
+    const double conv = (fabs(u) + c) * D.idx + (fabs(v) + c) / dy + (fabs(ww) + c) * D.idz;
+    cm = fmax(cm, conv);
+    if (D.viscous) {
+      const double t = T * D.iTref;
+      const double mu = D.muc * t * sqrt(t) / (t + D.S);
+      const double vis = D.vfac * (mu * ir) * (D.idx2 + 1.0 / (dy * dy) + D.idz2);
+      vm = fmax(vm, vis);
+    }
+  }
+  cm = block_max<256>(cm, sm);
+  vm = block_max<256>(vm, sm);
+  if (threadIdx.x == 0) {
+    D.red[2 * b] = cm;
+    D.red[2 * b + 1] = vm;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_dt_part(Desc D) {
+  __shared__ double sm[4];
+  dt_part_body(D, blockIdx.x, gridDim.x, sm);
+}
+
+__device__ void dt_final_body(const Desc& D, int nb, double* sm) {
+  double dt;
+  if (D.dt_fixed > 0.0) {
+    dt = D.dt_fixed;
+  } else {
+    double cm = 0.0, vm = 0.0;
+    for (int q = threadIdx.x; q < nb; q += 256) {
+      cm = fmax(cm, D.red[2 * q]);
+      vm = fmax(vm, D.red[2 * q + 1]);
+    }
+    cm = block_max<256>(cm, sm);
+    vm = block_max<256>(vm, sm);
+    dt = 1.0 / cm;
+    if (D.viscous && vm > 0.0) {
+      const double dv = 2.5 / (16.0 / 3.0 * vm);
+      if (dv < dt) dt = dv;
+    }
+    dt *= D.cfl;
+  }
+  if (threadIdx.x == 0) {
+    D.scal[SC_DT] = dt;
+    D.scal[SC_TIME] += dt;
+    D.scal[SC_STEP] += 1.0;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_dt_final(Desc D, int nb) {
+  __shared__ double sm[4];
+  dt_final_body(D, nb, sm);
+}
+
+// ------------------------------------------------------------------ diagnostics
+__global__ void __launch_bounds__(256) k_diag_part(Desc D) {
+  __shared__ double sm[4];
+  const double* w = D.win[0];
+  const size_t N = (size_t)D.N;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  double rmin = 1e300, pmin = 1e300, mmax = 0.0, nonf = 0.0;
+  const double dv0 = D.dx * D.dz * D.deta;
+  for (long long n = (long long)blockIdx.x * 256 + threadIdx.x; n < D.N;
+       n += (long long)gridDim.x * 256) {
+    const int j = (int)((n / D.nx) % D.ny);
+    const double dv = dv0 * D.y_eta[j];
+    double q[5];
+    for (int m = 0; m < 5; ++m) {
+      q[m] = w[m * N + n];
+      if (!(fabs(q[m]) < 1e300)) nonf += 1.0;
+      acc[m] += q[m] * dv;
+    }
+    const double ir = 1.0 / q[0];
+    const double ke = 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) * ir;
+    acc[5] += ke * dv;
+    const double p = D.gm1 * (q[4] - ke);
+    rmin = fmin(rmin, q[0]);
+    pmin = fmin(pmin, p);
+    const double c = sqrt(fabs(D.gamma * p * ir));
+    mmax = fmax(mmax, sqrt(2.0 * ke * ir) / c);
+  }
+  double* out = D.redd + (size_t)blockIdx.x * DG_COUNT;
+  for (int m = 0; m < 6; ++m) {
+    const double t = block_sum<256>(acc[m], sm);
+    if (threadIdx.x == 0) out[m] = t;
+  }
+  double t = block_min<256>(rmin, sm);
+  if (threadIdx.x == 0) out[DG_RHOMIN] = t;
+  t = block_min<256>(pmin, sm);
+  if (threadIdx.x == 0) out[DG_PMIN] = t;
+  t = block_max<256>(mmax, sm);
+  if (threadIdx.x == 0) out[DG_MACHMAX] = t;
+  t = block_sum<256>(nonf, sm);
+  if (threadIdx.x == 0) out[DG_NONFINITE] = t;
+}
+
+__global__ void __launch_bounds__(256) k_diag_final(Desc D, int nb) {
+  __shared__ double sm[4];
+  for (int m = 0; m < DG_COUNT; ++m) {
+    double v;
+    if (m == DG_RHOMIN || m == DG_PMIN) {
+      v = 1e300;
+      for (int q = threadIdx.x; q < nb; q += 256) v = fmin(v, D.redd[(size_t)q * DG_COUNT + m]);
+      v = block_min<256>(v, sm);
+    } else if (m == DG_MACHMAX) {
+      v = 0.0;
+      for (int q = threadIdx.x; q < nb; q += 256) v = fmax(v, D.redd[(size_t)q * DG_COUNT + m]);
+      v = block_max<256>(v, sm);
+    } else if (m <= DG_NONFINITE) {
+      v = 0.0;
+      for (int q = threadIdx.x; q < nb; q += 256) v += D.redd[(size_t)q * DG_COUNT + m];
+      v = block_sum<256>(v, sm);
+    } else {
+      v = 0.0;
+    }
+    if (threadIdx.x == 0) D.diag[m] = v;
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+static inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t launch_stage_begin(const Desc& D, hipStream_t st) {
+  k_stage_begin<<<1, 64, 0, st>>>(D);
+  return hipGetLastError();
+}
+
+hipError_t launch_ghosts(const Desc& D, int stage, hipStream_t st) {
+  if (!D.per_x) k_ghost_x<<<nblk(2LL * D.ny * D.nz, 128), 128, 0, st>>>(D, stage);
+  if (!D.per_y) k_ghost_y<<<nblk(2LL * D.nz * D.nxg, 128), 128, 0, st>>>(D, stage);
+  return hipGetLastError();
+}
+
+hipError_t launch_sensor(const Desc& D, int stage, bool export_theta, hipStream_t st) {
+  k_sensor<<<nblk(D.N, 256), 256, 0, st>>>(D, stage, export_theta ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_iflags(const Desc& D, hipStream_t st) {
+  k_iflags<<<nblk(D.N, 256), 256, 0, st>>>(D);
+  return hipGetLastError();
+}
+
+hipError_t launch_weno(const Desc& D, int stage, hipStream_t st) {
+  long long b = nblk(D.N, 256);
+  if (b > 4096) b = 4096;
+  dim3 grid((unsigned)b, 3);
+  if (D.precision == 1) k_weno<float><<<grid, 256, 0, st>>>(D, stage);
+  else k_weno<double><<<grid, 256, 0, st>>>(D, stage);
+  return hipGetLastError();
+}
+
+int rhs_blocks(const Desc& D) { return D.tiles_x * D.tiles_y * D.zchunks; }
+
+bool rhs_tile_supported(int tx, int ty) {
+  return (tx == 64 && ty == 4) || (tx == 32 && ty == 8) || (tx == 64 && ty == 2) ||
+         (tx == 128 && ty == 2);
+}
+
+template <typename F>
+static hipError_t launch_rhs_t(const Desc& D, int stage, hipStream_t st) {
+  const unsigned nb = (unsigned)rhs_blocks(D);
+  if (D.tile_x == 64 && D.tile_y == 4) k_rhs<F, 64, 4><<<nb, 256, 0, st>>>(D, stage);
+  else if (D.tile_x == 32 && D.tile_y == 8) k_rhs<F, 32, 8><<<nb, 256, 0, st>>>(D, stage);
+  else if (D.tile_x == 64 && D.tile_y == 2) k_rhs<F, 64, 2><<<nb, 128, 0, st>>>(D, stage);
+  else if (D.tile_x == 128 && D.tile_y == 2) k_rhs<F, 128, 2><<<nb, 256, 0, st>>>(D, stage);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs(const Desc& D, int stage, hipStream_t st) {
+  return D.precision == 1 ? launch_rhs_t<float>(D, stage, st) : launch_rhs_t<double>(D, stage, st);
+}
+
+hipError_t launch_force(const Desc& D, hipStream_t st) {
+  k_force<<<1, 256, 0, st>>>(D);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_force(const Desc& D, int stage, hipStream_t st) {
+  k_apply_force<<<nblk(D.N, 256), 256, 0, st>>>(D, stage);
+  return hipGetLastError();
+}
+
+hipError_t launch_rk(const Desc& D, int stage, hipStream_t st) {
+  k_rk<<<nblk(D.N, 256), 256, 0, st>>>(D, stage);
+  return hipGetLastError();
+}
+
+hipError_t launch_dt(const Desc& D, hipStream_t st) {
+  int nb = (int)nblk(D.N, 256);
+  if (nb > kRedBlocks) nb = kRedBlocks;
+  if (!(D.dt_fixed > 0.0)) k_dt_part<<<nb, 256, 0, st>>>(D);
+  k_dt_final<<<1, 256, 0, st>>>(D, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag(const Desc& D, hipStream_t st) {
+  int nb = (int)nblk(D.N, 256);
+  if (nb > kRedBlocks) nb = kRedBlocks;
+  k_diag_part<<<nb, 256, 0, st>>>(D);
+  k_diag_final<<<1, 256, 0, st>>>(D, nb);
+  return hipGetLastError();
+}
+
+}  // namespace cdns

@@ -1,0 +1,139 @@
+"""Python front end of the HIP solver: one instance on one GPU.
+
+`Solver` owns torch tensors for the state and the workspace and forwards
+every operation to libcdns.so; it performs no arithmetic of its own.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, Optional
+
+import numpy as np
+
+from . import _binding as B
+
+
+class Solver:
+    """A resident instance of the right-hand side / RK3 stepper.
+
+    `problem` is any object with the fields of `problems.Problem`
+    (grid sizes, lengths, metric arrays, physical parameters, boundary
+    conditions and an initial state w0 of shape (5, nz, ny, nx))."""
+
+    def __init__(self, problem, precision: int = B.CDNS_FP64, device: str = "cuda:0",
+                 tiling=None, stream=None):
+        import torch
+
+        self.torch = torch
+        self.lib = B.load()
+        self.pr = problem
+        self.device = torch.device(device)
+        self.precision = int(precision)
+        nx, ny, nz = problem.nx, problem.ny, problem.nz
+        self._ye = np.ascontiguousarray(problem.y_eta, dtype=np.float64)
+        self._yee = np.ascontiguousarray(problem.y_etaeta, dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        self.grid = B.Grid(nx, ny, nz, problem.lx, problem.lz,
+                           self._ye.ctypes.data_as(dp), self._yee.ctypes.data_as(dp))
+        self.phys = B.Phys(problem.gamma, problem.Pr, problem.R_gas, problem.mu_ref,
+                           problem.T_ref, problem.S_suth, int(bool(problem.viscous)),
+                           int(problem.sensor_mode), problem.theta_star, problem.sensor_eps,
+                           int(bool(problem.forcing)))
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.state = torch.empty((5, nz, ny, nx), dtype=torch.float64, device=self.device)
+        wsb = self.lib.cdns_workspace_bytes(ctypes.byref(self.grid), self.precision)
+        if wsb == 0:
+            raise B.CdnsError(B.CDNS_EINVAL, "invalid grid")
+        self._ws = torch.empty(wsb + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.ctx = ctypes.c_void_p()
+        st = self.lib.cdns_create(ctypes.byref(self.grid), ctypes.byref(self.phys),
+                                  self.precision, self.state.data_ptr(), self._ws_ptr, wsb,
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.ctx))
+        B.check(self.lib, None, st, "cdns_create")
+        for face, (kind, params) in enumerate(problem.bcs):
+            arr = np.ascontiguousarray(np.asarray(params, dtype=np.float64).ravel())
+            ptr = arr.ctypes.data_as(dp) if arr.size else None
+            B.check(self.lib, self.ctx,
+                    self.lib.cdns_set_bc(self.ctx, face, int(kind), ptr, arr.size), "cdns_set_bc")
+        if tiling is not None:
+            self.set_tiling(*tiling)
+        if problem.w0 is not None:
+            self.set_state(problem.w0)
+
+    # ------------------------------------------------------------ state
+    def set_state(self, w) -> None:
+        t = self.torch
+        if isinstance(w, np.ndarray):
+            w = t.from_numpy(np.ascontiguousarray(w, dtype=np.float64))
+        with t.cuda.stream(self.stream):
+            self.state.copy_(w.to(self.device, dtype=t.float64))
+
+    def get_state(self) -> np.ndarray:
+        with self.torch.cuda.stream(self.stream):
+            out = self.state.cpu()
+        return out.numpy()
+
+    # ------------------------------------------------------------ operations
+    def set_tiling(self, tile_x: int, tile_y: int, kz: int) -> None:
+        B.check(self.lib, self.ctx, self.lib.cdns_set_tiling(self.ctx, tile_x, tile_y, kz),
+                "cdns_set_tiling")
+
+    def rhs(self, w=None, out=None):
+        t = self.torch
+        if w is None:
+            w = self.state
+        elif isinstance(w, np.ndarray):
+            w = t.from_numpy(np.ascontiguousarray(w, dtype=np.float64)).to(self.device)
+        w = w.contiguous()
+        if out is None:
+            out = t.empty_like(w)
+        B.check(self.lib, self.ctx, self.lib.cdns_rhs(self.ctx, w.data_ptr(), out.data_ptr()),
+                "cdns_rhs")
+        return out
+
+    def rk_step(self, cfl: Optional[float] = None, dt_fixed: float = 0.0) -> None:
+        cfl = self.pr.cfl if cfl is None else cfl
+        B.check(self.lib, self.ctx, self.lib.cdns_rk_step(self.ctx, float(cfl), float(dt_fixed)),
+                "cdns_rk_step")
+
+    def advance(self, n: int, cfl: Optional[float] = None, dt_fixed: float = 0.0) -> None:
+        cfl = self.pr.cfl if cfl is None else cfl
+        B.check(self.lib, self.ctx,
+                self.lib.cdns_advance_n(self.ctx, int(n), float(cfl), float(dt_fixed)),
+                "cdns_advance_n")
+
+    def diagnostics(self, raise_on_error: bool = True) -> Dict:
+        d = B.Diag()
+        st = self.lib.cdns_diagnostics(self.ctx, ctypes.byref(d))
+        if raise_on_error:
+            B.check(self.lib, self.ctx, st, "cdns_diagnostics")
+        return {"dt": d.dt, "time": d.time, "mass": d.mass, "mom": list(d.mom),
+                "energy": d.energy, "kinetic": d.kinetic, "rho_min": d.rho_min,
+                "p_min": d.p_min, "mach_max": d.mach_max, "forcing_f": d.forcing_f,
+                "weno_frac": list(d.weno_frac), "step": d.step, "nonfinite": d.nonfinite,
+                "status": d.status, "rc": st}
+
+    def export_sensor(self):
+        t = self.torch
+        shp = (self.pr.nz, self.pr.ny, self.pr.nx)
+        theta = t.empty(shp, dtype=t.float64, device=self.device)
+        nfl = t.empty(shp, dtype=t.uint8, device=self.device)
+        ifl = t.empty(shp, dtype=t.uint8, device=self.device)
+        B.check(self.lib, self.ctx,
+                self.lib.cdns_export_sensor(self.ctx, theta.data_ptr(), nfl.data_ptr(),
+                                            ifl.data_ptr()), "cdns_export_sensor")
+        return theta, nfl, ifl
+
+    def close(self) -> None:
+        if self.ctx:
+            self.stream.synchronize()
+            self.lib.cdns_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
