@@ -88,6 +88,8 @@ def _load():
         lib.ora_eigenvectors.restype = None
         lib.ora_totals.argtypes = [pp, dp, dp]
         lib.ora_totals.restype = ctypes.c_int
+        lib.ora_iface_flux.argtypes = [pp, dp, ctypes.c_int, dp]
+        lib.ora_iface_flux.restype = ctypes.c_int
         lib.ora_num_threads.argtypes = []
         lib.ora_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -216,6 +218,17 @@ def totals(pr, w: np.ndarray) -> np.ndarray:
     out = np.zeros(6)
     m = _Marshalled(pr)
     _check(lib.ora_totals(ctypes.byref(m.s), _dptr(w), _dptr(out)), "ora_totals")
+    return out
+
+
+def iface_flux(pr, d: int, w: Optional[np.ndarray] = None) -> np.ndarray:
+    """Interface fluxes along direction d as used by the right-hand side
+    (interface i+1/2 stored at node i), shape (5, nz, ny, nx)."""
+    lib = _load()
+    w = np.ascontiguousarray(pr.w0 if w is None else w, dtype=np.float64)
+    out = np.zeros((5, pr.nz, pr.ny, pr.nx))
+    m = _Marshalled(pr)
+    _check(lib.ora_iface_flux(ctypes.byref(m.s), _dptr(w), int(d), _dptr(out)), "ora_iface_flux")
     return out
 
 

@@ -67,7 +67,7 @@ typedef struct {
   int nx, ny, nz, nxp, nyp, nzp;
   size_t np;
   double dx, dz, deta;
-  double cv, cp;
+  double cv, cp, icv;
 } geom;
 
 static void make_geom(const ora_problem* P, geom* g) {
@@ -76,6 +76,7 @@ static void make_geom(const ora_problem* P, geom* g) {
   g->np = (size_t)g->nxp * g->nyp * g->nzp;
   g->dx = P->lx / P->nx; g->dz = P->lz / P->nz; g->deta = 1.0 / P->ny;
   g->cv = P->R_gas / (P->gamma - 1.0);
+  g->icv = 1.0 / g->cv;
   g->cp = P->gamma * P->R_gas / (P->gamma - 1.0);
 }
 
@@ -93,17 +94,20 @@ static inline size_t uidx(const geom* g, int i, int j, int k) {
 typedef struct { double rho, u, v, w, p, T, Ht, mu; } prim_t;
 
 static prim_t to_prim(const ora_problem* P, const geom* g, const double q[5]) {
+  /* evaluation order shared with the GPU library's FP64 path (both without
+   * contraction): one reciprocal of the density, then products */
   prim_t s;
+  double ir = 1.0 / q[0];
   s.rho = q[0];
-  s.u = q[1] / q[0];
-  s.v = q[2] / q[0];
-  s.w = q[3] / q[0];
+  s.u = q[1] * ir;
+  s.v = q[2] * ir;
+  s.w = q[3] * ir;
   double ke = 0.5 * (s.u * s.u + s.v * s.v + s.w * s.w);
-  double E = q[4] / q[0];
-  s.T = (E - ke) / g->cv;
+  double E = q[4] * ir;
+  s.T = (E - ke) * g->icv;
   s.p = s.rho * P->R_gas * s.T;
-  s.Ht = E + s.p / s.rho;
-  double t = s.T / P->T_ref;
+  s.Ht = E + s.p * ir;
+  double t = s.T * (1.0 / P->T_ref);
   s.mu = P->mu_ref * t * sqrt(t) * (1.0 + P->S_suth) / (t + P->S_suth);
   return s;
 }
@@ -181,10 +185,13 @@ double ora_weno5(const double* v) {
   double q0 = (2.0 * vm2 - 7.0 * vm1 + 11.0 * v0) / 6.0;
   double q1 = (-vm1 + 5.0 * v0 + 2.0 * vp1) / 6.0;
   double q2 = (2.0 * v0 + 5.0 * vp1 - vp2) / 6.0;
-  double t;
-  double s0 = 13.0 / 12.0 * (t = vm2 - 2.0 * vm1 + v0, t * t) + 0.25 * (t = vm2 - 4.0 * vm1 + 3.0 * v0, t * t);
-  double s1 = 13.0 / 12.0 * (t = vm1 - 2.0 * v0 + vp1, t * t) + 0.25 * (t = vm1 - vp1, t * t);
-  double s2 = 13.0 / 12.0 * (t = v0 - 2.0 * vp1 + vp2, t * t) + 0.25 * (t = 3.0 * v0 - 4.0 * vp1 + vp2, t * t);
+  /* smoothness indicators: squared second and first differences of each candidate */
+  double c0 = vm2 - 2.0 * vm1 + v0, e0 = vm2 - 4.0 * vm1 + 3.0 * v0;
+  double c1 = vm1 - 2.0 * v0 + vp1, e1 = vm1 - vp1;
+  double c2 = v0 - 2.0 * vp1 + vp2, e2 = 3.0 * v0 - 4.0 * vp1 + vp2;
+  double s0 = 13.0 / 12.0 * (c0 * c0) + 0.25 * (e0 * e0);
+  double s1 = 13.0 / 12.0 * (c1 * c1) + 0.25 * (e1 * e1);
+  double s2 = 13.0 / 12.0 * (c2 * c2) + 0.25 * (e2 * e2);
   const double eps = 1e-6;
   double a0 = 0.1 / ((eps + s0) * (eps + s0));
   double a1 = 0.6 / ((eps + s1) * (eps + s1));
@@ -604,9 +611,10 @@ static void euler_terms(const ora_problem* P, work_t* a, double* r) {
         for (int ii = 0; ii < n[d]; ++ii) {
           int id[3];
           id[d] = ii; id[o1] = b1; id[o2] = b2;
-          double delta = d == 0 ? g->dx : (d == 2 ? g->dz : g->deta * P->y_eta[id[1]]);
+          /* flux difference times the inverse local spacing (eq. num_flux) */
+          double inv = d == 0 ? 1.0 / g->dx : (d == 2 ? 1.0 / g->dz : 1.0 / (g->deta * P->y_eta[id[1]]));
           size_t u = uidx(g, id[0], id[1], id[2]);
-          for (int c = 0; c < 5; ++c) r[(size_t)c * N + u] -= (F[ii + 1][c] - F[ii][c]) / delta;
+          for (int c = 0; c < 5; ++c) r[(size_t)c * N + u] -= (F[ii + 1][c] - F[ii][c]) * inv;
         }
         free(F);
       }
@@ -882,4 +890,36 @@ int ora_num_threads(void) {
   }
 #endif
   return n;
+}
+
+/* Test hook: the interface fluxes of direction d exactly as used by the
+ * right-hand side (central, shock-capturing or wall), interface i+1/2
+ * stored at node i, layout out[5][nz][ny][nx]. */
+int ora_iface_flux(const ora_problem* P, const double* w, int d, double* out) {
+  int st = validate(P);
+  if (st) return st;
+  work_t a;
+  if (work_alloc(P, &a)) return ORA_ENOMEM;
+  st = prepare(P, w, &a);
+  if (st) { work_free(&a); return st; }
+  const geom* g = &a.g;
+  size_t N = (size_t)g->nx * g->ny * g->nz;
+  if (P->sensor_mode == 1) { sensor_theta(P, &a, NULL); wrap_flags(P, &a); }
+  interface_flags(P, &a);
+  size_t stv[3] = {1, (size_t)g->nxp, (size_t)g->nxp * g->nyp};
+  int wall_hi = d == 1 && (P->bc_kind[3] == BC_WALL_ISO || P->bc_kind[3] == BC_WALL_ADIA);
+  int n[3] = {g->nx, g->ny, g->nz};
+  for (int k = 0; k < g->nz; ++k)
+    for (int j = 0; j < g->ny; ++j)
+      for (int i = 0; i < g->nx; ++i) {
+        size_t q = pidx(g, i, j, k);
+        int id[3] = {i, j, k};
+        double f[5];
+        if (P->sensor_mode > 0 && a.iflag[d][q]) weno_flux(P, &a, q, stv[d], d, f);
+        else central_flux(&a, q, stv[d], d, 1, 1, f);
+        if (wall_hi && id[d] == n[d] - 1) central_flux(&a, q, stv[d], d, 0, 1, f);
+        for (int c = 0; c < 5; ++c) out[(size_t)c * N + uidx(g, i, j, k)] = f[c];
+      }
+  work_free(&a);
+  return ORA_OK;
 }

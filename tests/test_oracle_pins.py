@@ -76,6 +76,44 @@ def test_weno5_reproduces_quadratics_exactly():
         assert abs(val - poly(x0 + h / 2)) < 1e-13 * max(1.0, abs(poly(x0 + h / 2)))
 
 
+def _weno5_from_polynomials(v, h=1.0, eps=1e-6):
+    """WENO5-JS rebuilt from its definition: the three quadratic candidates
+    matching the cell averages of their stencils, smoothness indicators
+    beta_k = sum_l h^(2l-1) int_cell (p_k^(l))^2 dx, weights d/(eps+beta)^2."""
+    P_ = np.polynomial.Polynomial
+    centers = h * np.arange(-2, 3)
+    x_face = h / 2
+    stencils = [(0, 1, 2), (1, 2, 3), (2, 3, 4)]
+    dlin = [0.1, 0.6, 0.3]
+    qs, betas = [], []
+    for st in stencils:
+        A = np.zeros((3, 3))
+        for r, c in enumerate(st):
+            for pw in range(3):
+                a, b = centers[c] - h / 2, centers[c] + h / 2
+                A[r, pw] = (b ** (pw + 1) - a ** (pw + 1)) / ((pw + 1) * h)
+        coef = np.linalg.solve(A, np.array([v[c] for c in st]))
+        p = P_(coef)
+        qs.append(p(x_face))
+        beta = 0.0
+        for l in (1, 2):
+            dp = p.deriv(l)
+            integ = (dp * dp).integ()
+            beta += h ** (2 * l - 1) * (integ(h / 2) - integ(-h / 2))
+        betas.append(beta)
+    al = np.array(dlin) / (eps + np.array(betas)) ** 2
+    return float(al @ np.array(qs) / al.sum())
+
+
+def test_weno5_matches_definition_from_candidate_polynomials():
+    rng = np.random.default_rng(7)
+    for scale in (1e-3, 1.0, 30.0):
+        for _ in range(200):
+            v = scale * rng.normal(size=5)
+            ref = _weno5_from_polynomials(v)
+            assert abs(oracle.weno5(v) - ref) <= 1e-12 * max(1.0, np.abs(v).max())
+
+
 def test_weno5_fifth_order_on_smooth_data():
     """Face value from cell averages of exp(sin x): error ratio ~32 per halving."""
     f = lambda x: np.exp(np.sin(x))
