@@ -183,6 +183,11 @@ cdns_status cdns_diagnostics(cdns_ctx* ctx, cdns_diag* out);
 cdns_status cdns_export_sensor(cdns_ctx* ctx, double* theta_dev, uint8_t* nflags_dev,
                                uint8_t* iflags_dev);
 
+/* Test hook: shock-capturing interface fluxes of direction dir (0..2) from
+ * the last cdns_rhs, interface i+1/2 at node i, layout [5][nz][ny][nx]
+ * (device); entries of interfaces that were not flagged are undefined. */
+cdns_status cdns_export_iface_flux(cdns_ctx* ctx, int32_t dir, double* out_dev);
+
 /* Last error message of the context (valid until the next call on it). */
 const char* cdns_last_error(const cdns_ctx* ctx);
 

@@ -21,6 +21,7 @@ CDNS_FP64, CDNS_FP32_FLUX = 0, 1
 EXPORTED = [
     "cdns_version", "cdns_workspace_bytes", "cdns_create", "cdns_set_bc", "cdns_set_tiling",
     "cdns_rhs", "cdns_rk_step", "cdns_advance_n", "cdns_diagnostics", "cdns_export_sensor",
+    "cdns_export_iface_flux",
     "cdns_last_error", "cdns_destroy", "cdns_batch_create", "cdns_batch_workspace_bytes",
     "cdns_batch_attach", "cdns_batch_detach", "cdns_batch_set_step", "cdns_batch_step",
     "cdns_batch_destroy",
@@ -93,6 +94,8 @@ def load() -> ctypes.CDLL:
     lib.cdns_diagnostics.restype = i32
     lib.cdns_export_sensor.argtypes = [vp, dp, dp, dp]
     lib.cdns_export_sensor.restype = i32
+    lib.cdns_export_iface_flux.argtypes = [vp, i32, dp]
+    lib.cdns_export_iface_flux.restype = i32
     lib.cdns_last_error.argtypes = [vp]
     lib.cdns_last_error.restype = ctypes.c_char_p
     lib.cdns_destroy.argtypes = [vp]

@@ -491,6 +491,18 @@ cdns_status cdns_export_sensor(cdns_ctx* c, double* theta_dev, uint8_t* nflags_d
   return CDNS_OK;
 }
 
+cdns_status cdns_export_iface_flux(cdns_ctx* c, int32_t dir, double* out_dev) {
+  if (!c) return CDNS_EINVAL;
+  if (dir < 0 || dir > 2 || !out_dev) return fail(c, CDNS_EINVAL, "bad direction or pointer");
+  if (!c->last_rhs_valid) return fail(c, CDNS_EINVAL, "no right-hand side evaluated yet");
+  const Desc& D = c->D;
+  hipError_t e = hipMemcpyAsync(out_dev, D.Fw[dir], 5 * D.N * sizeof(double),
+                                hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "export");
+  return CDNS_OK;
+}
+
 const char* cdns_last_error(const cdns_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
 cdns_status cdns_destroy(cdns_ctx* c) {

@@ -105,6 +105,27 @@ __device__ __forceinline__ void to_prim(const Desc& D, const double q[5], PV<F>&
   s.mu = (F)D.muc * tt * sqrt(tt) / (tt + (F)D.S);
 }
 
+// FP64 primitives in a fixed evaluation order without contraction: the
+// pressure and enthalpy feed fluxes that are differenced across a cell, so
+// at low Mach number (p >> rho u^2) their rounding dominates the residual;
+// keeping the order fixed keeps results reproducible against the reference.
+template <>
+__device__ __forceinline__ void to_prim<double>(const Desc& D, const double q[5], PV<double>& s) {
+#pragma clang fp contract(off)
+  const double ir = 1.0 / q[0];
+  s.r = q[0];
+  s.u = q[1] * ir;
+  s.v = q[2] * ir;
+  s.w = q[3] * ir;
+  const double ke = 0.5 * (s.u * s.u + s.v * s.v + s.w * s.w);
+  const double E = q[4] * ir;
+  s.t = (E - ke) * D.icv;
+  s.p = s.r * D.R * s.t;
+  s.h = E + s.p * ir;
+  const double tt = s.t * D.iTref;
+  s.mu = D.mu_ref * tt * sqrt(tt) * (1.0 + D.S) / (tt + D.S);
+}
+
 // Energy-preserving central flux (eq. encflux with L = 2) at the interface
 // between nodes b and c of the four consecutive nodes a, b, c, d along
 // direction DIR; pressure in the same conservative form.
@@ -126,12 +147,60 @@ __device__ __forceinline__ void central_flux(const PV<F>& a, const PV<F>& b, con
   f[1 + DIR] += F(CA1) * (b.p + c.p) + F(CA2) * ((b.p + d.p) + (a.p + c.p));
 }
 
+// FP64 version: the split-form triple products (1/8)(F_a+F_b)(G_a+G_b)(H_a+H_b)
+// are accumulated over the pairs (i,i+1), (i,i+2), (i-1,i+1) with the weights
+// a_1, a_2, a_2, then doubled, in a fixed order without contraction.
+template <int DIR>
+__device__ __forceinline__ void central_flux_f64(const PV<double>& a, const PV<double>& b,
+                                                 const PV<double>& c, const PV<double>& d,
+                                                 double f[5]) {
+#pragma clang fp contract(off)
+  const double na = DIR == 0 ? a.u : (DIR == 1 ? a.v : a.w);
+  const double nb = DIR == 0 ? b.u : (DIR == 1 ? b.v : b.w);
+  const double nc = DIR == 0 ? c.u : (DIR == 1 ? c.v : c.w);
+  const double nd = DIR == 0 ? d.u : (DIR == 1 ? d.v : d.w);
+  const double m1 = 0.125 * (b.r + c.r) * (nb + nc);
+  const double m2 = 0.125 * (b.r + d.r) * (nb + nd);
+  const double m3 = 0.125 * (a.r + c.r) * (na + nc);
+  f[0] = 2.0 * (CA1 * (m1 * 2.0) + CA2 * (m2 * 2.0) + CA2 * (m3 * 2.0));
+  f[1] = 2.0 * (CA1 * (m1 * (b.u + c.u)) + CA2 * (m2 * (b.u + d.u)) + CA2 * (m3 * (a.u + c.u)));
+  f[2] = 2.0 * (CA1 * (m1 * (b.v + c.v)) + CA2 * (m2 * (b.v + d.v)) + CA2 * (m3 * (a.v + c.v)));
+  f[3] = 2.0 * (CA1 * (m1 * (b.w + c.w)) + CA2 * (m2 * (b.w + d.w)) + CA2 * (m3 * (a.w + c.w)));
+  f[4] = 2.0 * (CA1 * (m1 * (b.h + c.h)) + CA2 * (m2 * (b.h + d.h)) + CA2 * (m3 * (a.h + c.h)));
+  const double pf = (CA1 * 0.5) * (b.p + c.p) + (CA2 * 0.5) * (b.p + d.p) + (CA2 * 0.5) * (a.p + c.p);
+  f[1 + DIR] = f[1 + DIR] + 2.0 * pf;
+}
+
 // Pressure-only flux at a staggered wall (convective fluxes vanish there).
 template <typename F, int DIR>
 __device__ __forceinline__ void wall_flux(const PV<F>& a, const PV<F>& b, const PV<F>& c,
                                           const PV<F>& d, F f[5]) {
   f[0] = f[1] = f[2] = f[3] = f[4] = F(0);
   f[1 + DIR] = F(CA1) * (b.p + c.p) + F(CA2) * ((b.p + d.p) + (a.p + c.p));
+}
+
+template <int DIR>
+__device__ __forceinline__ void wall_flux_f64(const PV<double>& a, const PV<double>& b,
+                                              const PV<double>& c, const PV<double>& d,
+                                              double f[5]) {
+#pragma clang fp contract(off)
+  f[0] = f[1] = f[2] = f[3] = f[4] = 0.0;
+  const double pf = (CA1 * 0.5) * (b.p + c.p) + (CA2 * 0.5) * (b.p + d.p) + (CA2 * 0.5) * (a.p + c.p);
+  f[1 + DIR] = 2.0 * pf;
+}
+
+// Dispatch: FP64 uses the fixed-order forms above.
+template <typename F, int DIR>
+__device__ __forceinline__ void cflux(const PV<F>& a, const PV<F>& b, const PV<F>& c,
+                                      const PV<F>& d, F f[5]) {
+  if constexpr (sizeof(F) == 8) central_flux_f64<DIR>(a, b, c, d, f);
+  else central_flux<F, DIR>(a, b, c, d, f);
+}
+template <typename F, int DIR>
+__device__ __forceinline__ void wflux(const PV<F>& a, const PV<F>& b, const PV<F>& c,
+                                      const PV<F>& d, F f[5]) {
+  if constexpr (sizeof(F) == 8) wall_flux_f64<DIR>(a, b, c, d, f);
+  else wall_flux<F, DIR>(a, b, c, d, f);
 }
 
 // WENO5 (Jiang-Shu) at the right face of v0 from (v-2, v-1, v0, v1, v2).
@@ -362,7 +431,7 @@ __device__ __forceinline__ double vel_at(const Desc& D, const double* __restrict
                                          int k, int comp) {
   double q[5];
   load_node(D, w, i, j, k, q);
-  return q[comp] / q[0];
+  return q[comp] * (1.0 / q[0]);
 }
 
 __device__ void sensor_body(const Desc& D, const double* __restrict__ w, long long n,
@@ -644,7 +713,7 @@ __device__ void rhs_body(const Desc& D, int stage, int lb, RhsSmem<F, TX, TY>& S
 #pragma unroll
         for (int m = 0; m < 5; ++m) Fzp[m] = (F)D.Fw[2][(size_t)m * N + nc];
       } else {
-        central_flux<F, 2>(win[1], win[2], win[3], win[4], Fzp);
+        cflux<F, 2>(win[1], win[2], win[3], win[4], Fzp);
       }
     }
     if (c >= kb && c < ke && valid) {
@@ -656,12 +725,12 @@ __device__ void rhs_body(const Desc& D, int stage, int lb, RhsSmem<F, TX, TY>& S
         lds_prim<F, TX, TY>(S, ly - 2 + o, lx, cM[o]);
       }
       F fxr[5], fxl[5], fyr[5], fyl[5];
-      central_flux<F, 0>(cN[1], cN[2], cN[3], cN[4], fxr);
-      central_flux<F, 0>(cN[0], cN[1], cN[2], cN[3], fxl);
-      if (wall_hi) wall_flux<F, 1>(cM[1], cM[2], cM[3], cM[4], fyr);
-      else central_flux<F, 1>(cM[1], cM[2], cM[3], cM[4], fyr);
-      if (wall_lo) wall_flux<F, 1>(cM[0], cM[1], cM[2], cM[3], fyl);
-      else central_flux<F, 1>(cM[0], cM[1], cM[2], cM[3], fyl);
+      cflux<F, 0>(cN[1], cN[2], cN[3], cN[4], fxr);
+      cflux<F, 0>(cN[0], cN[1], cN[2], cN[3], fxl);
+      if (wall_hi) wflux<F, 1>(cM[1], cM[2], cM[3], cM[4], fyr);
+      else cflux<F, 1>(cM[1], cM[2], cM[3], cM[4], fyr);
+      if (wall_lo) wflux<F, 1>(cM[0], cM[1], cM[2], cM[3], fyl);
+      else cflux<F, 1>(cM[0], cM[1], cM[2], cM[3], fyl);
       if (hybrid) {
         const size_t n0 = nidx(D, i, j, c);
         const uint8_t f0 = D.iflag[n0];
@@ -691,8 +760,11 @@ __device__ void rhs_body(const Desc& D, int stage, int lb, RhsSmem<F, TX, TY>& S
       const double didx = D.idx, diy = D.iy[j], didz = D.idz;
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
-        Ra0[m] = -((double)(fxr[m] - fxl[m]) * didx + (double)(fyr[m] - fyl[m]) * diy +
-                   (double)(Fzp[m] - Fzm[m]) * didz);
+        // flux difference times the inverse spacing, x then y then z (eq. num_flux)
+#pragma clang fp contract(off)
+        double acc = 0.0 - (double)(fxr[m] - fxl[m]) * didx;
+        acc = acc - (double)(fyr[m] - fyl[m]) * diy;
+        Ra0[m] = acc - (double)(Fzp[m] - Fzm[m]) * didz;
       }
       if (visc) {
         const PV<F>& o = win[2];
@@ -870,7 +942,7 @@ __global__ void k_apply_force(Desc D, int stage) {
   const double* w = D.win[stage];
   double* R = D.rcur[stage];
   R[D.N + n] += f;
-  R[4 * D.N + n] += f * (w[D.N + n] / w[n]);
+  R[4 * D.N + n] += f * (w[D.N + n] * (1.0 / w[n]));
 }
 
 // ------------------------------------------------------------------ RK3 update
@@ -892,7 +964,7 @@ __device__ __forceinline__ void rk_point(const Desc& D, int stage, long long n) 
   if (D.forcing) {
     const double f = D.scal[SC_FORCE];
     r[1] += f;
-    r[4] += f * (q[1] / q[0]);
+    r[4] += f * (q[1] * (1.0 / q[0]));
     if (stage < 2) {
       R[1 * N + n] = r[1];
       R[4 * N + n] = r[4];

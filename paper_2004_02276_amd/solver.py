@@ -126,6 +126,13 @@ class Solver:
                                             ifl.data_ptr()), "cdns_export_sensor")
         return theta, nfl, ifl
 
+    def export_iface_flux(self, d: int):
+        t = self.torch
+        out = t.empty((5, self.pr.nz, self.pr.ny, self.pr.nx), dtype=t.float64, device=self.device)
+        B.check(self.lib, self.ctx, self.lib.cdns_export_iface_flux(self.ctx, d, out.data_ptr()),
+                "cdns_export_iface_flux")
+        return out
+
     def close(self) -> None:
         if self.ctx:
             self.stream.synchronize()
