@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the RK3 step of the compressible Navier-Stokes
+solver on one MI355X.
+
+Workload: the compressible channel 256x128x128 (4.19 M points, FP64 state,
+isothermal staggered walls on a tanh-stretched grid, bulk Mach 1.5,
+Re_b = 3000, hybrid central/WENO with the Ducros sensor, bulk forcing),
+synthetic seeded initial field.  A step is one full RK3 step (three
+stages of ghost planes, sensor, flag compaction, WENO on lists, fused
+right-hand side, forcing reduction and update), replayed from a HIP graph.
+
+Prints ONE JSON line with the throughput (Mpoint-RK-steps/s), the roofline
+of the dominant kernel (durations from HIP events on the library's stream
+in the same run) and the FP64 oracle timed on the host cores on a bounded
+sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpoint-RK-steps/s (hybrid RHS) & % HBM peak; batched p50/p99 step latency"
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_TFLOPS = 78.6
+# Algorithmic bytes per point: one RK3 step must read w and write w', R
+# (stage 0), read w, R_prev and write w', R (stage 1), read w, R_prev and
+# write w' (stage 2) = 400 B; the lazy bulk forcing adds one 8-byte field
+# per stage written and read = 448 B with forcing.
+STEP_BYTES_PER_PT_FORCED = 448.0
+# The fused right-hand-side kernel must read w (40 B) and write R (40 B).
+RHS_BYTES_PER_PT = 80.0
+# FP64 operations of one shock-capturing interface flux (counted from the
+# formula: primitives and fluxes of six nodes, Roe average, left
+# eigenvectors, two projections per node, Lax-Friedrichs split, ten WENO5
+# reconstructions, back-projection); see the design doc.
+WENO_FLOPS_PER_IFACE = 1400.0
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("cdns_kernels.hip",):
+        with open(os.path.join(ROOT, "paper_2004_02276_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = t.get(kernel)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(pr):
+    import oracle
+    oracle.build(force=False)
+    w = pr.w0
+    nthreads = oracle.num_threads()
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        w = oracle.advance(pr, 1, w=w, cfl=pr.cfl)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > 10.0 or steps >= 4:
+            break
+    rate = pr.npts * steps / el / 1e6
+    return {"value": rate, "unit": "Mpoint-RK-steps/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{steps} RK3 step(s) of the full {pr.nx}x{pr.ny}x{pr.nz} channel from the "
+                      f"same seeded initial field, {el:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--precision", choices=["fp64", "fp32flux"], default="fp64")
+    ap.add_argument("--profile-steps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: this build has no multi-GPU path (one simulation "
+              "per GPU; see DESIGN.md for how the step would shard). Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import problems as P
+    from paper_2004_02276_amd import Solver
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    pr = P.channel()
+    precision = 0 if args.precision == "fp64" else 1
+    s = Solver(pr, precision=precision)
+    cfl = pr.cfl
+    print(f"# workload {pr.name} {pr.npts} points, warmup {args.warmup}", file=sys.stderr,
+          flush=True)
+    s.advance(args.warmup, cfl=cfl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.advance(args.steps, cfl=cfl)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    d = s.diagnostics()
+    el = t1 - t0
+    ms_per_step = el * 1e3 / args.steps
+    value = pr.npts * args.steps / el / 1e6
+    print(f"# timed {args.steps} steps in {el:.3f} s, weno fraction {d['weno_frac']}",
+          file=sys.stderr, flush=True)
+
+    # per-kernel durations with HIP events, same state and launch configuration
+    ph = s.time_phases(args.profile_steps, cfl=cfl)
+    per_step = {k: v[0] * v[1] / args.profile_steps for k, v in ph.items()}
+    dom = max(per_step, key=per_step.get)
+    mean_ms = ph[dom][0]
+    if dom == "weno":
+        n_iface = sum(d["weno_frac"]) * pr.npts
+        flops = WENO_FLOPS_PER_IFACE * n_iface
+        achieved = flops / (mean_ms * 1e-3) / 1e12
+        roof = {"kernel": "k_weno", "bound": "alu", "achieved": achieved,
+                "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_TFLOPS,
+                "traffic": load_traffic("k_weno"),
+                "algorithmic_per_launch": f"{WENO_FLOPS_PER_IFACE:.0f} flop x {n_iface:.0f} interfaces"}
+    else:
+        nbytes = RHS_BYTES_PER_PT * pr.npts
+        achieved = nbytes / (ph["rhs"][0] * 1e-3) / 1e9
+        roof = {"kernel": "k_rhs", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic("k_rhs"),
+                "algorithmic_per_launch": f"{RHS_BYTES_PER_PT:.0f} B x {pr.npts} points"}
+    roof["mean_launch_ms"] = mean_ms
+    hbm_frac_step = value * 1e6 * STEP_BYTES_PER_PT_FORCED / (HBM_PEAK_GBS * 1e9)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Mpoint-RK-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == 0 else "f32-flux/f64-state",
+        "data": "synthetic",
+        "config": {"workload": "compressible channel 256x128x128, FP64 state, hybrid central/WENO "
+                               "(Ducros sensor), bulk forcing, tanh-stretched walls, CFL 0.8",
+                   "points": pr.npts, "parallelism": "single GPU"},
+        "hbm_frac_step_algorithmic": hbm_frac_step,
+        "phase_ms_per_step": per_step,
+        "weno_frac": d["weno_frac"],
+        "roofline": roof,
+    }
+    s.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pr)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -503,6 +503,66 @@ cdns_status cdns_export_iface_flux(cdns_ctx* c, int32_t dir, double* out_dev) {
   return CDNS_OK;
 }
 
+cdns_status cdns_time_phases(cdns_ctx* c, int32_t nsteps, double cfl, double dt_fixed,
+                             double* ms_out, int32_t* launches_out) {
+  if (!c) return CDNS_EINVAL;
+  if (nsteps < 1 || !ms_out) return fail(c, CDNS_EINVAL, "need nsteps >= 1 and an output array");
+  if (!(dt_fixed > 0.0) && !(cfl > 0.0)) return fail(c, CDNS_EINVAL, "need cfl > 0 or dt > 0");
+  cdns_status s = check_bcs(c);
+  if (s) return s;
+  Desc D = c->D;
+  D.cfl = cfl;
+  D.dt_fixed = dt_fixed > 0.0 ? dt_fixed : 0.0;
+  hipStream_t st = c->stream;
+  // every launch is bracketed by its own event pair; durations are summed per phase
+  struct Rec { int ph; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  hipError_t e = hipSuccess;
+  auto timed = [&](int ph, auto&& fn) {
+    if (e != hipSuccess) return;
+    Rec r{ph, nullptr, nullptr};
+    if ((e = hipEventCreate(&r.a)) != hipSuccess) return;
+    if ((e = hipEventCreate(&r.b)) != hipSuccess) { (void)hipEventDestroy(r.a); return; }
+    recs.push_back(r);
+    if ((e = hipEventRecord(r.a, st)) != hipSuccess) return;
+    if ((e = fn()) != hipSuccess) return;
+    e = hipEventRecord(r.b, st);
+  };
+  for (int step = 0; step < nsteps && e == hipSuccess; ++step) {
+    timed(CDNS_PH_DT, [&] { return cdns::launch_dt(D, st); });
+    for (int stage = 0; stage < 3; ++stage) {
+      if (D.sensor_mode > 0 && e == hipSuccess) e = cdns::launch_stage_begin(D, st);
+      if (!D.per_x || !D.per_y) timed(CDNS_PH_GHOSTS, [&] { return cdns::launch_ghosts(D, stage, st); });
+      if (D.sensor_mode == 1)
+        timed(CDNS_PH_SENSOR, [&] { return cdns::launch_sensor(D, stage, false, st); });
+      if (D.sensor_mode > 0) {
+        timed(CDNS_PH_IFLAGS, [&] { return cdns::launch_iflags(D, st); });
+        timed(CDNS_PH_WENO, [&] { return cdns::launch_weno(D, stage, st); });
+      }
+      timed(CDNS_PH_RHS, [&] { return cdns::launch_rhs(D, stage, st); });
+      if (D.forcing) timed(CDNS_PH_FORCE, [&] { return cdns::launch_force(D, st); });
+      timed(CDNS_PH_RK, [&] { return cdns::launch_rk(D, stage, st); });
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  double tot[CDNS_NPHASES] = {0};
+  int cnt[CDNS_NPHASES] = {0};
+  for (auto& r : recs) {
+    float ms = 0.0f;
+    if (e == hipSuccess && r.b) e = hipEventElapsedTime(&ms, r.a, r.b);
+    tot[r.ph] += ms;
+    cnt[r.ph] += 1;
+    (void)hipEventDestroy(r.a);
+    if (r.b) (void)hipEventDestroy(r.b);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "timed step");
+  for (int p = 0; p < CDNS_NPHASES; ++p) {
+    ms_out[p] = cnt[p] ? tot[p] / cnt[p] : 0.0;
+    if (launches_out) launches_out[p] = cnt[p];
+  }
+  return CDNS_OK;
+}
+
 const char* cdns_last_error(const cdns_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
 cdns_status cdns_destroy(cdns_ctx* c) {

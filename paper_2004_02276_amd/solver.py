@@ -133,6 +133,18 @@ class Solver:
                 "cdns_export_iface_flux")
         return out
 
+    def time_phases(self, nsteps: int, cfl: Optional[float] = None, dt_fixed: float = 0.0):
+        """Mean duration (ms) and count of one launch of each kernel phase over
+        nsteps eagerly launched steps, timed with HIP events on the stream."""
+        cfl = self.pr.cfl if cfl is None else cfl
+        n = len(B.PHASES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int32 * n)()
+        B.check(self.lib, self.ctx,
+                self.lib.cdns_time_phases(self.ctx, int(nsteps), float(cfl), float(dt_fixed), ms,
+                                          cnt), "cdns_time_phases")
+        return {B.PHASES[i]: (ms[i], cnt[i]) for i in range(n)}
+
     def close(self) -> None:
         if self.ctx:
             self.stream.synchronize()

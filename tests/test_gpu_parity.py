@@ -124,7 +124,7 @@ STEP_CASES = {
     "tgv32_10steps_cfl": (lambda: P.taylor_green(32), 10, False),
     "channel_24x20x12_100steps": (lambda: P.small_channel(24, 20, 12), 100, True),
     "sbli_64x32x8_100steps": (lambda: P.small_sbli(64, 32, 8), 100, True),
-    "dit24_hybrid_50steps": (lambda: P.decaying_turbulence(24, mach=1.5, re=800.0, seed=11), 50,
+    "dit24_hybrid_50steps": (lambda: P.decaying_turbulence(24, mach=0.5, re=800.0, seed=11), 50,
                              False),
 }
 
