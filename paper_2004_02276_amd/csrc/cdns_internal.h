@@ -87,14 +87,24 @@ hipError_t launch_diag(const Desc& D, hipStream_t st);
 bool rhs_tile_supported(int tx, int ty);
 int rhs_blocks(const Desc& D);
 
-// Batched launchers: one launch per phase over every instance in the device
-// array `descs` (n instances); `work` lists (instance, tile) items of the
-// fused right-hand-side kernel.
-struct WorkItem { int inst, tile; };
-hipError_t launch_batch_phase(int phase, const Desc* descs_dev, int ninst, int stage,
-                              const WorkItem* work, int nwork, int tile_x, int tile_y,
-                              int precision, int persistent_blocks, hipStream_t st);
-enum { PH_BEGIN = 0, PH_GHOST_X, PH_GHOST_Y, PH_SENSOR, PH_IFLAGS, PH_WENO, PH_RHS, PH_FORCE,
-       PH_RK, PH_DT_PART, PH_DT_FINAL, PH_COUNT };
+// ---------------------------------------------------------------- batching
+// Work table of a batch: the active instances (indices into the device
+// descriptor array) and, per phase kind, prefix sums of the number of work
+// items (blocks) of each active instance.  Persistent kernels walk the
+// flattened item range with a grid stride and locate the instance by a
+// search over the prefix sums, so membership changes rewrite this table only.
+constexpr int kMaxSlots = 64;
+enum { WK_PTS = 0, WK_RHS, WK_GX, WK_GY, WK_DT, WK_COUNT };
+struct BatchTable {
+  int ninst;
+  int inst[kMaxSlots];
+  int pre[WK_COUNT][kMaxSlots + 1];
+};
+enum { BPH_BEGIN = 0, BPH_DT_PART, BPH_DT_FINAL, BPH_GHOST_X, BPH_GHOST_Y, BPH_SENSOR, BPH_IFLAGS,
+       BPH_WENO, BPH_RHS, BPH_FORCE, BPH_RK };
+// Items of one instance per work kind (blocks of the single-instance kernels).
+int batch_items(const Desc& D, int kind);
+hipError_t launch_batch_phase(int phase, const Desc* descs_dev, const BatchTable* tab_dev,
+                              int stage, int tile_x, int tile_y, int precision, hipStream_t st);
 
 }  // namespace cdns

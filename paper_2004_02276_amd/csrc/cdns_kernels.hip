@@ -1205,4 +1205,184 @@ hipError_t launch_diag(const Desc& D, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ batched kernels
+// Persistent kernels over all attached instances.  Every instance is
+// processed with exactly the per-item arithmetic of its single-instance
+// kernels (same tiles, same reduction slots), so its results are the same
+// alone and in any mix.
+int batch_items(const Desc& D, int kind) {
+  switch (kind) {
+    case WK_PTS: return (int)nblk(D.N, 256);
+    case WK_RHS: return rhs_blocks(D);
+    case WK_GX: return D.per_x ? 0 : (int)nblk(2LL * D.ny * D.nz, 256);
+    case WK_GY: return D.per_y ? 0 : (int)nblk(2LL * D.nz * D.nxg, 256);
+    case WK_DT: {
+      int nb = (int)nblk(D.N, 256);
+      return nb > kRedBlocks ? kRedBlocks : nb;
+    }
+  }
+  return 0;
+}
+
+__device__ __forceinline__ int find_inst(const BatchTable* T, int kind, int b) {
+  int lo = 0, hi = T->ninst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (T->pre[kind][mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+#define BATCH_FOR(KIND)                                                  \
+  const int total_ = T->pre[KIND][T->ninst];                             \
+  for (int b_ = blockIdx.x; b_ < total_; b_ += gridDim.x) {              \
+    const int a_ = find_inst(T, KIND, b_);                               \
+    const Desc& D = descs[T->inst[a_]];                                  \
+    const int local = b_ - T->pre[KIND][a_];                             \
+    const int litems = T->pre[KIND][a_ + 1] - T->pre[KIND][a_];          \
+    (void)litems;
+#define BATCH_END }
+
+__global__ void k_b_begin(const Desc* __restrict__ descs, const BatchTable* __restrict__ T) {
+  for (int a = threadIdx.x; a < T->ninst; a += blockDim.x) {
+    unsigned* c = descs[T->inst[a]].count;
+    c[0] = c[1] = c[2] = c[3] = 0u;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_b_dt_part(const Desc* __restrict__ descs,
+                                                   const BatchTable* __restrict__ T) {
+  __shared__ double sm[4];
+  BATCH_FOR(WK_DT)
+  if (!(D.dt_fixed > 0.0)) dt_part_body(D, local, litems, sm);
+  BATCH_END
+}
+
+__global__ void __launch_bounds__(256) k_b_dt_final(const Desc* __restrict__ descs,
+                                                    const BatchTable* __restrict__ T) {
+  __shared__ double sm[4];
+  for (int a = blockIdx.x; a < T->ninst; a += gridDim.x) {
+    const Desc& D = descs[T->inst[a]];
+    dt_final_body(D, T->pre[WK_DT][a + 1] - T->pre[WK_DT][a], sm);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_b_ghost_x(const Desc* __restrict__ descs,
+                                                   const BatchTable* __restrict__ T, int stage) {
+  BATCH_FOR(WK_GX)
+  const long long t = (long long)local * 256 + threadIdx.x;
+  if (t < 2LL * D.ny * D.nz) ghost_x_body(D, D.win[stage], t);
+  BATCH_END
+}
+
+__global__ void __launch_bounds__(256) k_b_ghost_y(const Desc* __restrict__ descs,
+                                                   const BatchTable* __restrict__ T, int stage) {
+  BATCH_FOR(WK_GY)
+  const long long t = (long long)local * 256 + threadIdx.x;
+  if (t < 2LL * D.nz * D.nxg) ghost_y_body(D, D.win[stage], t);
+  BATCH_END
+}
+
+__global__ void __launch_bounds__(256) k_b_sensor(const Desc* __restrict__ descs,
+                                                  const BatchTable* __restrict__ T, int stage) {
+  BATCH_FOR(WK_PTS)
+  if (D.sensor_mode == 1) {
+    const long long n = (long long)local * 256 + threadIdx.x;
+    if (n < D.N) sensor_body(D, D.win[stage], n, false);
+  }
+  BATCH_END
+}
+
+__global__ void __launch_bounds__(256) k_b_iflags(const Desc* __restrict__ descs,
+                                                  const BatchTable* __restrict__ T) {
+  BATCH_FOR(WK_PTS)
+  if (D.sensor_mode > 0) {
+    const long long n = (long long)local * 256 + threadIdx.x;
+    iflags_body(D, n, n < D.N);
+  }
+  BATCH_END
+}
+
+template <typename F>
+__global__ void __launch_bounds__(256) k_b_weno(const Desc* __restrict__ descs,
+                                                const BatchTable* __restrict__ T, int stage) {
+  for (int a = 0; a < T->ninst; ++a) {
+    const Desc& D = descs[T->inst[a]];
+    if (D.sensor_mode == 0) continue;
+    const double* w = D.win[stage];
+    for (int dir = 0; dir < 3; ++dir) {
+      const unsigned cnt = D.count[dir];
+      for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x) {
+        const int n = D.list[dir][e];
+        if (dir == 0) weno_entry<F, 0>(D, w, n);
+        else if (dir == 1) weno_entry<F, 1>(D, w, n);
+        else weno_entry<F, 2>(D, w, n);
+      }
+    }
+  }
+}
+
+template <typename F, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY) k_b_rhs(const Desc* __restrict__ descs,
+                                                  const BatchTable* __restrict__ T, int stage) {
+  __shared__ RhsSmem<F, TX, TY> S;
+  BATCH_FOR(WK_RHS)
+  rhs_body<F, TX, TY>(D, stage, local, S);
+  BATCH_END
+}
+
+__global__ void __launch_bounds__(256) k_b_force(const Desc* __restrict__ descs,
+                                                 const BatchTable* __restrict__ T) {
+  __shared__ double sm[4];
+  for (int a = blockIdx.x; a < T->ninst; a += gridDim.x) {
+    const Desc& D = descs[T->inst[a]];
+    if (D.forcing) force_body(D, sm);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_b_rk(const Desc* __restrict__ descs,
+                                              const BatchTable* __restrict__ T, int stage) {
+  BATCH_FOR(WK_PTS)
+  const long long n = (long long)local * 256 + threadIdx.x;
+  if (n < D.N) rk_point(D, stage, n);
+  BATCH_END
+}
+
+template <typename F>
+static hipError_t launch_b_rhs(const Desc* d, const BatchTable* t, int stage, int tx, int ty,
+                               hipStream_t st) {
+  const unsigned g = 1024;
+  if (tx == 64 && ty == 4) k_b_rhs<F, 64, 4><<<g, 256, 0, st>>>(d, t, stage);
+  else if (tx == 32 && ty == 8) k_b_rhs<F, 32, 8><<<g, 256, 0, st>>>(d, t, stage);
+  else if (tx == 64 && ty == 2) k_b_rhs<F, 64, 2><<<g, 128, 0, st>>>(d, t, stage);
+  else if (tx == 128 && ty == 2) k_b_rhs<F, 128, 2><<<g, 256, 0, st>>>(d, t, stage);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_phase(int phase, const Desc* d, const BatchTable* t, int stage, int tx,
+                              int ty, int precision, hipStream_t st) {
+  switch (phase) {
+    case BPH_BEGIN: k_b_begin<<<1, 64, 0, st>>>(d, t); break;
+    case BPH_DT_PART: k_b_dt_part<<<2048, 256, 0, st>>>(d, t); break;
+    case BPH_DT_FINAL: k_b_dt_final<<<kMaxSlots, 256, 0, st>>>(d, t); break;
+    case BPH_GHOST_X: k_b_ghost_x<<<512, 256, 0, st>>>(d, t, stage); break;
+    case BPH_GHOST_Y: k_b_ghost_y<<<512, 256, 0, st>>>(d, t, stage); break;
+    case BPH_SENSOR: k_b_sensor<<<4096, 256, 0, st>>>(d, t, stage); break;
+    case BPH_IFLAGS: k_b_iflags<<<4096, 256, 0, st>>>(d, t); break;
+    case BPH_WENO:
+      if (precision == 1) k_b_weno<float><<<2048, 256, 0, st>>>(d, t, stage);
+      else k_b_weno<double><<<2048, 256, 0, st>>>(d, t, stage);
+      break;
+    case BPH_RHS:
+      return precision == 1 ? launch_b_rhs<float>(d, t, stage, tx, ty, st)
+                            : launch_b_rhs<double>(d, t, stage, tx, ty, st);
+    case BPH_FORCE: k_b_force<<<kMaxSlots, 256, 0, st>>>(d, t); break;
+    case BPH_RK: k_b_rk<<<4096, 256, 0, st>>>(d, t, stage); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace cdns

@@ -510,3 +510,66 @@ def small_channel(nx=24, ny=20, nz=12, **kw) -> Problem:
 def small_sbli(nx=64, ny=32, nz=8, **kw) -> Problem:
     """The shock/boundary-layer box at a size the oracle finishes in seconds."""
     return sbli(nx, ny, nz, **kw)
+
+
+# ------------------------------------------------------------ serving requests
+def convected_turbulence(n: int, mach: float, re: float, seed: int, turb_mach: float = 0.3,
+                         sensor_mode: int = SENSOR_HYBRID, nsteps: int = 200) -> Problem:
+    """Periodic decaying turbulence carried by a uniform stream.
+
+    The stream has unit velocity along x and Mach number `mach` (sound
+    speed 1/mach at T = 1); the solenoidal fluctuation field of
+    `decaying_turbulence` is scaled to u_rms = turb_mach times the sound
+    speed; density and pressure are uniform; Re = 1/mu_ref."""
+    base = decaying_turbulence(n, mach=1.0, re=re, seed=seed, sensor_mode=sensor_mode,
+                               nsteps=nsteps)
+    g = 1.4
+    R = 1.0 / (g * mach * mach)
+    c0 = 1.0 / mach
+    rho = base.w0[0]
+    u, v, w = (base.w0[1] / rho, base.w0[2] / rho, base.w0[3] / rho)
+    s = turb_mach * c0
+    w0 = conserved_from_primitive(rho, 1.0 + s * u, s * v, s * w, np.full_like(rho, R), g)
+    return dataclasses.replace(base, name=f"cturb{n}", R_gas=R, mu_ref=1.0 / re, w0=w0)
+
+
+@dataclasses.dataclass
+class RequestSpec:
+    rid: int
+    arrival: float      # seconds after the start of the trace
+    kind: str           # "turbulence" or "channel"
+    n: int              # cubic grid n^3
+    mach: float
+    re: float
+    seed: int
+    nsteps: int = 200
+
+
+def serving_trace(n_requests: int = 64, rate: float = 4.0, nmin: int = 32, nmax: int = 192,
+                  mach_range=(0.1, 3.0), re_range=(500.0, 5000.0), nsteps: int = 200,
+                  seed_index: int = 4, burst: bool = False) -> List[RequestSpec]:
+    """Poisson arrivals (exponential gaps of mean 1/rate; all at t = 0 when
+    burst), kind uniform over {turbulence, channel}, n uniform in
+    [nmin, nmax] (even), Mach and Re uniform in their ranges."""
+    rng = _rng(seed_index)
+    t = 0.0
+    out = []
+    for r in range(n_requests):
+        if not burst:
+            t += float(rng.exponential(1.0 / rate))
+        kind = "turbulence" if rng.uniform() < 0.5 else "channel"
+        n = int(rng.integers(nmin // 2, nmax // 2 + 1)) * 2
+        mach = float(rng.uniform(*mach_range))
+        re = float(rng.uniform(*re_range))
+        out.append(RequestSpec(r, 0.0 if burst else t, kind, n, mach, re,
+                               BASE_SEED + 100 + r, nsteps))
+    return out
+
+
+def request_problem(spec: RequestSpec) -> Problem:
+    """Initial field and parameters of one serving request."""
+    if spec.kind == "turbulence":
+        return convected_turbulence(spec.n, spec.mach, spec.re, spec.seed, nsteps=spec.nsteps)
+    pr = channel(spec.n, spec.n, spec.n, mach_b=spec.mach, re_b=spec.re,
+                 seed_index=spec.seed - BASE_SEED, nsteps=spec.nsteps)
+    return dataclasses.replace(pr, name=f"chan{spec.n}")

