@@ -717,112 +717,129 @@ __device__ void rhs_body(const Desc& D, int stage, int lb, RhsSmem<F, TX, TY>& S
       }
     }
     if (c >= kb && c < ke && valid) {
-      PV<F> cN[5];  // x-neighbours i-2..i+2
-      PV<F> cM[5];  // y-neighbours j-2..j+2
-#pragma unroll
-      for (int o = 0; o < 5; ++o) {
-        lds_prim<F, TX, TY>(S, ly, lx - 2 + o, cN[o]);
-        lds_prim<F, TX, TY>(S, ly - 2 + o, lx, cM[o]);
-      }
-      F fxr[5], fxl[5], fyr[5], fyl[5];
-      cflux<F, 0>(cN[1], cN[2], cN[3], cN[4], fxr);
-      cflux<F, 0>(cN[0], cN[1], cN[2], cN[3], fxl);
-      if (wall_hi) wflux<F, 1>(cM[1], cM[2], cM[3], cM[4], fyr);
-      else cflux<F, 1>(cM[1], cM[2], cM[3], cM[4], fyr);
-      if (wall_lo) wflux<F, 1>(cM[0], cM[1], cM[2], cM[3], fyl);
-      else cflux<F, 1>(cM[0], cM[1], cM[2], cM[3], fyl);
-      if (hybrid) {
-        const size_t n0 = nidx(D, i, j, c);
-        const uint8_t f0 = D.iflag[n0];
-        if (f0 & 1) {
-#pragma unroll
-          for (int m = 0; m < 5; ++m) fxr[m] = (F)D.Fw[0][(size_t)m * N + n0];
-        }
-        if (f0 & 2) {
-#pragma unroll
-          for (int m = 0; m < 5; ++m) fyr[m] = (F)D.Fw[1][(size_t)m * N + n0];
-        }
-        if (i > 0 || D.per_x) {
-          const size_t nl = nidx(D, i > 0 ? i - 1 : D.nx - 1, j, c);
-          if (D.iflag[nl] & 1) {
-#pragma unroll
-            for (int m = 0; m < 5; ++m) fxl[m] = (F)D.Fw[0][(size_t)m * N + nl];
-          }
-        }
-        if (j > 0 || D.per_y) {
-          const size_t nl = nidx(D, i, j > 0 ? j - 1 : D.ny - 1, c);
-          if (D.iflag[nl] & 2) {
-#pragma unroll
-            for (int m = 0; m < 5; ++m) fyl[m] = (F)D.Fw[1][(size_t)m * N + nl];
-          }
-        }
-      }
       const double didx = D.idx, diy = D.iy[j], didz = D.idz;
+      double acc[5];
+      size_t n0 = 0;
+      uint8_t f0 = 0;
+      if (hybrid) {
+        n0 = nidx(D, i, j, c);
+        f0 = D.iflag[n0];
+      }
+      // x direction: interfaces i-1/2, i+1/2 from the LDS row
+      {
+        F fr[5], fl[5];
+        PV<F> a, b, cc, d, e;
+        lds_prim<F, TX, TY>(S, ly, lx - 2, a);
+        lds_prim<F, TX, TY>(S, ly, lx - 1, b);
+        lds_prim<F, TX, TY>(S, ly, lx, cc);
+        lds_prim<F, TX, TY>(S, ly, lx + 1, d);
+        lds_prim<F, TX, TY>(S, ly, lx + 2, e);
+        cflux<F, 0>(b, cc, d, e, fr);
+        cflux<F, 0>(a, b, cc, d, fl);
+        if (hybrid) {
+          if (f0 & 1) {
+#pragma unroll
+            for (int m = 0; m < 5; ++m) fr[m] = (F)D.Fw[0][(size_t)m * N + n0];
+          }
+          if (i > 0 || D.per_x) {
+            const size_t nl = nidx(D, i > 0 ? i - 1 : D.nx - 1, j, c);
+            if (D.iflag[nl] & 1) {
+#pragma unroll
+              for (int m = 0; m < 5; ++m) fl[m] = (F)D.Fw[0][(size_t)m * N + nl];
+            }
+          }
+        }
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+#pragma clang fp contract(off)
+          acc[m] = 0.0 - (double)(fr[m] - fl[m]) * didx;
+        }
+      }
+      // y direction (stretched): interfaces j-1/2, j+1/2 from the LDS column
+      {
+        F fr[5], fl[5];
+        PV<F> a, b, cc, d, e;
+        lds_prim<F, TX, TY>(S, ly - 2, lx, a);
+        lds_prim<F, TX, TY>(S, ly - 1, lx, b);
+        lds_prim<F, TX, TY>(S, ly, lx, cc);
+        lds_prim<F, TX, TY>(S, ly + 1, lx, d);
+        lds_prim<F, TX, TY>(S, ly + 2, lx, e);
+        if (wall_hi) wflux<F, 1>(b, cc, d, e, fr);
+        else cflux<F, 1>(b, cc, d, e, fr);
+        if (wall_lo) wflux<F, 1>(a, b, cc, d, fl);
+        else cflux<F, 1>(a, b, cc, d, fl);
+        if (hybrid) {
+          if (f0 & 2) {
+#pragma unroll
+            for (int m = 0; m < 5; ++m) fr[m] = (F)D.Fw[1][(size_t)m * N + n0];
+          }
+          if (j > 0 || D.per_y) {
+            const size_t nl = nidx(D, i, j > 0 ? j - 1 : D.ny - 1, c);
+            if (D.iflag[nl] & 2) {
+#pragma unroll
+              for (int m = 0; m < 5; ++m) fl[m] = (F)D.Fw[1][(size_t)m * N + nl];
+            }
+          }
+        }
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+#pragma clang fp contract(off)
+          acc[m] = acc[m] - (double)(fr[m] - fl[m]) * diy;
+        }
+      }
+      // z direction from the register window (flux at c+1/2 computed above)
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
-        // flux difference times the inverse spacing, x then y then z (eq. num_flux)
 #pragma clang fp contract(off)
-        double acc = 0.0 - (double)(fxr[m] - fxl[m]) * didx;
-        acc = acc - (double)(fyr[m] - fyl[m]) * diy;
-        Ra0[m] = acc - (double)(Fzp[m] - Fzm[m]) * didz;
+        Ra0[m] = acc[m] - (double)(Fzp[m] - Fzm[m]) * didz;
       }
       if (visc) {
         const PV<F>& o = win[2];
-        // first derivatives
-        const F ux = d1c<F>(cN[0].u, cN[1].u, cN[3].u, cN[4].u, idx);
-        const F vx = d1c<F>(cN[0].v, cN[1].v, cN[3].v, cN[4].v, idx);
-        const F wx = d1c<F>(cN[0].w, cN[1].w, cN[3].w, cN[4].w, idx);
-        const F Tx = d1c<F>(cN[0].t, cN[1].t, cN[3].t, cN[4].t, idx);
-        const F mx = d1c<F>(cN[0].mu, cN[1].mu, cN[3].mu, cN[4].mu, idx);
-        const F uy = d1c<F>(cM[0].u, cM[1].u, cM[3].u, cM[4].u, iy);
-        const F vy = d1c<F>(cM[0].v, cM[1].v, cM[3].v, cM[4].v, iy);
-        const F wy = d1c<F>(cM[0].w, cM[1].w, cM[3].w, cM[4].w, iy);
-        const F Ty = d1c<F>(cM[0].t, cM[1].t, cM[3].t, cM[4].t, iy);
-        const F my = d1c<F>(cM[0].mu, cM[1].mu, cM[3].mu, cM[4].mu, iy);
-        const F uz = d1c<F>(win[0].u, win[1].u, win[3].u, win[4].u, idz);
-        const F vz = d1c<F>(win[0].v, win[1].v, win[3].v, win[4].v, idz);
-        const F wz = d1c<F>(win[0].w, win[1].w, win[3].w, win[4].w, idz);
-        const F Tz = d1c<F>(win[0].t, win[1].t, win[3].t, win[4].t, idz);
-        const F mz = d1c<F>(win[0].mu, win[1].mu, win[3].mu, win[4].mu, idz);
-        // second derivatives
-        const F uxx = d2c<F>(cN[0].u, cN[1].u, o.u, cN[3].u, cN[4].u, idx2);
-        const F vxx = d2c<F>(cN[0].v, cN[1].v, o.v, cN[3].v, cN[4].v, idx2);
-        const F wxx = d2c<F>(cN[0].w, cN[1].w, o.w, cN[3].w, cN[4].w, idx2);
-        const F Txx = d2c<F>(cN[0].t, cN[1].t, o.t, cN[3].t, cN[4].t, idx2);
-        const F uyy = (d2c<F>(cM[0].u, cM[1].u, o.u, cM[3].u, cM[4].u, ideta2) - yee * uy) * iye2;
-        const F vyy = (d2c<F>(cM[0].v, cM[1].v, o.v, cM[3].v, cM[4].v, ideta2) - yee * vy) * iye2;
-        const F wyy = (d2c<F>(cM[0].w, cM[1].w, o.w, cM[3].w, cM[4].w, ideta2) - yee * wy) * iye2;
-        const F Tyy = (d2c<F>(cM[0].t, cM[1].t, o.t, cM[3].t, cM[4].t, ideta2) - yee * Ty) * iye2;
-        const F uzz = d2c<F>(win[0].u, win[1].u, o.u, win[3].u, win[4].u, idz2);
-        const F vzz = d2c<F>(win[0].v, win[1].v, o.v, win[3].v, win[4].v, idz2);
-        const F wzz = d2c<F>(win[0].w, win[1].w, o.w, win[3].w, win[4].w, idz2);
-        const F Tzz = d2c<F>(win[0].t, win[1].t, o.t, win[3].t, win[4].t, idz2);
-        // in-plane mixed derivatives: d_y (d_x f) with the metric at j
-        F uxr[5], vxr[5];
-#pragma unroll
-        for (int dy = -2; dy <= 2; ++dy) {
-          if (dy == 0) { uxr[2] = ux; vxr[2] = vx; continue; }
-          uxr[dy + 2] = d1c<F>(S.q[QU][ly + dy][lx - 2], S.q[QU][ly + dy][lx - 1],
-                               S.q[QU][ly + dy][lx + 1], S.q[QU][ly + dy][lx + 2], idx);
-          vxr[dy + 2] = d1c<F>(S.q[QV][ly + dy][lx - 2], S.q[QV][ly + dy][lx - 1],
-                               S.q[QV][ly + dy][lx + 1], S.q[QV][ly + dy][lx + 2], idx);
-        }
-        const F uxy = d1c<F>(uxr[0], uxr[1], uxr[3], uxr[4], iy);
-        const F vxy = d1c<F>(vxr[0], vxr[1], vxr[3], vxr[4], iy);
-        const F mu = o.mu;
+#define SQ(qq, dy, dx) S.q[qq][ly + (dy)][lx + (dx)]
+#define DX1(q) d1c<F>(SQ(q, 0, -2), SQ(q, 0, -1), SQ(q, 0, 1), SQ(q, 0, 2), idx)
+#define DY1(q) d1c<F>(SQ(q, -2, 0), SQ(q, -1, 0), SQ(q, 1, 0), SQ(q, 2, 0), iy)
+#define DX2(q, ctr) d2c<F>(SQ(q, 0, -2), SQ(q, 0, -1), ctr, SQ(q, 0, 1), SQ(q, 0, 2), idx2)
+#define DY2(q, ctr, dy1) \
+  ((d2c<F>(SQ(q, -2, 0), SQ(q, -1, 0), ctr, SQ(q, 1, 0), SQ(q, 2, 0), ideta2) - yee * (dy1)) * iye2)
+#define DZ1(fld) d1c<F>(win[0].fld, win[1].fld, win[3].fld, win[4].fld, idz)
+#define DZ2(fld) d2c<F>(win[0].fld, win[1].fld, o.fld, win[3].fld, win[4].fld, idz2)
+        // velocity gradient
+        const F ux = DX1(QU), uy = DY1(QU), uz = DZ1(u);
+        const F vx = DX1(QV), vy = DY1(QV), vz = DZ1(v);
+        const F wx = DX1(QW), wy = DY1(QW), wz = DZ1(w);
         const F div = ux + vy + wz;
+        const F mx = DX1(QM), my = DY1(QM), mz = DZ1(mu);
+        const F mu = o.mu;
         const F third = F(1.0 / 3.0), twoth = F(2.0 / 3.0);
-        // everything except the z-mixed parts (added two planes later)
-        const F Fx = mu * (uxx + uyy + uzz + third * (uxx + vxy)) + mx * (ux + ux) +
+        // in-plane mixed derivatives d_y(d_x f), metric of the outer (y) operator
+        auto dxrow = [&](int q, int dy) {
+          return d1c<F>(S.q[q][ly + dy][lx - 2], S.q[q][ly + dy][lx - 1], S.q[q][ly + dy][lx + 1],
+                        S.q[q][ly + dy][lx + 2], idx);
+        };
+        const F uxy = d1c<F>(dxrow(QU, -2), dxrow(QU, -1), dxrow(QU, 1), dxrow(QU, 2), iy);
+        const F vxy = d1c<F>(dxrow(QV, -2), dxrow(QV, -1), dxrow(QV, 1), dxrow(QV, 2), iy);
+        const F uxx = DX2(QU, o.u);
+        const F vyy = DY2(QV, o.v, vy);
+        const F wzz = DZ2(w);
+        const F Fx = mu * (uxx + DY2(QU, o.u, uy) + DZ2(u) + third * (uxx + vxy)) + mx * (ux + ux) +
                      my * (uy + vx) + mz * (uz + wx) - twoth * mx * div;
-        const F Fy = mu * (vxx + vyy + vzz + third * (uxy + vyy)) + mx * (vx + uy) +
+        const F Fy = mu * (DX2(QV, o.v) + vyy + DZ2(v) + third * (uxy + vyy)) + mx * (vx + uy) +
                      my * (vy + vy) + mz * (vz + wy) - twoth * my * div;
-        const F Fz = mu * (wxx + wyy + wzz + third * wzz) + mx * (wx + uz) + my * (wy + vz) +
-                     mz * (wz + wz) - twoth * mz * div;
+        const F Fz = mu * (DX2(QW, o.w) + DY2(QW, o.w, wy) + wzz + third * wzz) + mx * (wx + uz) +
+                     my * (wy + vz) + mz * (wz + wz) - twoth * mz * div;
         const F sxy = uy + vx, sxz = uz + wx, syz = vz + wy;
-        const F phi = mu * (F(2) * (ux * ux + vy * vy + wz * wz) + sxy * sxy + sxz * sxz + syz * syz -
-                            twoth * div * div);
-        const F heat = kfac * (mu * (Txx + Tyy + Tzz) + mx * Tx + my * Ty + mz * Tz);
+        const F phi = mu * (F(2) * (ux * ux + vy * vy + wz * wz) + sxy * sxy + sxz * sxz +
+                            syz * syz - twoth * div * div);
+        const F Ty = DY1(QT);
+        const F heat = kfac * (mu * (DX2(QT, o.t) + DY2(QT, o.t, Ty) + DZ2(t)) + mx * DX1(QT) +
+                               my * Ty + mz * DZ1(t));
+#undef SQ
+#undef DX1
+#undef DY1
+#undef DX2
+#undef DY2
+#undef DZ1
+#undef DZ2
         Ra0[1] += (double)Fx;
         Ra0[2] += (double)Fy;
         Ra0[3] += (double)Fz;
