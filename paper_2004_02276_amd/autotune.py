@@ -1,0 +1,98 @@
+"""Tile-shape autotuner for the fused right-hand-side kernel.
+
+For a problem (or a size class of problems) it times every compiled tile
+shape (tile_x, tile_y) and a set of z-chunk depths kz with HIP events
+(`cdns_time_phases`, mean duration of one right-hand-side launch) and keeps
+the fastest.  Results are cached in a JSON table keyed by device name,
+precision and size class, so the serving loop and the benchmark reuse them.
+Tile shape never changes results beyond the rounding of the forcing sum.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, Optional, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tuning.json")
+
+TILES = [(64, 4), (32, 8), (64, 2), (128, 2)]
+KZS = [4, 8, 16, 32]
+
+
+def size_class(pr) -> str:
+    """Bucket by point count (powers of two) and aspect (nx >= 64 or not)."""
+    n = pr.nx * pr.ny * pr.nz
+    b = max(0, int(n).bit_length() - 1)
+    return f"2^{b}-{'wide' if pr.nx >= 64 else 'narrow'}"
+
+
+def _key(device: str, precision: int, cls: str) -> str:
+    return f"{device}|{'fp64' if precision == 0 else 'fp32flux'}|{cls}"
+
+
+def load_cache() -> Dict:
+    try:
+        with open(CACHE) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(tab: Dict) -> None:
+    tmp = CACHE + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(tab, fh, indent=1, sort_keys=True)
+    os.replace(tmp, CACHE)
+
+
+def tune(pr, precision: int = 0, steps: int = 2, tiles=TILES, kzs=KZS,
+         fixed_tile: Optional[Tuple[int, int]] = None, verbose: bool = False) -> Dict:
+    """Time every (tile, kz) on `pr`; return {"tile": (tx, ty), "kz": kz, "ms": t, "all": {...}}."""
+    import torch
+
+    from .solver import Solver
+
+    dev = torch.cuda.get_device_name(0)
+    results = {}
+    cand_tiles = [fixed_tile] if fixed_tile else tiles
+    for (tx, ty) in cand_tiles:
+        for kz in kzs:
+            if kz > pr.nz:
+                continue
+            s = Solver(pr, precision=precision, tiling=(tx, ty, kz))
+            ph = s.time_phases(steps, cfl=pr.cfl)
+            s.close()
+            results[f"{tx}x{ty}/kz{kz}"] = ph["rhs"][0]
+            if verbose:
+                print(f"  tile {tx}x{ty} kz {kz}: rhs {ph['rhs'][0]:.4f} ms", flush=True)
+    best = min(results, key=results.get)
+    t, kz = best.split("/kz")
+    tx, ty = (int(v) for v in t.split("x"))
+    out = {"tile": [tx, ty], "kz": int(kz), "ms": results[best], "all": results, "device": dev}
+    tab = load_cache()
+    tab[_key(dev, precision, size_class(pr))] = out
+    save_cache(tab)
+    return out
+
+
+def lookup(pr, precision: int = 0, device: Optional[str] = None,
+           fixed_tile: Optional[Tuple[int, int]] = None) -> Tuple[int, int, int]:
+    """Tiling for `pr` from the cache (nearest size class of the same device),
+    else the library default shape with a kz giving at least ~1000 blocks."""
+    tab = load_cache()
+    if device is None:
+        try:
+            import torch
+            device = torch.cuda.get_device_name(0)
+        except Exception:
+            device = ""
+    ent = tab.get(_key(device, precision, size_class(pr)))
+    if ent and (fixed_tile is None or tuple(ent["tile"]) == tuple(fixed_tile)):
+        return ent["tile"][0], ent["tile"][1], ent["kz"]
+    tx, ty = fixed_tile or (64, 4)
+    tiles = -(-pr.nx // tx) * -(-pr.ny // ty)
+    kz = 16
+    while kz > 4 and tiles * -(-pr.nz // kz) < 1024:
+        kz //= 2
+    return tx, ty, kz

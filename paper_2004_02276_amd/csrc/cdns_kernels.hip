@@ -566,7 +566,9 @@ enum { QR = 0, QU, QV, QW, QP, QH, QT, QM, NQ };
 
 template <typename F, int TX, int TY>
 struct RhsSmem {
-  F q[NQ][TY + 4][TX + 4];
+  F q[NQ][TY + 4][TX + 4];             // current plane with a 2-node halo
+  F zr[4][3][TX * TY];                 // per-thread ring of (rho, p, H) of planes c-1..c+2
+  double pend[2][5][TX * TY];          // per-thread residuals awaiting their z-mixed terms
   double red[TX * TY / 64];
 };
 
@@ -625,15 +627,17 @@ __device__ void rhs_body(const Desc& D, int stage, int lb, RhsSmem<F, TX, TY>& S
 
   // own-column register window, slots 0..4 = planes c-2..c+2
   PV<F> win[5];
+  // (rho, p, H) of the column live in the LDS ring S.zr; the other fields
+  // of the window stay in registers.
   // deferred mixed-derivative windows (planes c-4..c)
   F Sw[5], Tw[5], Qw[5];
-  double Ra2[5], Ra1[5], Ra0[5];
+  double Ra0[5];
   F Fzm[5];
 #pragma unroll
   for (int s = 0; s < 5; ++s) {
     win[s] = PV<F>{F(0), F(0), F(0), F(0), F(0), F(0), F(0), F(0)};
     Sw[s] = Tw[s] = Qw[s] = F(0);
-    Ra2[s] = Ra1[s] = Ra0[s] = 0.0;
+    Ra0[s] = 0.0;
     Fzm[s] = F(0);
   }
   double fsum = 0.0;
@@ -648,6 +652,19 @@ __device__ void rhs_body(const Desc& D, int stage, int lb, RhsSmem<F, TX, TY>& S
       load_node(D, w, i, j, plane, q);
     }
     to_prim<F>(D, q, s);
+    const int slot = plane & 3;
+    S.zr[slot][0][tid] = s.r;
+    S.zr[slot][1][tid] = s.p;
+    S.zr[slot][2][tid] = s.h;
+  };
+  // window slot with (rho, p, H) restored from the ring
+  auto full = [&](int ws, int plane) {
+    PV<F> s = win[ws];
+    const int slot = plane & 3;
+    s.r = S.zr[slot][0][tid];
+    s.p = S.zr[slot][1][tid];
+    s.h = S.zr[slot][2][tid];
+    return s;
   };
 
   load_col(kb - 2, win[3]);
@@ -658,7 +675,7 @@ __device__ void rhs_body(const Desc& D, int stage, int lb, RhsSmem<F, TX, TY>& S
     for (int s = 0; s < 4; ++s) win[s] = win[s + 1];
     load_col(c + 2, win[4]);
     // stage plane c into LDS: interior from the window, halo cooperatively
-    lds_store<F, TX, TY>(S, ty + 2, tx + 2, win[2]);
+    lds_store<F, TX, TY>(S, ty + 2, tx + 2, full(2, c));
     {
       const int kk = wrapi(c, D.nz);
       for (int h = tid; h < NH; h += NT) {
@@ -713,7 +730,7 @@ __device__ void rhs_body(const Desc& D, int stage, int lb, RhsSmem<F, TX, TY>& S
 #pragma unroll
         for (int m = 0; m < 5; ++m) Fzp[m] = (F)D.Fw[2][(size_t)m * N + nc];
       } else {
-        cflux<F, 2>(win[1], win[2], win[3], win[4], Fzp);
+        cflux<F, 2>(full(1, c - 1), full(2, c), full(3, c + 1), full(4, c + 2), Fzp);
       }
     }
     if (c >= kb && c < ke && valid) {
@@ -851,8 +868,14 @@ __device__ void rhs_body(const Desc& D, int stage, int lb, RhsSmem<F, TX, TY>& S
       for (int m = 0; m < 5; ++m) Fzm[m] = Fzp[m];
     }
     // finish plane c-2: z-mixed viscous parts, store, forcing partial sum
+    // (plane c-2 and plane c share the slot c & 1 of the pending ring: the
+    // older one is read before the newer one is written)
+    const int pslot = c & 1;
     if (c >= kb + 2 && valid) {
       const int m2 = c - 2;
+      double Ra2[5];
+#pragma unroll
+      for (int m = 0; m < 5; ++m) Ra2[m] = S.pend[pslot][m][tid];
       if (visc) {
         const F dS = d1c<F>(Sw[0], Sw[1], Sw[3], Sw[4], idz);  // d_x d_z w
         const F dT = d1c<F>(Tw[0], Tw[1], Tw[3], Tw[4], idz);  // d_y d_z w
@@ -870,8 +893,10 @@ __device__ void rhs_body(const Desc& D, int stage, int lb, RhsSmem<F, TX, TY>& S
       for (int m = 0; m < 5; ++m) R[(size_t)m * N + no] = Ra2[m];
       fsum += Ra2[1] * D.y_eta[j];
     }
+    if (c >= kb && c < ke && valid) {
 #pragma unroll
-    for (int m = 0; m < 5; ++m) { Ra2[m] = Ra1[m]; Ra1[m] = Ra0[m]; Ra0[m] = 0.0; }
+      for (int m = 0; m < 5; ++m) S.pend[pslot][m][tid] = Ra0[m];
+    }
     __syncthreads();
   }
   // block partial sum of R_rhou dV (fixed order)
