@@ -31,6 +31,12 @@ namespace cdns {
 #define CB1 (4.0 / 3.0)
 #define CB2 (-1.0 / 12.0)
 
+// consecutive logical tiles land on the same XCD (blocks are dealt
+// round-robin over the 8 XCDs), so neighbouring tiles share an L2
+__device__ __forceinline__ int xcd_swizzle_blk(int b, int nb) {
+  return (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+}
+
 __device__ __forceinline__ int wrapi(int i, int n) {
   i %= n;
   return i < 0 ? i + n : i;
@@ -216,9 +222,12 @@ __device__ __forceinline__ F weno5(F vm2, F vm1, F v0, F vp1, F vp2) {
   const F s0 = eps + F(13.0 / 12.0) * d0 * d0 + F(0.25) * e0 * e0;
   const F s1 = eps + F(13.0 / 12.0) * d1 * d1 + F(0.25) * e1 * e1;
   const F s2 = eps + F(13.0 / 12.0) * d2 * d2 + F(0.25) * e2 * e2;
-  const F a0 = F(0.1) / (s0 * s0);
-  const F a1 = F(0.6) / (s1 * s1);
-  const F a2 = F(0.3) / (s2 * s2);
+  // weights d_k/(eps+beta_k)^2 normalised, with numerator and denominator
+  // multiplied by the product of the three squares: one division
+  const F t0 = s0 * s0, t1 = s1 * s1, t2 = s2 * s2;
+  const F a0 = F(0.1) * (t1 * t2);
+  const F a1 = F(0.6) * (t0 * t2);
+  const F a2 = F(0.3) * (t0 * t1);
   return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
 }
 
@@ -319,7 +328,7 @@ __device__ __forceinline__ void from_prim(const Desc& D, double r, double u, dou
   q[4] = p / D.gm1 + 0.5 * r * (u * u + v * v + w * w);
 }
 
-__device__ void ghost_x_body(const Desc& D, const double* __restrict__ w, long long t) {
+__device__ __forceinline__ void ghost_x_body(const Desc& D, const double* __restrict__ w, long long t) {
   // t over 2 * ny * nz (side, k, j)
   const long long per_side = (long long)D.ny * D.nz;
   const int side = (int)(t / per_side);
@@ -380,7 +389,7 @@ __device__ void ghost_x_body(const Desc& D, const double* __restrict__ w, long l
       g[m * mst + ((size_t)s * D.nz + k) * D.ny + j] = gq[s][m];
 }
 
-__device__ void ghost_y_body(const Desc& D, const double* __restrict__ w, long long t) {
+__device__ __forceinline__ void ghost_y_body(const Desc& D, const double* __restrict__ w, long long t) {
   // t over 2 * nz * nxg (side, k, ii)
   const long long per_side = (long long)D.nz * D.nxg;
   const int side = (int)(t / per_side);
@@ -427,45 +436,116 @@ __global__ void k_ghost_y(Desc D, int stage) {
 // Ducros sensor (eq. sensor), FP64, operations in the order of the
 // definition and without contraction, so that the flag decision is
 // reproducible: theta = max(-div / sqrt(div^2 + |curl|^2 + eps), 0).
-__device__ __forceinline__ double vel_at(const Desc& D, const double* __restrict__ w, int i, int j,
-                                         int k, int comp) {
-  double q[5];
-  load_node(D, w, i, j, k, q);
-  return q[comp] * (1.0 / q[0]);
+// 2.5-D tiling: a 64x4 tile of velocities with a 2-node cross-shaped halo
+// is staged in LDS plane by plane; each thread keeps its own column's
+// velocities for planes c-2..c+2 in registers.
+constexpr int kSenTX = 64, kSenTY = 4, kSenKz = 16;
+
+struct SenSmem {
+  double v[3][kSenTY + 4][kSenTX + 4];
+};
+
+int sensor_tiles(const Desc& D) {
+  return ((D.nx + kSenTX - 1) / kSenTX) * ((D.ny + kSenTY - 1) / kSenTY) *
+         ((D.nz + kSenKz - 1) / kSenKz);
 }
 
-__device__ void sensor_body(const Desc& D, const double* __restrict__ w, long long n,
+__device__ __forceinline__ void vel_of(const double q[5], double& u, double& v, double& w) {
+  const double ir = 1.0 / q[0];
+  u = q[1] * ir;
+  v = q[2] * ir;
+  w = q[3] * ir;
+}
+
+__device__ void sensor_tile(const Desc& D, const double* __restrict__ w, int lb, SenSmem& S,
                             bool export_theta) {
+  constexpr int LX = kSenTX + 4;
+  const int stx = (D.nx + kSenTX - 1) / kSenTX, sty = (D.ny + kSenTY - 1) / kSenTY;
+  const int txi = lb % stx, rem = lb / stx;
+  const int tyi = rem % sty, zc = rem / sty;
+  const int i0 = txi * kSenTX, j0 = tyi * kSenTY;
+  const int kb = zc * kSenKz, ke = min(kb + kSenKz, D.nz);
+  const int tid = threadIdx.x, tx = tid % kSenTX, ty = tid / kSenTX;
+  const int i = i0 + tx, j = j0 + ty;
+  const bool valid = i < D.nx && j < D.ny;
+  const bool tile_in = i0 >= 2 && i0 + kSenTX + 2 <= D.nx && j0 >= 2 && j0 + kSenTY + 2 <= D.ny;
+  const size_t N = (size_t)D.N;
+  const double iy = D.iy[j < D.ny ? j : D.ny - 1];
+  double U[5], V[5], W[5];
+  auto load = [&](int gi, int gj, int plane, bool fast, double& u, double& v, double& ww) {
+    double q[5];
+    if (fast) {
+      const size_t b = nidx(D, gi, gj, wrapi(plane, D.nz));
+#pragma unroll
+      for (int m = 0; m < 4; ++m) q[m] = w[(size_t)m * N + b];
+    } else {
+      load_node(D, w, gi, gj, plane, q);
+    }
+    vel_of(q, u, v, ww);
+  };
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl) load(i, j, kb - 2 + sl, valid, U[sl], V[sl], W[sl]);
+  for (int c = kb; c < ke; ++c) {
+    load(i, j, c + 2, valid, U[4], V[4], W[4]);
+    S.v[0][ty + 2][tx + 2] = U[2];
+    S.v[1][ty + 2][tx + 2] = V[2];
+    S.v[2][ty + 2][tx + 2] = W[2];
+    const int kk = wrapi(c, D.nz);
+    for (int h = tid; h < 4 * kSenTX + 4 * kSenTY; h += 256) {
+      int lx, ly;
+      if (h < 4 * kSenTX) {  // two rows below and two above the tile
+        const int r = h / kSenTX;
+        ly = r < 2 ? r : kSenTY + r;
+        lx = 2 + h - r * kSenTX;
+      } else {               // two columns left and two right of the tile
+        const int hh = h - 4 * kSenTX;
+        ly = 2 + hh / 4;
+        const int cc = hh & 3;
+        lx = cc < 2 ? cc : kSenTX + cc;
+      }
+      double u, v, ww;
+      load(i0 - 2 + lx, j0 - 2 + ly, kk, tile_in, u, v, ww);
+      S.v[0][ly][lx] = u;
+      S.v[1][ly][lx] = v;
+      S.v[2][ly][lx] = ww;
+    }
+    __syncthreads();
+    if (valid) {
 #pragma clang fp contract(off)
-  const int i = (int)(n % D.nx);
-  const long long r = n / D.nx;
-  const int j = (int)(r % D.ny), k = (int)(r / D.ny);
-  double g[3][3];  // g[c][d] = d u_c / d x_d
-  const double inv[3] = {D.idx, D.iy[j], D.idz};
+      const int ly = ty + 2, lx = tx + 2;
+      double g[3][3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
+      for (int q = 0; q < 3; ++q) {
+        g[q][0] = D.idx * (CA1 * (S.v[q][ly][lx + 1] - S.v[q][ly][lx - 1]) +
+                           CA2 * (S.v[q][ly][lx + 2] - S.v[q][ly][lx - 2]));
+        g[q][1] = iy * (CA1 * (S.v[q][ly + 1][lx] - S.v[q][ly - 1][lx]) +
+                        CA2 * (S.v[q][ly + 2][lx] - S.v[q][ly - 2][lx]));
+      }
+      g[0][2] = D.idz * (CA1 * (U[3] - U[1]) + CA2 * (U[4] - U[0]));
+      g[1][2] = D.idz * (CA1 * (V[3] - V[1]) + CA2 * (V[4] - V[0]));
+      g[2][2] = D.idz * (CA1 * (W[3] - W[1]) + CA2 * (W[4] - W[0]));
+      const double div = g[0][0] + g[1][1] + g[2][2];
+      const double ox = g[2][1] - g[1][2], oy = g[0][2] - g[2][0], oz = g[1][0] - g[0][1];
+      const double den = sqrt(div * div + (ox * ox + oy * oy + oz * oz) + D.eps_s);
+      double th = -div / den;
+      if (th < 0.0) th = 0.0;
+      const size_t n = nidx(D, i, j, c);
+      D.nflag[n] = th > D.theta_star ? 1 : 0;
+      if (export_theta) D.theta[n] = th;
+    }
+    __syncthreads();
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const int di = d == 0, dj = d == 1, dk = d == 2;
-      const double fp1 = vel_at(D, w, i + di, j + dj, k + dk, 1 + c);
-      const double fm1 = vel_at(D, w, i - di, j - dj, k - dk, 1 + c);
-      const double fp2 = vel_at(D, w, i + 2 * di, j + 2 * dj, k + 2 * dk, 1 + c);
-      const double fm2 = vel_at(D, w, i - 2 * di, j - 2 * dj, k - 2 * dk, 1 + c);
-      g[c][d] = inv[d] * (CA1 * (fp1 - fm1) + CA2 * (fp2 - fm2));
+    for (int sl = 0; sl < 4; ++sl) {
+      U[sl] = U[sl + 1];
+      V[sl] = V[sl + 1];
+      W[sl] = W[sl + 1];
     }
   }
-  const double div = g[0][0] + g[1][1] + g[2][2];
-  const double ox = g[2][1] - g[1][2], oy = g[0][2] - g[2][0], oz = g[1][0] - g[0][1];
-  const double den = sqrt(div * div + (ox * ox + oy * oy + oz * oz) + D.eps_s);
-  double th = -div / den;
-  if (th < 0.0) th = 0.0;
-  D.nflag[n] = th > D.theta_star ? 1 : 0;
-  if (export_theta) D.theta[n] = th;
 }
 
-__global__ void k_sensor(Desc D, int stage, int export_theta) {
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < D.N) sensor_body(D, D.win[stage], n, export_theta != 0);
+__global__ void __launch_bounds__(256) k_sensor(Desc D, int stage, int export_theta) {
+  __shared__ SenSmem S;
+  sensor_tile(D, D.win[stage], xcd_swizzle_blk(blockIdx.x, gridDim.x), S, export_theta != 0);
 }
 
 // ------------------------------------------------------------------ interface flags + lists
@@ -482,51 +562,90 @@ __device__ __forceinline__ uint8_t node_flag(const Desc& D, int i, int j, int k)
   return D.nflag[nidx(D, i, j, k)];
 }
 
-__device__ void iflags_body(const Desc& D, long long n, bool in) {
+__device__ __forceinline__ uint8_t iface_bits(const Desc& D, long long n) {
+  const int i = (int)(n % D.nx);
+  const long long r = n / D.nx;
+  const int j = (int)(r % D.ny), k = (int)(r / D.ny);
   uint8_t f = 0;
-  if (in) {
-    const int i = (int)(n % D.nx);
-    const long long r = n / D.nx;
-    const int j = (int)(r % D.ny), k = (int)(r / D.ny);
-    const int id[3] = {i, j, k};
-    const int nd[3] = {D.nx, D.ny, D.nz};
-    const int per[3] = {D.per_x, D.per_y, 1};
-    for (int d = 0; d < 3; ++d) {
-      if (!per[d] && id[d] == nd[d] - 1) continue;  // boundary interface: central
-      uint8_t b;
-      if (D.sensor_mode == 2) {
-        b = 1;
-      } else {
-        const int di = d == 0, dj = d == 1, dk = d == 2;
-        b = node_flag(D, i - di, j - dj, k - dk) | node_flag(D, i, j, k) |
-            node_flag(D, i + di, j + dj, k + dk) | node_flag(D, i + 2 * di, j + 2 * dj, k + 2 * dk);
-      }
-      f |= (uint8_t)(b << d);
-    }
-    D.iflag[n] = f;
+  // boundary interfaces of non-periodic directions always use the central flux
+  const bool bx = !D.per_x && i == D.nx - 1, by = !D.per_y && j == D.ny - 1;
+  if (D.sensor_mode == 2) {
+    f = (uint8_t)((bx ? 0 : 1) | (by ? 0 : 2) | 4);
+  } else {
+    const uint8_t c0 = node_flag(D, i, j, k);
+    if (!bx && (c0 | node_flag(D, i - 1, j, k) | node_flag(D, i + 1, j, k) | node_flag(D, i + 2, j, k)))
+      f |= 1;
+    if (!by && (c0 | node_flag(D, i, j - 1, k) | node_flag(D, i, j + 1, k) | node_flag(D, i, j + 2, k)))
+      f |= 2;
+    if (c0 | node_flag(D, i, j, k - 1) | node_flag(D, i, j, k + 1) | node_flag(D, i, j, k + 2)) f |= 4;
   }
-  // wave-aggregated append to the per-direction lists
-  for (int d = 0; d < 3; ++d) {
-    const bool b = in && ((f >> d) & 1);
-    const unsigned long long mask = __ballot(b);
-    if (mask == 0ull) continue;
-    const int leader = __ffsll((long long)mask) - 1;
-    const int lane = __lane_id();
-    unsigned base = 0;
-    if (lane == leader) base = atomicAdd(&D.count[d], (unsigned)__popcll(mask));
-    base = __shfl(base, leader);
-    if (b) {
-      const unsigned rank = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-      D.list[d][base + rank] = (int)n;
-    }
-  }
+  return f;
 }
 
-__global__ void k_iflags(Desc D) {
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  iflags_body(D, n, n < D.N);
+// Exclusive prefix sum over the 256 threads of a block (fixed order); returns
+// the thread's offset and writes the block total to *tot.
+__device__ __forceinline__ unsigned block_scan256(unsigned v, unsigned* sm, unsigned* tot) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  unsigned x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sm[wv] = x;
+  __syncthreads();
+  unsigned pre = 0, all = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (q < wv) pre += sm[q];
+    all += sm[q];
+  }
+  __syncthreads();
+  *tot = all;
+  return pre + x - v;
 }
+
+// Interface flags of a range of kIflagsPer*256 nodes and their compaction
+// into the per-direction lists: one atomic per direction and block reserves
+// the block's segment; inside it the order is fixed.
+constexpr int kIflagsPer = 16;
+
+__device__ __forceinline__ void iflags_body(const Desc& D, long long blk) {
+  __shared__ unsigned sm[4];
+  __shared__ unsigned base[3];
+  const long long n0 = blk * (256LL * kIflagsPer);
+  unsigned cnt[3] = {0u, 0u, 0u};
+  uint8_t fl[kIflagsPer];
+#pragma unroll
+  for (int r = 0; r < kIflagsPer; ++r) {
+    const long long n = n0 + (long long)r * 256 + threadIdx.x;
+    uint8_t f = 0;
+    if (n < D.N) {
+      f = iface_bits(D, n);
+      D.iflag[n] = f;
+    }
+    fl[r] = f;
+    cnt[0] += f & 1;
+    cnt[1] += (f >> 1) & 1;
+    cnt[2] += (f >> 2) & 1;
+  }
+  unsigned off[3], tot[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) off[d] = block_scan256(cnt[d], sm, &tot[d]);
+  if (threadIdx.x < 3) base[threadIdx.x] = tot[threadIdx.x] ? atomicAdd(&D.count[threadIdx.x], tot[threadIdx.x]) : 0u;
+  __syncthreads();
+  unsigned pos[3] = {base[0] + off[0], base[1] + off[1], base[2] + off[2]};
+#pragma unroll
+  for (int r = 0; r < kIflagsPer; ++r) {
+    const long long n = n0 + (long long)r * 256 + threadIdx.x;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if ((fl[r] >> d) & 1) D.list[d][pos[d]++] = (int)n;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_iflags(Desc D) { iflags_body(D, blockIdx.x); }
 
 // ------------------------------------------------------------------ WENO on lists
 template <typename F, int DIR>
@@ -965,7 +1084,7 @@ __device__ double block_min(double v, double* sm) {
   return t;
 }
 
-__device__ void force_body(const Desc& D, double* sm) {
+__device__ __forceinline__ void force_body(const Desc& D, double* sm) {
   double v = 0.0;
   for (int q = threadIdx.x; q < D.npart; q += 256) v += D.part[q];
   const double t = block_sum<256>(v, sm);
@@ -1031,7 +1150,7 @@ __global__ void k_rk(Desc D, int stage) {
 }
 
 // ------------------------------------------------------------------ time step
-__device__ void dt_part_body(const Desc& D, int b, int nb, double* sm) {
+__device__ __forceinline__ void dt_part_body(const Desc& D, int b, int nb, double* sm) {
   const double* w = D.win[0];
   const size_t N = (size_t)D.N;
   double cm = 0.0, vm = 0.0;
@@ -1065,7 +1184,7 @@ __global__ void __launch_bounds__(256) k_dt_part(Desc D) {
   dt_part_body(D, blockIdx.x, gridDim.x, sm);
 }
 
-__device__ void dt_final_body(const Desc& D, int nb, double* sm) {
+__device__ __forceinline__ void dt_final_body(const Desc& D, int nb, double* sm) {
   double dt;
   if (D.dt_fixed > 0.0) {
     dt = D.dt_fixed;
@@ -1176,12 +1295,12 @@ hipError_t launch_ghosts(const Desc& D, int stage, hipStream_t st) {
 }
 
 hipError_t launch_sensor(const Desc& D, int stage, bool export_theta, hipStream_t st) {
-  k_sensor<<<nblk(D.N, 256), 256, 0, st>>>(D, stage, export_theta ? 1 : 0);
+  k_sensor<<<sensor_tiles(D), 256, 0, st>>>(D, stage, export_theta ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_iflags(const Desc& D, hipStream_t st) {
-  k_iflags<<<nblk(D.N, 256), 256, 0, st>>>(D);
+  k_iflags<<<nblk(D.N, 256 * kIflagsPer), 256, 0, st>>>(D);
   return hipGetLastError();
 }
 
@@ -1255,6 +1374,8 @@ hipError_t launch_diag(const Desc& D, hipStream_t st) {
 int batch_items(const Desc& D, int kind) {
   switch (kind) {
     case WK_PTS: return (int)nblk(D.N, 256);
+    case WK_IFL: return (int)nblk(D.N, 256 * kIflagsPer);
+    case WK_SEN: return sensor_tiles(D);
     case WK_RHS: return rhs_blocks(D);
     case WK_GX: return D.per_x ? 0 : (int)nblk(2LL * D.ny * D.nz, 256);
     case WK_GY: return D.per_y ? 0 : (int)nblk(2LL * D.nz * D.nxg, 256);
@@ -1328,21 +1449,16 @@ __global__ void __launch_bounds__(256) k_b_ghost_y(const Desc* __restrict__ desc
 
 __global__ void __launch_bounds__(256) k_b_sensor(const Desc* __restrict__ descs,
                                                   const BatchTable* __restrict__ T, int stage) {
-  BATCH_FOR(WK_PTS)
-  if (D.sensor_mode == 1) {
-    const long long n = (long long)local * 256 + threadIdx.x;
-    if (n < D.N) sensor_body(D, D.win[stage], n, false);
-  }
+  __shared__ SenSmem S;
+  BATCH_FOR(WK_SEN)
+  if (D.sensor_mode == 1) sensor_tile(D, D.win[stage], local, S, false);
   BATCH_END
 }
 
 __global__ void __launch_bounds__(256) k_b_iflags(const Desc* __restrict__ descs,
                                                   const BatchTable* __restrict__ T) {
-  BATCH_FOR(WK_PTS)
-  if (D.sensor_mode > 0) {
-    const long long n = (long long)local * 256 + threadIdx.x;
-    iflags_body(D, n, n < D.N);
-  }
+  BATCH_FOR(WK_IFL)
+  if (D.sensor_mode > 0) iflags_body(D, local);
   BATCH_END
 }
 
