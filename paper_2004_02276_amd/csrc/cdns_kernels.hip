@@ -235,69 +235,80 @@ __device__ __forceinline__ F weno5(F vm2, F vm1, F v0, F vp1, F vp2) {
 // DIR from the conserved states of nodes i-2..i+3 (Sec. 2.1).  Eigenvectors
 // at the Roe average of nodes i, i+1; splitting constant per field from the
 // largest |eigenvalue| over the six nodes.
-template <typename F, int DIR>
-__device__ void weno_flux(const Desc& D, const double qd[6][5], F out[5]) {
+template <typename F, int DIR, typename Loader>
+__device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5]) {
   constexpr int PN = 1 + DIR, P1 = 1 + (DIR + 1) % 3, P2 = 1 + (DIR + 2) % 3;
   const F gm1 = (F)D.gm1, gam = (F)D.gamma;
-  F wq[6][5], fq[6][5], hs[6], un_s[6], t1_s[6], t2_s[6];
-  F am0 = F(0), am1 = F(0), am4 = F(0);
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    const F r = (F)qd[s][0];
-    const F ir = F(1) / r;
-    const F mn = (F)qd[s][PN], m1 = (F)qd[s][P1], m2 = (F)qd[s][P2], E = (F)qd[s][4];
-    const F un = mn * ir, t1 = m1 * ir, t2 = m2 * ir;
-    const F p = gm1 * (E - F(0.5) * r * (un * un + t1 * t1 + t2 * t2));
-    const F c = sqrt(gam * p * ir);
-    wq[s][0] = r; wq[s][1] = mn; wq[s][2] = m1; wq[s][3] = m2; wq[s][4] = E;
-    fq[s][0] = mn;
-    fq[s][1] = mn * un + p;
-    fq[s][2] = mn * t1;
-    fq[s][3] = mn * t2;
-    fq[s][4] = un * (E + p);
-    hs[s] = (E + p) * ir;
-    un_s[s] = un; t1_s[s] = t1; t2_s[s] = t2;
-    am0 = fmax(am0, fabs(un - c));
-    am1 = fmax(am1, fabs(un));
-    am4 = fmax(am4, fabs(un + c));
-  }
   // Roe average of nodes i (s=2) and i+1 (s=3)
-  const F sl = sqrt(wq[2][0]), sr = sqrt(wq[3][0]);
-  const F iw = F(1) / (sl + sr);
-  const F ur = (sl * un_s[2] + sr * un_s[3]) * iw;
-  const F vr = (sl * t1_s[2] + sr * t1_s[3]) * iw;
-  const F wr = (sl * t2_s[2] + sr * t2_s[3]) * iw;
-  const F Hr = (sl * hs[2] + sr * hs[3]) * iw;
+  F ur, vr, wr, Hr;
+  {
+    double qa[5], qb[5];
+    get(2, qa);
+    get(3, qb);
+    const F ra = (F)qa[0], rb = (F)qb[0];
+    const F ira = F(1) / ra, irb = F(1) / rb;
+    const F una = (F)qa[PN] * ira, t1a = (F)qa[P1] * ira, t2a = (F)qa[P2] * ira;
+    const F unb = (F)qb[PN] * irb, t1b = (F)qb[P1] * irb, t2b = (F)qb[P2] * irb;
+    const F Ea = (F)qa[4], Eb = (F)qb[4];
+    const F pa = gm1 * (Ea - F(0.5) * ra * (una * una + t1a * t1a + t2a * t2a));
+    const F pb = gm1 * (Eb - F(0.5) * rb * (unb * unb + t1b * t1b + t2b * t2b));
+    const F Ha = (Ea + pa) * ira, Hb = (Eb + pb) * irb;
+    const F sl = sqrt(ra), sr = sqrt(rb);
+    const F iw = F(1) / (sl + sr);
+    ur = (sl * una + sr * unb) * iw;
+    vr = (sl * t1a + sr * t1b) * iw;
+    wr = (sl * t2a + sr * t2b) * iw;
+    Hr = (sl * Ha + sr * Hb) * iw;
+  }
   const F q2 = ur * ur + vr * vr + wr * wr;
   const F cr = sqrt(gm1 * (Hr - F(0.5) * q2));
   const F ic = F(1) / cr;
   const F b1 = gm1 * ic * ic;
   const F b2 = F(0.5) * q2 * b1;
-  // left eigenvectors (rows), permuted component order (rho, m_n, m_t1, m_t2, E)
-  const F L[5][5] = {
-      {F(0.5) * (b2 + ur * ic), F(-0.5) * (b1 * ur + ic), F(-0.5) * b1 * vr, F(-0.5) * b1 * wr, F(0.5) * b1},
-      {F(1) - b2, b1 * ur, b1 * vr, b1 * wr, -b1},
-      {-vr, F(0), F(1), F(0), F(0)},
-      {-wr, F(0), F(0), F(1), F(0)},
-      {F(0.5) * (b2 - ur * ic), F(-0.5) * (b1 * ur - ic), F(-0.5) * b1 * vr, F(-0.5) * b1 * wr, F(0.5) * b1}};
+  // Projection on the left eigenvectors (permuted order rho, m_n, m_t1,
+  // m_t2, E).  With X = b2 q0 - b1 (u q1 + v q2 + w q3) + b1 q4 and
+  // Y = (u q0 - q1)/c the rows are: (X + Y)/2, q0 - X, q2 - v q0,
+  // q3 - w q0, (X - Y)/2.
+  auto project = [&](const F* q, F out[5]) {
+    const F X = b2 * q[0] - b1 * (ur * q[1] + vr * q[2] + wr * q[3]) + b1 * q[4];
+    const F Y = (ur * q[0] - q[1]) * ic;
+    out[0] = F(0.5) * (X + Y);
+    out[1] = q[0] - X;
+    out[2] = q[2] - vr * q[0];
+    out[3] = q[3] - wr * q[0];
+    out[4] = F(0.5) * (X - Y);
+  };
+  // stencil nodes: physical flux, eigenvalue bounds, characteristic projections
+  F v[6][5], g[6][5];
+  F am0 = F(0), am1 = F(0), am4 = F(0);
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    double qd[5];
+    get(s, qd);
+    const F r = (F)qd[0];
+    const F ir = F(1) / r;
+    const F mn = (F)qd[PN], m1 = (F)qd[P1], m2 = (F)qd[P2], E = (F)qd[4];
+    const F un = mn * ir, t1 = m1 * ir, t2 = m2 * ir;
+    const F p = gm1 * (E - F(0.5) * r * (un * un + t1 * t1 + t2 * t2));
+    const F c = sqrt(gam * p * ir);
+    const F wq[5] = {r, mn, m1, m2, E};
+    const F fq[5] = {mn, mn * un + p, mn * t1, mn * t2, un * (E + p)};
+    project(wq, v[s]);
+    project(fq, g[s]);
+    am0 = fmax(am0, fabs(un - c));
+    am1 = fmax(am1, fabs(un));
+    am4 = fmax(am4, fabs(un + c));
+  }
   const F alpha[5] = {am0, am1, am1, am1, am4};
   F gh[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    F gp[6], gmi[6];
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-      F v = F(0), g = F(0);
-#pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        v += L[k][c] * wq[s][c];
-        g += L[k][c] * fq[s][c];
-      }
-      gp[s] = F(0.5) * (g + alpha[k] * v);
-      gmi[s] = F(0.5) * (g - alpha[k] * v);
-    }
-    gh[k] = weno5<F>(gp[0], gp[1], gp[2], gp[3], gp[4]) +
-            weno5<F>(gmi[5], gmi[4], gmi[3], gmi[2], gmi[1]);
+    const F a = alpha[k];
+#define GP(s) (F(0.5) * (g[s][k] + a * v[s][k]))
+#define GM(s) (F(0.5) * (g[s][k] - a * v[s][k]))
+    gh[k] = weno5<F>(GP(0), GP(1), GP(2), GP(3), GP(4)) + weno5<F>(GM(5), GM(4), GM(3), GM(2), GM(1));
+#undef GP
+#undef GM
   }
   // right eigenvectors applied to the reconstructed characteristic flux
   const F f0 = gh[0] + gh[1] + gh[4];
@@ -653,14 +664,12 @@ __device__ void weno_entry(const Desc& D, const double* __restrict__ w, int n) {
   const int i = n % D.nx;
   const int r = n / D.nx;
   const int j = r % D.ny, k = r / D.ny;
-  double q[6][5];
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
+  auto get = [&](int s, double q[5]) {
     const int o = s - 2;
-    load_node(D, w, i + (DIR == 0 ? o : 0), j + (DIR == 1 ? o : 0), k + (DIR == 2 ? o : 0), q[s]);
-  }
+    load_node(D, w, i + (DIR == 0 ? o : 0), j + (DIR == 1 ? o : 0), k + (DIR == 2 ? o : 0), q);
+  };
   F f[5];
-  weno_flux<F, DIR>(D, q, f);
+  weno_flux<F, DIR>(D, get, f);
   double* out = D.Fw[DIR];
 #pragma unroll
   for (int m = 0; m < 5; ++m) out[(size_t)m * D.N + n] = (double)f[m];
