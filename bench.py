@@ -104,6 +104,13 @@ def main():
     from paper_2004_02276_amd import Solver
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    # one device-to-device copy of known size (256 MiB read + 256 MiB written):
+    # reference dispatch for scaling the HBM byte counters of a profiled run
+    src = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
     pr = P.channel()
     precision = 0 if args.precision == "fp64" else 1
     s = Solver(pr, precision=precision)

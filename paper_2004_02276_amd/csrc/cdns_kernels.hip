@@ -664,9 +664,16 @@ __device__ void weno_entry(const Desc& D, const double* __restrict__ w, int n) {
   const int i = n % D.nx;
   const int r = n / D.nx;
   const int j = r % D.ny, k = r / D.ny;
-  auto get = [&](int s, double q[5]) {
+  // all 30 loads are issued before any arithmetic (latency-bound kernel)
+  double qn[6][5];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
     const int o = s - 2;
-    load_node(D, w, i + (DIR == 0 ? o : 0), j + (DIR == 1 ? o : 0), k + (DIR == 2 ? o : 0), q);
+    load_node(D, w, i + (DIR == 0 ? o : 0), j + (DIR == 1 ? o : 0), k + (DIR == 2 ? o : 0), qn[s]);
+  }
+  auto get = [&](int s, double q[5]) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) q[m] = qn[s][m];
   };
   F f[5];
   weno_flux<F, DIR>(D, get, f);
