@@ -618,27 +618,38 @@ __device__ __forceinline__ unsigned block_scan256(unsigned v, unsigned* sm, unsi
 
 // Interface flags of a range of kIflagsPer*256 nodes and their compaction
 // into the per-direction lists: one atomic per direction and block reserves
-// the block's segment; inside it the order is fixed.
+// the block's segment; each thread owns kIflagsPer consecutive nodes, so
+// the segment is in node order and the shock-capturing kernel reading the
+// list touches consecutive nodes in consecutive lanes.
 constexpr int kIflagsPer = 16;
 
 __device__ __forceinline__ void iflags_body(const Desc& D, long long blk) {
   __shared__ unsigned sm[4];
   __shared__ unsigned base[3];
-  const long long n0 = blk * (256LL * kIflagsPer);
+  const long long n0 = blk * (256LL * kIflagsPer) + (long long)threadIdx.x * kIflagsPer;
   unsigned cnt[3] = {0u, 0u, 0u};
   uint8_t fl[kIflagsPer];
 #pragma unroll
   for (int r = 0; r < kIflagsPer; ++r) {
-    const long long n = n0 + (long long)r * 256 + threadIdx.x;
+    const long long n = n0 + r;
     uint8_t f = 0;
-    if (n < D.N) {
-      f = iface_bits(D, n);
-      D.iflag[n] = f;
-    }
+    if (n < D.N) f = iface_bits(D, n);
     fl[r] = f;
     cnt[0] += f & 1;
     cnt[1] += (f >> 1) & 1;
     cnt[2] += (f >> 2) & 1;
+  }
+  if (n0 + kIflagsPer <= D.N) {  // 16 flag bytes in one 128-bit store (n0 is 16-aligned)
+    unsigned wd[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      wd[q] = (unsigned)fl[4 * q] | ((unsigned)fl[4 * q + 1] << 8) | ((unsigned)fl[4 * q + 2] << 16) |
+              ((unsigned)fl[4 * q + 3] << 24);
+    reinterpret_cast<uint4*>(D.iflag)[n0 / kIflagsPer] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < kIflagsPer; ++r)
+      if (n0 + r < D.N) D.iflag[n0 + r] = fl[r];
   }
   unsigned off[3], tot[3];
 #pragma unroll
@@ -648,7 +659,7 @@ __device__ __forceinline__ void iflags_body(const Desc& D, long long blk) {
   unsigned pos[3] = {base[0] + off[0], base[1] + off[1], base[2] + off[2]};
 #pragma unroll
   for (int r = 0; r < kIflagsPer; ++r) {
-    const long long n = n0 + (long long)r * 256 + threadIdx.x;
+    const long long n = n0 + r;
 #pragma unroll
     for (int d = 0; d < 3; ++d)
       if ((fl[r] >> d) & 1) D.list[d][pos[d]++] = (int)n;
