@@ -16,7 +16,7 @@ from typing import Dict, Optional, Tuple
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning.json")
 
-TILES = [(64, 4), (32, 8), (64, 2), (128, 2)]
+TILES = [(64, 4), (64, 8), (32, 8), (64, 2), (128, 2)]
 KZS = [4, 8, 16, 32]
 
 

@@ -114,12 +114,12 @@ void set_tiling_desc(Desc& D, int tx, int ty, int kz) {
   D.npart = D.tiles_x * D.tiles_y * D.zchunks;
 }
 
-// Default tiling: enough blocks to fill 256 CUs at least twice.
+// Default tiling: enough blocks to give each of the 256 CUs two.
 void default_tiling(Desc& D) {
   int tx = 64, ty = 4;
-  int kz = 16;
+  int kz = 32;  // deep z chunks amortise the 4-plane pipeline start
   long long tiles = (long long)((D.nx + tx - 1) / tx) * ((D.ny + ty - 1) / ty);
-  while (kz > 4 && tiles * ((D.nz + kz - 1) / kz) < 1024) kz /= 2;
+  while (kz > 4 && tiles * ((D.nz + kz - 1) / kz) < 512) kz /= 2;
   set_tiling_desc(D, tx, ty, kz);
 }
 

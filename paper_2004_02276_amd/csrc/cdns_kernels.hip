@@ -698,7 +698,14 @@ __global__ void __launch_bounds__(256) k_weno(Desc D, int stage) {
   const int dir = blockIdx.y;
   const unsigned cnt = D.count[dir];
   const double* w = D.win[stage];
-  for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x) {
+  // each block streams through one contiguous segment of the list, and
+  // consecutive segments sit on the same XCD: neighbouring interfaces share
+  // stencil nodes in that XCD's L2
+  const unsigned G = gridDim.x;
+  const unsigned lb = (unsigned)xcd_swizzle_blk(blockIdx.x, G);
+  const unsigned per = ((cnt + G - 1) / G + 255u) & ~255u;
+  const unsigned e1 = min(cnt, (lb + 1) * per);
+  for (unsigned e = lb * per + threadIdx.x; e < e1; e += 256u) {
     const int n = D.list[dir][e];
     if (dir == 0) weno_entry<F, 0>(D, w, n);
     else if (dir == 1) weno_entry<F, 1>(D, w, n);
@@ -1344,7 +1351,7 @@ int rhs_blocks(const Desc& D) { return D.tiles_x * D.tiles_y * D.zchunks; }
 
 bool rhs_tile_supported(int tx, int ty) {
   return (tx == 64 && ty == 4) || (tx == 32 && ty == 8) || (tx == 64 && ty == 2) ||
-         (tx == 128 && ty == 2);
+         (tx == 128 && ty == 2) || (tx == 64 && ty == 8);
 }
 
 template <typename F>
@@ -1354,6 +1361,7 @@ static hipError_t launch_rhs_t(const Desc& D, int stage, hipStream_t st) {
   else if (D.tile_x == 32 && D.tile_y == 8) k_rhs<F, 32, 8><<<nb, 256, 0, st>>>(D, stage);
   else if (D.tile_x == 64 && D.tile_y == 2) k_rhs<F, 64, 2><<<nb, 128, 0, st>>>(D, stage);
   else if (D.tile_x == 128 && D.tile_y == 2) k_rhs<F, 128, 2><<<nb, 256, 0, st>>>(D, stage);
+  else if (D.tile_x == 64 && D.tile_y == 8) k_rhs<F, 64, 8><<<nb, 512, 0, st>>>(D, stage);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -1542,6 +1550,7 @@ static hipError_t launch_b_rhs(const Desc* d, const BatchTable* t, int stage, in
   else if (tx == 32 && ty == 8) k_b_rhs<F, 32, 8><<<g, 256, 0, st>>>(d, t, stage);
   else if (tx == 64 && ty == 2) k_b_rhs<F, 64, 2><<<g, 128, 0, st>>>(d, t, stage);
   else if (tx == 128 && ty == 2) k_b_rhs<F, 128, 2><<<g, 256, 0, st>>>(d, t, stage);
+  else if (tx == 64 && ty == 8) k_b_rhs<F, 64, 8><<<g, 512, 0, st>>>(d, t, stage);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
