@@ -126,7 +126,8 @@ void default_tiling(Desc& D) {
 // Enqueue the right-hand-side phases of one stage (ghosts .. forcing sum).
 hipError_t enqueue_rhs_phases(const Desc& D, int stage, bool export_theta, hipStream_t st) {
   hipError_t e;
-  if (D.sensor_mode > 0 && (e = cdns::launch_stage_begin(D, st)) != hipSuccess) return e;
+  // list counters: reset by the sensor kernel in hybrid mode, else here
+  if (D.sensor_mode == 2 && (e = cdns::launch_stage_begin(D, st)) != hipSuccess) return e;
   if ((e = cdns::launch_ghosts(D, stage, st)) != hipSuccess) return e;
   if (D.sensor_mode == 1 && (e = cdns::launch_sensor(D, stage, export_theta, st)) != hipSuccess)
     return e;
@@ -135,7 +136,9 @@ hipError_t enqueue_rhs_phases(const Desc& D, int stage, bool export_theta, hipSt
     if ((e = cdns::launch_weno(D, stage, st)) != hipSuccess) return e;
   }
   if ((e = cdns::launch_rhs(D, stage, st)) != hipSuccess) return e;
-  if (D.forcing && (e = cdns::launch_force(D, st)) != hipSuccess) return e;
+  // the RK kernel reduces the forcing partials itself; a standalone
+  // right-hand side needs the explicit reduction
+  if (D.forcing && stage == 3 && (e = cdns::launch_force(D, st)) != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -531,7 +534,7 @@ cdns_status cdns_time_phases(cdns_ctx* c, int32_t nsteps, double cfl, double dt_
   for (int step = 0; step < nsteps && e == hipSuccess; ++step) {
     timed(CDNS_PH_DT, [&] { return cdns::launch_dt(D, st); });
     for (int stage = 0; stage < 3; ++stage) {
-      if (D.sensor_mode > 0 && e == hipSuccess) e = cdns::launch_stage_begin(D, st);
+      if (D.sensor_mode == 2 && e == hipSuccess) e = cdns::launch_stage_begin(D, st);
       if (!D.per_x || !D.per_y) timed(CDNS_PH_GHOSTS, [&] { return cdns::launch_ghosts(D, stage, st); });
       if (D.sensor_mode == 1)
         timed(CDNS_PH_SENSOR, [&] { return cdns::launch_sensor(D, stage, false, st); });
@@ -540,7 +543,6 @@ cdns_status cdns_time_phases(cdns_ctx* c, int32_t nsteps, double cfl, double dt_
         timed(CDNS_PH_WENO, [&] { return cdns::launch_weno(D, stage, st); });
       }
       timed(CDNS_PH_RHS, [&] { return cdns::launch_rhs(D, stage, st); });
-      if (D.forcing) timed(CDNS_PH_FORCE, [&] { return cdns::launch_force(D, st); });
       timed(CDNS_PH_RK, [&] { return cdns::launch_rk(D, stage, st); });
     }
   }

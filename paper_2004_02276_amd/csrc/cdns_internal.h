@@ -94,7 +94,7 @@ int rhs_blocks(const Desc& D);
 // flattened item range with a grid stride and locate the instance by a
 // search over the prefix sums, so membership changes rewrite this table only.
 constexpr int kMaxSlots = 64;
-enum { WK_PTS = 0, WK_RHS, WK_GX, WK_GY, WK_DT, WK_IFL, WK_SEN, WK_COUNT };
+enum { WK_PTS = 0, WK_RHS, WK_GX, WK_GY, WK_DT, WK_IFL, WK_SEN, WK_RK, WK_COUNT };
 struct BatchTable {
   int ninst;
   int inst[kMaxSlots];

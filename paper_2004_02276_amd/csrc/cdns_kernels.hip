@@ -556,6 +556,9 @@ __device__ void sensor_tile(const Desc& D, const double* __restrict__ w, int lb,
 
 __global__ void __launch_bounds__(256) k_sensor(Desc D, int stage, int export_theta) {
   __shared__ SenSmem S;
+  // the list counters of this stage start at zero (the previous stage's
+  // lists were consumed before this kernel starts)
+  if (blockIdx.x == 0 && threadIdx.x < 4) D.count[threadIdx.x] = 0u;
   sensor_tile(D, D.win[stage], xcd_swizzle_blk(blockIdx.x, gridDim.x), S, export_theta != 0);
 }
 
@@ -703,7 +706,7 @@ __global__ void __launch_bounds__(256) k_weno(Desc D, int stage) {
   // stencil nodes in that XCD's L2
   const unsigned G = gridDim.x;
   const unsigned lb = (unsigned)xcd_swizzle_blk(blockIdx.x, G);
-  const unsigned per = ((cnt + G - 1) / G + 255u) & ~255u;
+  const unsigned per = (cnt + G - 1) / G;  // even split: every XCD gets work
   const unsigned e1 = min(cnt, (lb + 1) * per);
   for (unsigned e = lb * per + threadIdx.x; e < e1; e += 256u) {
     const int n = D.list[dir][e];
@@ -1141,7 +1144,7 @@ __global__ void k_apply_force(Desc D, int stage) {
 }
 
 // ------------------------------------------------------------------ RK3 update
-__device__ __forceinline__ void rk_point(const Desc& D, int stage, long long n) {
+__device__ __forceinline__ void rk_point(const Desc& D, int stage, long long n, double f) {
   const double alpha = stage == 0 ? 0.0 : (stage == 1 ? -17.0 / 60.0 : -5.0 / 12.0);
   const double beta = stage == 0 ? 8.0 / 15.0 : (stage == 1 ? 5.0 / 12.0 : 3.0 / 4.0);
   const double* __restrict__ w = D.win[stage];
@@ -1157,7 +1160,6 @@ __device__ __forceinline__ void rk_point(const Desc& D, int stage, long long n) 
     r[m] = R[m * N + n];
   }
   if (D.forcing) {
-    const double f = D.scal[SC_FORCE];
     r[1] += f;
     r[4] += f * (q[1] * (1.0 / q[0]));
     if (stage < 2) {
@@ -1178,9 +1180,35 @@ __device__ __forceinline__ void rk_point(const Desc& D, int stage, long long n) 
   if (!(o[0] > 0.0) || !(pe > 0.0) || !(fabs(o[4]) < 1e300)) atomicOr(D.status, (unsigned)ST_BAD_STATE);
 }
 
-__global__ void k_rk(Desc D, int stage) {
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < D.N) rk_point(D, stage, n);
+// Bulk force for every thread of the block: the fixed-order sum of the
+// right-hand-side partials, evaluated identically by every block.
+__device__ __forceinline__ double force_all(const Desc& D, double* sm) {
+  if (!D.forcing) return 0.0;
+  double v = 0.0;
+  for (int q = threadIdx.x; q < D.npart; q += 256) v += D.part[q];
+  const double t = block_sum<256>(v, sm);
+  if (threadIdx.x == 0) sm[4] = -t / D.vol_den;
+  __syncthreads();
+  const double f = sm[4];
+  __syncthreads();
+  return f;
+}
+
+constexpr int kRkPer = 4;  // points per thread of the update kernel
+
+__device__ __forceinline__ void rk_block(const Desc& D, int stage, long long blk, double* sm) {
+  const double f = force_all(D, sm);
+  if (blk == 0 && threadIdx.x == 0 && D.forcing) D.scal[SC_FORCE] = f;
+#pragma unroll
+  for (int r = 0; r < kRkPer; ++r) {
+    const long long n = (blk * kRkPer + r) * 256 + threadIdx.x;
+    if (n < D.N) rk_point(D, stage, n, f);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_rk(Desc D, int stage) {
+  __shared__ double sm[8];
+  rk_block(D, stage, blockIdx.x, sm);
 }
 
 // ------------------------------------------------------------------ time step
@@ -1381,7 +1409,7 @@ hipError_t launch_apply_force(const Desc& D, int stage, hipStream_t st) {
 }
 
 hipError_t launch_rk(const Desc& D, int stage, hipStream_t st) {
-  k_rk<<<nblk(D.N, 256), 256, 0, st>>>(D, stage);
+  k_rk<<<nblk(D.N, 256 * kRkPer), 256, 0, st>>>(D, stage);
   return hipGetLastError();
 }
 
@@ -1411,6 +1439,7 @@ int batch_items(const Desc& D, int kind) {
     case WK_PTS: return (int)nblk(D.N, 256);
     case WK_IFL: return (int)nblk(D.N, 256 * kIflagsPer);
     case WK_SEN: return sensor_tiles(D);
+    case WK_RK: return (int)nblk(D.N, 256 * kRkPer);
     case WK_RHS: return rhs_blocks(D);
     case WK_GX: return D.per_x ? 0 : (int)nblk(2LL * D.ny * D.nz, 256);
     case WK_GY: return D.per_y ? 0 : (int)nblk(2LL * D.nz * D.nxg, 256);
@@ -1536,9 +1565,9 @@ __global__ void __launch_bounds__(256) k_b_force(const Desc* __restrict__ descs,
 
 __global__ void __launch_bounds__(256) k_b_rk(const Desc* __restrict__ descs,
                                               const BatchTable* __restrict__ T, int stage) {
-  BATCH_FOR(WK_PTS)
-  const long long n = (long long)local * 256 + threadIdx.x;
-  if (n < D.N) rk_point(D, stage, n);
+  __shared__ double sm[8];
+  BATCH_FOR(WK_RK)
+  rk_block(D, stage, local, sm);
   BATCH_END
 }
 
