@@ -99,7 +99,7 @@ cdns_status hip_fail(cdns_ctx* c, hipError_t e, const char* what) {
 
 void invalidate_graph(cdns_ctx* c) {
   if (c->gexec) {
-    hipGraphExecDestroy(c->gexec);
+    (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
   }
 }
@@ -136,9 +136,7 @@ hipError_t enqueue_rhs_phases(const Desc& D, int stage, bool export_theta, hipSt
     if ((e = cdns::launch_weno(D, stage, st)) != hipSuccess) return e;
   }
   if ((e = cdns::launch_rhs(D, stage, st)) != hipSuccess) return e;
-  // the RK kernel reduces the forcing partials itself; a standalone
-  // right-hand side needs the explicit reduction
-  if (D.forcing && stage == 3 && (e = cdns::launch_force(D, st)) != hipSuccess) return e;
+  if (D.forcing && (e = cdns::launch_force(D, st)) != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -411,12 +409,12 @@ cdns_status cdns_advance_n(cdns_ctx* c, int32_t n, double cfl, double dt_fixed) 
     hipError_t le = enqueue_step(D, c->cap);
     e = hipStreamEndCapture(c->cap, &g);
     if (le != hipSuccess) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return hip_fail(c, le, "capture launch");
     }
     if (e != hipSuccess) return hip_fail(c, e, "end capture");
     e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
       c->gexec = nullptr;
       return hip_fail(c, e, "graph instantiate");
@@ -571,7 +569,7 @@ cdns_status cdns_destroy(cdns_ctx* c) {
   if (!c) return CDNS_EINVAL;
   if (c->batch_refs > 0) return fail(c, CDNS_EBUSY, "context attached to a batch");
   invalidate_graph(c);
-  if (c->cap) hipStreamDestroy(c->cap);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   delete c;
   return CDNS_OK;
 }

@@ -62,7 +62,7 @@ hipError_t enqueue_batch_step(cdns_batch* b, hipStream_t st) {
   if ((e = ph(BPH_DT_FINAL, 0)) != hipSuccess) return e;
   for (int stage = 0; stage < 3; ++stage) {
     const int seq[] = {BPH_BEGIN, BPH_GHOST_X, BPH_GHOST_Y, BPH_SENSOR, BPH_IFLAGS,
-                       BPH_WENO,  BPH_RHS,     BPH_RK};
+                       BPH_WENO,  BPH_RHS,     BPH_FORCE, BPH_RK};
     for (int p : seq)
       if ((e = ph(p, stage)) != hipSuccess) return e;
   }

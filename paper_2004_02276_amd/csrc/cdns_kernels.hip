@@ -1180,25 +1180,11 @@ __device__ __forceinline__ void rk_point(const Desc& D, int stage, long long n, 
   if (!(o[0] > 0.0) || !(pe > 0.0) || !(fabs(o[4]) < 1e300)) atomicOr(D.status, (unsigned)ST_BAD_STATE);
 }
 
-// Bulk force for every thread of the block: the fixed-order sum of the
-// right-hand-side partials, evaluated identically by every block.
-__device__ __forceinline__ double force_all(const Desc& D, double* sm) {
-  if (!D.forcing) return 0.0;
-  double v = 0.0;
-  for (int q = threadIdx.x; q < D.npart; q += 256) v += D.part[q];
-  const double t = block_sum<256>(v, sm);
-  if (threadIdx.x == 0) sm[4] = -t / D.vol_den;
-  __syncthreads();
-  const double f = sm[4];
-  __syncthreads();
-  return f;
-}
-
 constexpr int kRkPer = 4;  // points per thread of the update kernel
 
 __device__ __forceinline__ void rk_block(const Desc& D, int stage, long long blk, double* sm) {
-  const double f = force_all(D, sm);
-  if (blk == 0 && threadIdx.x == 0 && D.forcing) D.scal[SC_FORCE] = f;
+  (void)sm;
+  const double f = D.forcing ? D.scal[SC_FORCE] : 0.0;  // reduced by the forcing kernel
 #pragma unroll
   for (int r = 0; r < kRkPer; ++r) {
     const long long n = (blk * kRkPer + r) * 256 + threadIdx.x;
