@@ -40,7 +40,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t metric, bcp, w1, w2, ra, rb, nflag, iflag, theta, fw, list, count, gx, gy, part, red,
+  size_t metric, bcp, w1, w2, ra, rb, nflag, slot, theta, fw, list, count, gx, gy, part, red,
       redd, scal, status, diag, total;
   size_t bcp_cap, part_cap;
 };
@@ -71,7 +71,7 @@ Layout layout_of(const cdns_grid* g) {
   L.ra = take(5 * N * sizeof(double));
   L.rb = take(5 * N * sizeof(double));
   L.nflag = take(N);
-  L.iflag = take(N);
+  L.slot = take(3 * N * sizeof(int));
   L.theta = take(N * sizeof(double));
   L.fw = take(3 * 5 * N * sizeof(double));
   L.list = take(3 * N * sizeof(int));
@@ -191,6 +191,8 @@ cdns_status cdns_create(const cdns_grid* grid, const cdns_phys* phys, int32_t pr
   D.nx = nx; D.ny = ny; D.nz = nz;
   D.nxg = nx + 2 * cdns::kHalo;
   D.N = (long long)nx * ny * nz;
+  D.rnx = 1.0 / nx;
+  D.rny = 1.0 / ny;
   D.dx = grid->lx / nx;
   D.dz = grid->lz / nz;
   D.deta = 1.0 / ny;
@@ -253,11 +255,11 @@ cdns_status cdns_create(const cdns_grid* grid, const cdns_phys* phys, int32_t pr
   D.win[2] = w2; D.wout[2] = state_dev; D.rcur[2] = ra; D.rprev[2] = rb;
   D.win[3] = state_dev; D.wout[3] = nullptr; D.rcur[3] = ra; D.rprev[3] = nullptr;
   D.nflag = (uint8_t*)(ws + L.nflag);
-  D.iflag = (uint8_t*)(ws + L.iflag);
   D.theta = (double*)(ws + L.theta);
   for (int d = 0; d < 3; ++d) {
     D.Fw[d] = (double*)(ws + L.fw) + (size_t)d * 5 * D.N;
     D.list[d] = (int*)(ws + L.list) + (size_t)d * D.N;
+    D.slot[d] = (int*)(ws + L.slot) + (size_t)d * D.N;
   }
   D.count = (unsigned*)(ws + L.count);
   const size_t gxs = (size_t)5 * cdns::kHalo * nz * ny;
@@ -288,7 +290,7 @@ cdns_status cdns_create(const cdns_grid* grid, const cdns_phys* phys, int32_t pr
       (e = hipMemsetAsync(ws + L.count, 0, align_up(4 * sizeof(unsigned)), c->stream)) != hipSuccess ||
       (e = hipMemsetAsync(ws + L.scal, 0, cdns::SC_COUNT * sizeof(double), c->stream)) != hipSuccess ||
       (e = hipMemsetAsync(ws + L.status, 0, 4 * sizeof(unsigned), c->stream)) != hipSuccess ||
-      (e = hipMemsetAsync(ws + L.iflag, 0, D.N, c->stream)) != hipSuccess ||
+      (e = hipMemsetAsync(ws + L.slot, 0xFF, 3 * D.N * sizeof(int), c->stream)) != hipSuccess ||
       (e = hipMemsetAsync(ws + L.nflag, 0, D.N, c->stream)) != hipSuccess ||
       (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
     delete c;
@@ -483,7 +485,7 @@ cdns_status cdns_export_sensor(cdns_ctx* c, double* theta_dev, uint8_t* nflags_d
   }
   if (e == hipSuccess && iflags_dev) {
     if (D.sensor_mode > 0)
-      e = hipMemcpyAsync(iflags_dev, D.iflag, D.N, hipMemcpyDeviceToDevice, c->stream);
+      e = cdns::launch_export_iflags(D, iflags_dev, c->stream);
     else
       e = hipMemsetAsync(iflags_dev, 0, D.N, c->stream);
   }
@@ -497,8 +499,7 @@ cdns_status cdns_export_iface_flux(cdns_ctx* c, int32_t dir, double* out_dev) {
   if (dir < 0 || dir > 2 || !out_dev) return fail(c, CDNS_EINVAL, "bad direction or pointer");
   if (!c->last_rhs_valid) return fail(c, CDNS_EINVAL, "no right-hand side evaluated yet");
   const Desc& D = c->D;
-  hipError_t e = hipMemcpyAsync(out_dev, D.Fw[dir], 5 * D.N * sizeof(double),
-                                hipMemcpyDeviceToDevice, c->stream);
+  hipError_t e = cdns::launch_export_iface(D, dir, out_dev, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "export");
   return CDNS_OK;
@@ -533,7 +534,8 @@ cdns_status cdns_time_phases(cdns_ctx* c, int32_t nsteps, double cfl, double dt_
     timed(CDNS_PH_DT, [&] { return cdns::launch_dt(D, st); });
     for (int stage = 0; stage < 3; ++stage) {
       if (D.sensor_mode == 2 && e == hipSuccess) e = cdns::launch_stage_begin(D, st);
-      if (!D.per_x || !D.per_y) timed(CDNS_PH_GHOSTS, [&] { return cdns::launch_ghosts(D, stage, st); });
+      if (cdns::ghosts_needed(D))
+        timed(CDNS_PH_GHOSTS, [&] { return cdns::launch_ghosts(D, stage, st); });
       if (D.sensor_mode == 1)
         timed(CDNS_PH_SENSOR, [&] { return cdns::launch_sensor(D, stage, false, st); });
       if (D.sensor_mode > 0) {
@@ -541,6 +543,7 @@ cdns_status cdns_time_phases(cdns_ctx* c, int32_t nsteps, double cfl, double dt_
         timed(CDNS_PH_WENO, [&] { return cdns::launch_weno(D, stage, st); });
       }
       timed(CDNS_PH_RHS, [&] { return cdns::launch_rhs(D, stage, st); });
+      if (D.forcing) timed(CDNS_PH_FORCE, [&] { return cdns::launch_force(D, st); });
       timed(CDNS_PH_RK, [&] { return cdns::launch_rk(D, stage, st); });
     }
   }

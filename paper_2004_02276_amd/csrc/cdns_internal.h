@@ -31,6 +31,7 @@ enum { DG_MASS = 0, DG_MX, DG_MY, DG_MZ, DG_E, DG_K, DG_RHOMIN, DG_PMIN, DG_MACH
 struct Desc {
   int nx, ny, nz, nxg;            // nxg = nx + 2*kHalo (row length of y ghost planes)
   long long N;                    // nx*ny*nz
+  double rnx, rny;                // 1/nx, 1/ny (node index decomposition)
   double dx, dz, deta;
   double idx, idz, ideta, idx2, idz2, ideta2;
   const double* y_eta;            // [ny]
@@ -52,9 +53,11 @@ struct Desc {
   const double* rprev[4];
   // work arrays
   uint8_t* nflag;                 // [N]
-  uint8_t* iflag;                 // [N] bit d: interface i+1/2 along d is shock-capturing
+  int* slot[3];                   // [N] per direction: position of interface i+1/2 in the
+                                  // direction's list if it is shock-capturing, else -1
   double* theta;                  // [N] optional sensor export (may be null)
-  double* Fw[3];                  // [5][N] shock-capturing interface fluxes per direction
+  double* Fw[3];                  // [5][N] shock-capturing interface fluxes per direction,
+                                  // compacted: entry e belongs to node list[d][e]
   int* list[3];                   // [N] compacted interface lists per direction
   unsigned* count;                // [4] list lengths
   double* gx[2];                  // [5][3][nz][ny] x-face ghost planes
@@ -74,6 +77,7 @@ struct Desc {
 
 // Host launchers (cdns_kernels.hip).  All enqueue on `st`.
 hipError_t launch_stage_begin(const Desc& D, hipStream_t st);
+bool ghosts_needed(const Desc& D);  // does launch_ghosts launch anything
 hipError_t launch_ghosts(const Desc& D, int stage, hipStream_t st);
 hipError_t launch_sensor(const Desc& D, int stage, bool export_theta, hipStream_t st);
 hipError_t launch_iflags(const Desc& D, hipStream_t st);
@@ -84,6 +88,8 @@ hipError_t launch_apply_force(const Desc& D, int stage, hipStream_t st);
 hipError_t launch_rk(const Desc& D, int stage, hipStream_t st);
 hipError_t launch_dt(const Desc& D, hipStream_t st);
 hipError_t launch_diag(const Desc& D, hipStream_t st);
+hipError_t launch_export_iflags(const Desc& D, uint8_t* out, hipStream_t st);
+hipError_t launch_export_iface(const Desc& D, int dir, double* out, hipStream_t st);
 bool rhs_tile_supported(int tx, int ty);
 int rhs_blocks(const Desc& D);
 

@@ -42,8 +42,56 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
+// periodic wrap of an index within one period of the range: -n <= i < 2n
+__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// q = n / d and rem = n % d for 0 <= n < 2^31, d >= 1, rd = 1/d: the double
+// estimate is within 2^-21 of the exact quotient, so truncation is off by at
+// most one and one correction step makes it exact.
+__device__ __forceinline__ int qdiv(int n, int d, double rd, int& rem) {
+  int q = (int)((double)n * rd);
+  int r = n - q * d;
+  if (r < 0) {
+    --q;
+    r += d;
+  } else if (r >= d) {
+    ++q;
+    r -= d;
+  }
+  rem = r;
+  return q;
+}
+
 __device__ __forceinline__ size_t nidx(const Desc& D, int i, int j, int k) {
   return ((size_t)k * D.ny + (size_t)j) * D.nx + (size_t)i;
+}
+
+__device__ __forceinline__ void from_prim(const Desc& D, double r, double u, double v, double w,
+                                          double p, double q[5]) {
+  q[0] = r;
+  q[1] = r * u;
+  q[2] = r * v;
+  q[3] = r * w;
+  q[4] = p / D.gm1 + 0.5 * r * (u * u + v * v + w * w);
+}
+
+// Ghost node of a staggered wall (y face `side`) from its mirror image qm:
+// velocity reversed, pressure copied, temperature 2 T_w - T (isothermal) or
+// T (adiabatic).  A non-positive ghost temperature is reported in the
+// status word.
+__device__ __forceinline__ void wall_ghost(const Desc& D, int kind, int side, const double qm[5],
+                                           double q[5]) {
+  const double rr = qm[0], ir = 1.0 / rr;
+  const double u = qm[1] * ir, v = qm[2] * ir, ww = qm[3] * ir;
+  const double T = (qm[4] * ir - 0.5 * (u * u + v * v + ww * ww)) * D.icv;
+  const double p = rr * D.R * T;
+  const double Tg = kind == BC_WALL_ISO ? 2.0 * D.bcp[2 + side][0] - T : T;
+  if (!(Tg > 0.0)) atomicOr(D.status, (unsigned)ST_BAD_GHOST);
+  from_prim(D, p / (D.R * Tg), -u, -v, -ww, p, q);
+}
+
+__host__ __device__ __forceinline__ bool is_wall(int kind) {
+  return kind == BC_WALL_ISO || kind == BC_WALL_ADIA;
 }
 
 // Conserved variables at any node index (interior, periodic image or ghost
@@ -330,14 +378,6 @@ __global__ void k_stage_begin(Desc D) {
 }
 
 // ------------------------------------------------------------------ ghost planes
-__device__ __forceinline__ void from_prim(const Desc& D, double r, double u, double v, double w,
-                                          double p, double q[5]) {
-  q[0] = r;
-  q[1] = r * u;
-  q[2] = r * v;
-  q[3] = r * w;
-  q[4] = p / D.gm1 + 0.5 * r * (u * u + v * v + w * w);
-}
 
 __device__ __forceinline__ void ghost_x_body(const Desc& D, const double* __restrict__ w, long long t) {
   // t over 2 * ny * nz (side, k, j)
@@ -412,17 +452,10 @@ __device__ __forceinline__ void ghost_y_body(const Desc& D, const double* __rest
   const size_t mst = (size_t)kHalo * D.nz * D.nxg;
   for (int s = 1; s <= kHalo; ++s) {
     double q[5];
-    if (kind == BC_WALL_ISO || kind == BC_WALL_ADIA) {
-      const int mj = side == 0 ? s - 1 : D.ny - s;
+    if (is_wall(kind)) {
       double qm[5];
-      load_node(D, w, i, mj, k, qm);
-      const double rr = qm[0], ir = 1.0 / rr;
-      const double u = qm[1] * ir, v = qm[2] * ir, ww = qm[3] * ir;
-      const double T = (qm[4] * ir - 0.5 * (u * u + v * v + ww * ww)) * D.icv;
-      const double p = rr * D.R * T;
-      const double Tg = kind == BC_WALL_ISO ? 2.0 * D.bcp[2 + side][0] - T : T;
-      if (!(Tg > 0.0)) atomicOr(D.status, (unsigned)ST_BAD_GHOST);
-      from_prim(D, p / (D.R * Tg), -u, -v, -ww, p, q);
+      load_node(D, w, i, side == 0 ? s - 1 : D.ny - s, k, qm);
+      wall_ghost(D, kind, side, qm, q);
     } else {  // imposed shock state
       const double* pr = D.bcp[2 + side];
       const int ish = (int)pr[0];
@@ -486,7 +519,7 @@ __device__ void sensor_tile(const Desc& D, const double* __restrict__ w, int lb,
   auto load = [&](int gi, int gj, int plane, bool fast, double& u, double& v, double& ww) {
     double q[5];
     if (fast) {
-      const size_t b = nidx(D, gi, gj, wrapi(plane, D.nz));
+      const size_t b = nidx(D, gi, gj, wrap1(plane, D.nz));  // plane in [-2, nz+1]
 #pragma unroll
       for (int m = 0; m < 4; ++m) q[m] = w[(size_t)m * N + b];
     } else {
@@ -501,7 +534,7 @@ __device__ void sensor_tile(const Desc& D, const double* __restrict__ w, int lb,
     S.v[0][ty + 2][tx + 2] = U[2];
     S.v[1][ty + 2][tx + 2] = V[2];
     S.v[2][ty + 2][tx + 2] = W[2];
-    const int kk = wrapi(c, D.nz);
+    const int kk = c;  // 0 <= c < nz
     for (int h = tid; h < 4 * kSenTX + 4 * kSenTY; h += 256) {
       int lx, ly;
       if (h < 4 * kSenTX) {  // two rows below and two above the tile
@@ -576,26 +609,6 @@ __device__ __forceinline__ uint8_t node_flag(const Desc& D, int i, int j, int k)
   return D.nflag[nidx(D, i, j, k)];
 }
 
-__device__ __forceinline__ uint8_t iface_bits(const Desc& D, long long n) {
-  const int i = (int)(n % D.nx);
-  const long long r = n / D.nx;
-  const int j = (int)(r % D.ny), k = (int)(r / D.ny);
-  uint8_t f = 0;
-  // boundary interfaces of non-periodic directions always use the central flux
-  const bool bx = !D.per_x && i == D.nx - 1, by = !D.per_y && j == D.ny - 1;
-  if (D.sensor_mode == 2) {
-    f = (uint8_t)((bx ? 0 : 1) | (by ? 0 : 2) | 4);
-  } else {
-    const uint8_t c0 = node_flag(D, i, j, k);
-    if (!bx && (c0 | node_flag(D, i - 1, j, k) | node_flag(D, i + 1, j, k) | node_flag(D, i + 2, j, k)))
-      f |= 1;
-    if (!by && (c0 | node_flag(D, i, j - 1, k) | node_flag(D, i, j + 1, k) | node_flag(D, i, j + 2, k)))
-      f |= 2;
-    if (c0 | node_flag(D, i, j, k - 1) | node_flag(D, i, j, k + 1) | node_flag(D, i, j, k + 2)) f |= 4;
-  }
-  return f;
-}
-
 // Exclusive prefix sum over the 256 threads of a block (fixed order); returns
 // the thread's offset and writes the block total to *tot.
 __device__ __forceinline__ unsigned block_scan256(unsigned v, unsigned* sm, unsigned* tot) {
@@ -619,53 +632,142 @@ __device__ __forceinline__ unsigned block_scan256(unsigned v, unsigned* sm, unsi
   return pre + x - v;
 }
 
+// 16 node flags (bytes 0/1) of one 128-bit word -> 16-bit mask.
+__device__ __forceinline__ unsigned flag_mask16(uint4 v) {
+  auto m4 = [](unsigned x) { return (x | (x >> 7) | (x >> 14) | (x >> 21)) & 0xFu; };
+  return m4(v.x) | (m4(v.y) << 4) | (m4(v.z) << 8) | (m4(v.w) << 12);
+}
+
+// Interface-flag masks (bit r = node n0+r) of 16 consecutive nodes that lie
+// in one x-row starting at i0 (row (j, k)); the node flags are read as
+// 128-bit words.
+__device__ __forceinline__ void iface_masks_row(const Desc& D, int n0, int i0, int j, int k,
+                                                unsigned& mx, unsigned& my, unsigned& mz) {
+  const uint4* nf = reinterpret_cast<const uint4*>(D.nflag);
+  const unsigned mc = flag_mask16(nf[n0 >> 4]);
+  const int rowstep = D.nx, plane = D.nx * D.ny;
+  // x: neighbours i0-1, i0+16, i0+17 beyond the word
+  const unsigned e = (unsigned)node_flag(D, i0 - 1, j, k) | (mc << 1) |
+                     ((unsigned)node_flag(D, i0 + 16, j, k) << 17) |
+                     ((unsigned)node_flag(D, i0 + 17, j, k) << 18);
+  mx = (e | (e >> 1) | (e >> 2) | (e >> 3)) & 0xFFFFu;
+  if (!D.per_x && i0 + 16 == D.nx) mx &= 0x7FFFu;  // last x interface is a boundary
+  // y: rows j-1, j+1, j+2 (non-periodic rows beyond the walls are unflagged)
+  unsigned oy = mc;
+  const int jj[3] = {j - 1, j + 1, j + 2};
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    int t = jj[q];
+    if (t < 0 || t >= D.ny) {
+      if (!D.per_y) continue;
+      t = wrapi(t, D.ny);
+    }
+    oy |= flag_mask16(nf[(n0 + (t - j) * rowstep) >> 4]);
+  }
+  my = (!D.per_y && j == D.ny - 1) ? 0u : oy;
+  // z: planes k-1, k+1, k+2 (periodic)
+  unsigned oz = mc;
+  const int kk[3] = {k - 1, k + 1, k + 2};
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int t = wrapi(kk[q], D.nz);
+    oz |= flag_mask16(nf[(n0 + (t - k) * plane) >> 4]);
+  }
+  mz = oz;
+}
+
 // Interface flags of a range of kIflagsPer*256 nodes and their compaction
 // into the per-direction lists: one atomic per direction and block reserves
-// the block's segment; each thread owns kIflagsPer consecutive nodes, so
-// the segment is in node order and the shock-capturing kernel reading the
-// list touches consecutive nodes in consecutive lanes.
+// the block's segment; each thread owns kIflagsPer consecutive nodes, the
+// block stages its entries in LDS and writes the segment with coalesced
+// stores, so the segment is in node order and the shock-capturing kernel
+// reading the list touches consecutive nodes in consecutive lanes.
 constexpr int kIflagsPer = 16;
 
 __device__ __forceinline__ void iflags_body(const Desc& D, long long blk) {
   __shared__ unsigned sm[4];
   __shared__ unsigned base[3];
-  const long long n0 = blk * (256LL * kIflagsPer) + (long long)threadIdx.x * kIflagsPer;
-  unsigned cnt[3] = {0u, 0u, 0u};
-  uint8_t fl[kIflagsPer];
-#pragma unroll
-  for (int r = 0; r < kIflagsPer; ++r) {
-    const long long n = n0 + r;
-    uint8_t f = 0;
-    if (n < D.N) f = iface_bits(D, n);
-    fl[r] = f;
-    cnt[0] += f & 1;
-    cnt[1] += (f >> 1) & 1;
-    cnt[2] += (f >> 2) & 1;
+  __shared__ uint16_t seg[3][256 * kIflagsPer];  // entries as offsets from the block start
+  const int N = (int)D.N;  // below 2^31 (checked at creation)
+  const int nb = (int)blk * (256 * kIflagsPer);
+  const int n0 = nb + (int)threadIdx.x * kIflagsPer;
+  unsigned mx = 0u, my = 0u, mz = 0u;
+  if (n0 < N) {
+    const int i0 = n0 % D.nx;
+    const int rr = n0 / D.nx;
+    int j = rr % D.ny, k = rr / D.ny;
+    if (D.sensor_mode == 1 && D.nx % kIflagsPer == 0 && n0 + kIflagsPer <= N) {
+      iface_masks_row(D, n0, i0, j, k, mx, my, mz);
+    } else {
+      // general shape: walk the nodes with incremental indices.  An
+      // interface is shock-capturing when a node of its central stencil is
+      // flagged; boundary interfaces of non-periodic directions never are.
+      int i = i0;
+      for (int r = 0; r < kIflagsPer && n0 + r < N; ++r) {
+        uint8_t f;
+        const bool bx = !D.per_x && i == D.nx - 1, by = !D.per_y && j == D.ny - 1;
+        if (D.sensor_mode == 2) {
+          f = (uint8_t)((bx ? 0 : 1) | (by ? 0 : 2) | 4);
+        } else {
+          f = 0;
+          const uint8_t c0 = node_flag(D, i, j, k);
+          if (!bx && (c0 | node_flag(D, i - 1, j, k) | node_flag(D, i + 1, j, k) |
+                      node_flag(D, i + 2, j, k)))
+            f |= 1;
+          if (!by && (c0 | node_flag(D, i, j - 1, k) | node_flag(D, i, j + 1, k) |
+                      node_flag(D, i, j + 2, k)))
+            f |= 2;
+          if (c0 | node_flag(D, i, j, k - 1) | node_flag(D, i, j, k + 1) | node_flag(D, i, j, k + 2))
+            f |= 4;
+        }
+        mx |= (unsigned)(f & 1) << r;
+        my |= (unsigned)((f >> 1) & 1) << r;
+        mz |= (unsigned)((f >> 2) & 1) << r;
+        if (++i == D.nx) {
+          i = 0;
+          if (++j == D.ny) {
+            j = 0;
+            ++k;
+          }
+        }
+      }
+    }
   }
-  if (n0 + kIflagsPer <= D.N) {  // 16 flag bytes in one 128-bit store (n0 is 16-aligned)
-    unsigned wd[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      wd[q] = (unsigned)fl[4 * q] | ((unsigned)fl[4 * q + 1] << 8) | ((unsigned)fl[4 * q + 2] << 16) |
-              ((unsigned)fl[4 * q + 3] << 24);
-    reinterpret_cast<uint4*>(D.iflag)[n0 / kIflagsPer] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
-  } else {
-#pragma unroll
-    for (int r = 0; r < kIflagsPer; ++r)
-      if (n0 + r < D.N) D.iflag[n0 + r] = fl[r];
-  }
+  const unsigned msk[3] = {mx, my, mz};
   unsigned off[3], tot[3];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) off[d] = block_scan256(cnt[d], sm, &tot[d]);
+  for (int d = 0; d < 3; ++d) off[d] = block_scan256((unsigned)__popc(msk[d]), sm, &tot[d]);
   if (threadIdx.x < 3) base[threadIdx.x] = tot[threadIdx.x] ? atomicAdd(&D.count[threadIdx.x], tot[threadIdx.x]) : 0u;
+  const uint16_t loc = (uint16_t)(threadIdx.x * kIflagsPer);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    unsigned m = msk[d], p = off[d];
+    while (m) {
+      const int r = __ffs(m) - 1;
+      m &= m - 1u;
+      seg[d][p++] = (uint16_t)(loc + r);
+    }
+  }
   __syncthreads();
-  unsigned pos[3] = {base[0] + off[0], base[1] + off[1], base[2] + off[2]};
 #pragma unroll
-  for (int r = 0; r < kIflagsPer; ++r) {
-    const long long n = n0 + r;
+  for (int d = 0; d < 3; ++d) {
+    int* __restrict__ out = D.list[d] + base[d];
+    for (unsigned e = threadIdx.x; e < tot[d]; e += 256u) out[e] = nb + (int)seg[d][e];
+    // list position of every flagged node of the thread, -1 for the others
+    int sl[kIflagsPer];
+    int p = (int)(base[d] + off[d]);
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
-      if ((fl[r] >> d) & 1) D.list[d][pos[d]++] = (int)n;
+    for (int r = 0; r < kIflagsPer; ++r) sl[r] = ((msk[d] >> r) & 1u) ? p++ : -1;
+    if (n0 + kIflagsPer <= N) {  // n0 is 16-aligned: four 128-bit stores
+      int4* o4 = reinterpret_cast<int4*>(D.slot[d] + n0);
+#pragma unroll
+      for (int q = 0; q < kIflagsPer / 4; ++q)
+        o4[q] = make_int4(sl[4 * q], sl[4 * q + 1], sl[4 * q + 2], sl[4 * q + 3]);
+    } else {
+#pragma unroll
+      for (int r = 0; r < kIflagsPer; ++r)
+        if (n0 + r < N) D.slot[d][n0 + r] = sl[r];
+    }
   }
   __syncthreads();
 }
@@ -674,16 +776,27 @@ __global__ void __launch_bounds__(256) k_iflags(Desc D) { iflags_body(D, blockId
 
 // ------------------------------------------------------------------ WENO on lists
 template <typename F, int DIR>
-__device__ void weno_entry(const Desc& D, const double* __restrict__ w, int n) {
-  const int i = n % D.nx;
-  const int r = n / D.nx;
-  const int j = r % D.ny, k = r / D.ny;
+__device__ void weno_entry(const Desc& D, const double* __restrict__ w, int n, unsigned e) {
+  int i, j;
+  const int k = qdiv(qdiv(n, D.nx, D.rnx, i), D.ny, D.rny, j);
   // all 30 loads are issued before any arithmetic (latency-bound kernel)
   double qn[6][5];
+  const int c = DIR == 0 ? i : (DIR == 1 ? j : k);
+  const int nd = DIR == 0 ? D.nx : (DIR == 1 ? D.ny : D.nz);
+  if (c >= 2 && c + 3 < nd) {  // stencil inside the interior: direct addressing
+    const long long st = DIR == 0 ? 1LL : (DIR == 1 ? (long long)D.nx : (long long)D.nx * D.ny);
+    const double* __restrict__ b = w + (n - 2 * st);
 #pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    const int o = s - 2;
-    load_node(D, w, i + (DIR == 0 ? o : 0), j + (DIR == 1 ? o : 0), k + (DIR == 2 ? o : 0), qn[s]);
+    for (int s = 0; s < 6; ++s)
+#pragma unroll
+      for (int m = 0; m < 5; ++m) qn[s][m] = b[m * D.N + s * st];
+  } else {
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const int o = s - 2;
+      load_node(D, w, i + (DIR == 0 ? o : 0), j + (DIR == 1 ? o : 0), k + (DIR == 2 ? o : 0),
+                qn[s]);
+    }
   }
   auto get = [&](int s, double q[5]) {
 #pragma unroll
@@ -693,7 +806,7 @@ __device__ void weno_entry(const Desc& D, const double* __restrict__ w, int n) {
   weno_flux<F, DIR>(D, get, f);
   double* out = D.Fw[DIR];
 #pragma unroll
-  for (int m = 0; m < 5; ++m) out[(size_t)m * D.N + n] = (double)f[m];
+  for (int m = 0; m < 5; ++m) out[(size_t)m * D.N + e] = (double)f[m];
 }
 
 template <typename F>
@@ -710,9 +823,9 @@ __global__ void __launch_bounds__(256) k_weno(Desc D, int stage) {
   const unsigned e1 = min(cnt, (lb + 1) * per);
   for (unsigned e = lb * per + threadIdx.x; e < e1; e += 256u) {
     const int n = D.list[dir][e];
-    if (dir == 0) weno_entry<F, 0>(D, w, n);
-    else if (dir == 1) weno_entry<F, 1>(D, w, n);
-    else weno_entry<F, 2>(D, w, n);
+    if (dir == 0) weno_entry<F, 0>(D, w, n, e);
+    else if (dir == 1) weno_entry<F, 1>(D, w, n, e);
+    else weno_entry<F, 2>(D, w, n, e);
   }
 }
 
@@ -801,7 +914,7 @@ __device__ void rhs_body(const Desc& D, int stage, int lb, RhsSmem<F, TX, TY>& S
   auto load_col = [&](int plane, PV<F>& s) {
     double q[5];
     if (col_in) {
-      const size_t b = nidx(D, i, j, wrapi(plane, D.nz));
+      const size_t b = nidx(D, i, j, wrap1(plane, D.nz));  // plane in [-2, nz+3], nz >= 4
 #pragma unroll
       for (int m = 0; m < 5; ++m) q[m] = w[(size_t)m * N + b];
     } else {
@@ -833,7 +946,7 @@ __device__ void rhs_body(const Desc& D, int stage, int lb, RhsSmem<F, TX, TY>& S
     // stage plane c into LDS: interior from the window, halo cooperatively
     lds_store<F, TX, TY>(S, ty + 2, tx + 2, full(2, c));
     {
-      const int kk = wrapi(c, D.nz);
+      const int kk = wrap1(c, D.nz);
       for (int h = tid; h < NH; h += NT) {
         int lx, ly;
         if (h < 2 * LX) {
@@ -876,15 +989,11 @@ __device__ void rhs_body(const Desc& D, int stage, int lb, RhsSmem<F, TX, TY>& S
     // z-direction interface flux at c+1/2 (own column)
     F Fzp[5] = {F(0), F(0), F(0), F(0), F(0)};
     if (c >= kb - 1 && c < ke && valid) {
-      bool wz = false;
-      size_t nc = 0;
-      if (hybrid) {
-        nc = nidx(D, i, j, wrapi(c, D.nz));
-        wz = (D.iflag[nc] >> 2) & 1;
-      }
-      if (wz) {
+      int ez = -1;
+      if (hybrid) ez = D.slot[2][nidx(D, i, j, wrap1(c, D.nz))];
+      if (ez >= 0) {
 #pragma unroll
-        for (int m = 0; m < 5; ++m) Fzp[m] = (F)D.Fw[2][(size_t)m * N + nc];
+        for (int m = 0; m < 5; ++m) Fzp[m] = (F)D.Fw[2][(size_t)m * N + ez];
       } else {
         cflux<F, 2>(full(1, c - 1), full(2, c), full(3, c + 1), full(4, c + 2), Fzp);
       }
@@ -892,12 +1001,7 @@ __device__ void rhs_body(const Desc& D, int stage, int lb, RhsSmem<F, TX, TY>& S
     if (c >= kb && c < ke && valid) {
       const double didx = D.idx, diy = D.iy[j], didz = D.idz;
       double acc[5];
-      size_t n0 = 0;
-      uint8_t f0 = 0;
-      if (hybrid) {
-        n0 = nidx(D, i, j, c);
-        f0 = D.iflag[n0];
-      }
+      const size_t n0 = nidx(D, i, j, c);
       // x direction: interfaces i-1/2, i+1/2 from the LDS row
       {
         F fr[5], fl[5];
@@ -910,15 +1014,16 @@ __device__ void rhs_body(const Desc& D, int stage, int lb, RhsSmem<F, TX, TY>& S
         cflux<F, 0>(b, cc, d, e, fr);
         cflux<F, 0>(a, b, cc, d, fl);
         if (hybrid) {
-          if (f0 & 1) {
+          const int er = D.slot[0][n0];
+          if (er >= 0) {
 #pragma unroll
-            for (int m = 0; m < 5; ++m) fr[m] = (F)D.Fw[0][(size_t)m * N + n0];
+            for (int m = 0; m < 5; ++m) fr[m] = (F)D.Fw[0][(size_t)m * N + er];
           }
           if (i > 0 || D.per_x) {
-            const size_t nl = nidx(D, i > 0 ? i - 1 : D.nx - 1, j, c);
-            if (D.iflag[nl] & 1) {
+            const int el = D.slot[0][i > 0 ? n0 - 1 : n0 + (D.nx - 1)];
+            if (el >= 0) {
 #pragma unroll
-              for (int m = 0; m < 5; ++m) fl[m] = (F)D.Fw[0][(size_t)m * N + nl];
+              for (int m = 0; m < 5; ++m) fl[m] = (F)D.Fw[0][(size_t)m * N + el];
             }
           }
         }
@@ -942,15 +1047,16 @@ __device__ void rhs_body(const Desc& D, int stage, int lb, RhsSmem<F, TX, TY>& S
         if (wall_lo) wflux<F, 1>(a, b, cc, d, fl);
         else cflux<F, 1>(a, b, cc, d, fl);
         if (hybrid) {
-          if (f0 & 2) {
+          const int er = D.slot[1][n0];
+          if (er >= 0) {
 #pragma unroll
-            for (int m = 0; m < 5; ++m) fr[m] = (F)D.Fw[1][(size_t)m * N + n0];
+            for (int m = 0; m < 5; ++m) fr[m] = (F)D.Fw[1][(size_t)m * N + er];
           }
           if (j > 0 || D.per_y) {
-            const size_t nl = nidx(D, i, j > 0 ? j - 1 : D.ny - 1, c);
-            if (D.iflag[nl] & 2) {
+            const int el = D.slot[1][j > 0 ? n0 - D.nx : n0 + (size_t)(D.ny - 1) * D.nx];
+            if (el >= 0) {
 #pragma unroll
-              for (int m = 0; m < 5; ++m) fl[m] = (F)D.Fw[1][(size_t)m * N + nl];
+              for (int m = 0; m < 5; ++m) fl[m] = (F)D.Fw[1][(size_t)m * N + el];
             }
           }
         }
@@ -1078,7 +1184,7 @@ __device__ __forceinline__ int xcd_swizzle(int b, int nb) {
 }
 
 template <typename F, int TX, int TY>
-__global__ void __launch_bounds__(TX* TY) k_rhs(Desc D, int stage) {
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) k_rhs(Desc D, int stage) {
   __shared__ RhsSmem<F, TX, TY> S;
   const int lb = xcd_swizzle(blockIdx.x, gridDim.x);
   rhs_body<F, TX, TY>(D, stage, lb, S);
@@ -1336,6 +1442,8 @@ hipError_t launch_stage_begin(const Desc& D, hipStream_t st) {
   return hipGetLastError();
 }
 
+bool ghosts_needed(const Desc& D) { return !D.per_x || !D.per_y; }
+
 hipError_t launch_ghosts(const Desc& D, int stage, hipStream_t st) {
   if (!D.per_x) k_ghost_x<<<nblk(2LL * D.ny * D.nz, 128), 128, 0, st>>>(D, stage);
   if (!D.per_y) k_ghost_y<<<nblk(2LL * D.nz * D.nxg, 128), 128, 0, st>>>(D, stage);
@@ -1344,6 +1452,30 @@ hipError_t launch_ghosts(const Desc& D, int stage, hipStream_t st) {
 
 hipError_t launch_sensor(const Desc& D, int stage, bool export_theta, hipStream_t st) {
   k_sensor<<<sensor_tiles(D), 256, 0, st>>>(D, stage, export_theta ? 1 : 0);
+  return hipGetLastError();
+}
+
+__global__ void k_export_iflags(Desc D, uint8_t* __restrict__ out) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= D.N) return;
+  out[n] = (uint8_t)((D.slot[0][n] >= 0 ? 1 : 0) | (D.slot[1][n] >= 0 ? 2 : 0) |
+                     (D.slot[2][n] >= 0 ? 4 : 0));
+}
+
+__global__ void k_export_iface(Desc D, int dir, double* __restrict__ out) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= D.N) return;
+  const int e = D.slot[dir][n];
+  for (int m = 0; m < 5; ++m) out[(size_t)m * D.N + n] = e >= 0 ? D.Fw[dir][(size_t)m * D.N + e] : 0.0;
+}
+
+hipError_t launch_export_iflags(const Desc& D, uint8_t* out, hipStream_t st) {
+  k_export_iflags<<<nblk(D.N, 256), 256, 0, st>>>(D, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_iface(const Desc& D, int dir, double* out, hipStream_t st) {
+  k_export_iface<<<nblk(D.N, 256), 256, 0, st>>>(D, dir, out);
   return hipGetLastError();
 }
 
@@ -1523,16 +1655,16 @@ __global__ void __launch_bounds__(256) k_b_weno(const Desc* __restrict__ descs,
       const unsigned cnt = D.count[dir];
       for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x) {
         const int n = D.list[dir][e];
-        if (dir == 0) weno_entry<F, 0>(D, w, n);
-        else if (dir == 1) weno_entry<F, 1>(D, w, n);
-        else weno_entry<F, 2>(D, w, n);
+        if (dir == 0) weno_entry<F, 0>(D, w, n, e);
+        else if (dir == 1) weno_entry<F, 1>(D, w, n, e);
+        else weno_entry<F, 2>(D, w, n, e);
       }
     }
   }
 }
 
 template <typename F, int TX, int TY>
-__global__ void __launch_bounds__(TX* TY) k_b_rhs(const Desc* __restrict__ descs,
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) k_b_rhs(const Desc* __restrict__ descs,
                                                   const BatchTable* __restrict__ T, int stage) {
   __shared__ RhsSmem<F, TX, TY> S;
   BATCH_FOR(WK_RHS)

@@ -111,6 +111,31 @@ def test_rhs_parity(torch_cuda, case):
     assert max(errs) <= RHS_TOL, errs
 
 
+IFACE_CASES = ["dit24_hybrid", "sbli_64x32x8", "channel_70x22x10", "dit24_weno_all"]
+
+
+@pytest.mark.parametrize("case", IFACE_CASES)
+def test_weno_interface_fluxes(torch_cuda, case):
+    """Shock-capturing interface fluxes, per direction, at every flagged
+    interface (compacted on the GPU, scattered back by the export hook)."""
+    from paper_2004_02276_amd import Solver
+    pr = RHS_CASES[case]()
+    say(f"[iface flux] {case} {pr.nx}x{pr.ny}x{pr.nz}")
+    s = Solver(pr)
+    s.rhs(s.state)
+    ifl = s.export_sensor()[2].cpu().numpy()
+    fg = [s.export_iface_flux(d).cpu().numpy() for d in range(3)]
+    s.close()
+    for d in range(3):
+        mask = ((ifl >> d) & 1).astype(bool)
+        assert mask.any(), f"no shock-capturing interface along {d}"
+        fo = oracle.iface_flux(pr, d)
+        for m in range(5):
+            scale = max(np.abs(fo[m][mask]).max(), 1e-300)
+            err = np.abs(fg[d][m][mask] - fo[m][mask]).max() / scale
+            assert err <= 1e-13, (d, m, err)
+
+
 @pytest.mark.parametrize("tiling", [(64, 4, 3), (32, 8, 5), (64, 2, 7), (128, 2, 16)])
 def test_rhs_independent_of_tiling(torch_cuda, tiling):
     pr = P.small_sbli(100, 36, 12, theta_star=0.02)
