@@ -258,25 +258,45 @@ __device__ __forceinline__ void wflux(const PV<F>& a, const PV<F>& b, const PV<F
 }
 
 // WENO5 (Jiang-Shu) at the right face of v0 from (v-2, v-1, v0, v1, v2).
+// Reciprocal used by the shock-capturing flux: in FP64 the hardware estimate
+// refined by two Newton steps (within one ulp of 1/x for normal x, not
+// correctly rounded), in FP32 the ordinary division.
 template <typename F>
-__device__ __forceinline__ F weno5(F vm2, F vm1, F v0, F vp1, F vp2) {
+__device__ __forceinline__ F wrcp(F x) {
+  return F(1) / x;
+}
+template <>
+__device__ __forceinline__ double wrcp<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// WENO5-JS reconstruction at i+1/2 from v_{i-2..i+2}.  The argument `eps4`
+// is four times the regulariser: the callers pass twice the split fluxes
+// (the factor 1/2 of the splitting is applied once to the sum), and
+// scaling the inputs by 2 scales the smoothness indicators by exactly 4,
+// so the weights are those of the unscaled reconstruction.
+template <typename F>
+__device__ __forceinline__ F weno5(F vm2, F vm1, F v0, F vp1, F vp2, F eps4) {
   const F q0 = (F(2) * vm2 - F(7) * vm1 + F(11) * v0) * F(1.0 / 6.0);
   const F q1 = (-vm1 + F(5) * v0 + F(2) * vp1) * F(1.0 / 6.0);
   const F q2 = (F(2) * v0 + F(5) * vp1 - vp2) * F(1.0 / 6.0);
   const F d0 = vm2 - F(2) * vm1 + v0, e0 = vm2 - F(4) * vm1 + F(3) * v0;
   const F d1 = vm1 - F(2) * v0 + vp1, e1 = vm1 - vp1;
   const F d2 = v0 - F(2) * vp1 + vp2, e2 = F(3) * v0 - F(4) * vp1 + vp2;
-  const F eps = F(1e-6);
-  const F s0 = eps + F(13.0 / 12.0) * d0 * d0 + F(0.25) * e0 * e0;
-  const F s1 = eps + F(13.0 / 12.0) * d1 * d1 + F(0.25) * e1 * e1;
-  const F s2 = eps + F(13.0 / 12.0) * d2 * d2 + F(0.25) * e2 * e2;
+  const F s0 = eps4 + F(13.0 / 12.0) * d0 * d0 + F(0.25) * e0 * e0;
+  const F s1 = eps4 + F(13.0 / 12.0) * d1 * d1 + F(0.25) * e1 * e1;
+  const F s2 = eps4 + F(13.0 / 12.0) * d2 * d2 + F(0.25) * e2 * e2;
   // weights d_k/(eps+beta_k)^2 normalised, with numerator and denominator
   // multiplied by the product of the three squares: one division
   const F t0 = s0 * s0, t1 = s1 * s1, t2 = s2 * s2;
   const F a0 = F(0.1) * (t1 * t2);
   const F a1 = F(0.6) * (t0 * t2);
   const F a2 = F(0.3) * (t0 * t1);
-  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+  return (a0 * q0 + a1 * q1 + a2 * q2) * wrcp<F>(a0 + a1 + a2);
 }
 
 // Lax-Friedrichs split characteristic WENO5 flux at interface i+1/2 along
@@ -294,7 +314,7 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
     get(2, qa);
     get(3, qb);
     const F ra = (F)qa[0], rb = (F)qb[0];
-    const F ira = F(1) / ra, irb = F(1) / rb;
+    const F ira = wrcp<F>(ra), irb = wrcp<F>(rb);
     const F una = (F)qa[PN] * ira, t1a = (F)qa[P1] * ira, t2a = (F)qa[P2] * ira;
     const F unb = (F)qb[PN] * irb, t1b = (F)qb[P1] * irb, t2b = (F)qb[P2] * irb;
     const F Ea = (F)qa[4], Eb = (F)qb[4];
@@ -302,7 +322,7 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
     const F pb = gm1 * (Eb - F(0.5) * rb * (unb * unb + t1b * t1b + t2b * t2b));
     const F Ha = (Ea + pa) * ira, Hb = (Eb + pb) * irb;
     const F sl = sqrt(ra), sr = sqrt(rb);
-    const F iw = F(1) / (sl + sr);
+    const F iw = wrcp<F>(sl + sr);
     ur = (sl * una + sr * unb) * iw;
     vr = (sl * t1a + sr * t1b) * iw;
     wr = (sl * t2a + sr * t2b) * iw;
@@ -310,7 +330,7 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
   }
   const F q2 = ur * ur + vr * vr + wr * wr;
   const F cr = sqrt(gm1 * (Hr - F(0.5) * q2));
-  const F ic = F(1) / cr;
+  const F ic = wrcp<F>(cr);
   const F b1 = gm1 * ic * ic;
   const F b2 = F(0.5) * q2 * b1;
   // Projection on the left eigenvectors (permuted order rho, m_n, m_t1,
@@ -334,7 +354,7 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
     double qd[5];
     get(s, qd);
     const F r = (F)qd[0];
-    const F ir = F(1) / r;
+    const F ir = wrcp<F>(r);
     const F mn = (F)qd[PN], m1 = (F)qd[P1], m2 = (F)qd[P2], E = (F)qd[4];
     const F un = mn * ir, t1 = m1 * ir, t2 = m2 * ir;
     const F p = gm1 * (E - F(0.5) * r * (un * un + t1 * t1 + t2 * t2));
@@ -348,13 +368,16 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
     am4 = fmax(am4, fabs(un + c));
   }
   const F alpha[5] = {am0, am1, am1, am1, am4};
+  const F eps4 = F(4) * F(1e-6);  // exact power-of-two multiple of the regulariser
   F gh[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     const F a = alpha[k];
-#define GP(s) (F(0.5) * (g[s][k] + a * v[s][k]))
-#define GM(s) (F(0.5) * (g[s][k] - a * v[s][k]))
-    gh[k] = weno5<F>(GP(0), GP(1), GP(2), GP(3), GP(4)) + weno5<F>(GM(5), GM(4), GM(3), GM(2), GM(1));
+    // twice the Lax-Friedrichs split characteristic fluxes g+- = (g +- a v)/2
+#define GP(s) (g[s][k] + a * v[s][k])
+#define GM(s) (g[s][k] - a * v[s][k])
+    gh[k] = F(0.5) * (weno5<F>(GP(0), GP(1), GP(2), GP(3), GP(4), eps4) +
+                      weno5<F>(GM(5), GM(4), GM(3), GM(2), GM(1), eps4));
 #undef GP
 #undef GM
   }
