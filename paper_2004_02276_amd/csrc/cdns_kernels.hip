@@ -257,7 +257,6 @@ __device__ __forceinline__ void wflux(const PV<F>& a, const PV<F>& b, const PV<F
   else wall_flux<F, DIR>(a, b, c, d, f);
 }
 
-// WENO5 (Jiang-Shu) at the right face of v0 from (v-2, v-1, v0, v1, v2).
 // Reciprocal used by the shock-capturing flux: in FP64 the hardware estimate
 // refined by two Newton steps (within one ulp of 1/x for normal x, not
 // correctly rounded), in FP32 the ordinary division.
@@ -799,7 +798,7 @@ __global__ void __launch_bounds__(256) k_iflags(Desc D) { iflags_body(D, blockId
 
 // ------------------------------------------------------------------ WENO on lists
 template <typename F, int DIR>
-__device__ void weno_entry(const Desc& D, const double* __restrict__ w, int n, unsigned e) {
+__device__ __forceinline__ void weno_entry(const Desc& D, const double* __restrict__ w, int n, unsigned e) {
   int i, j;
   const int k = qdiv(qdiv(n, D.nx, D.rnx, i), D.ny, D.rny, j);
   // all 30 loads are issued before any arithmetic (latency-bound kernel)
@@ -833,10 +832,9 @@ __device__ void weno_entry(const Desc& D, const double* __restrict__ w, int n, u
 }
 
 template <typename F>
-__global__ void __launch_bounds__(256) k_weno(Desc D, int stage) {
+__global__ void __launch_bounds__(256) k_weno(Desc D, const double* __restrict__ w) {
   const int dir = blockIdx.y;
   const unsigned cnt = D.count[dir];
-  const double* w = D.win[stage];
   // each block streams through one contiguous segment of the list, and
   // consecutive segments sit on the same XCD: neighbouring interfaces share
   // stencil nodes in that XCD's L2
@@ -887,7 +885,8 @@ __device__ __forceinline__ void lds_store(RhsSmem<F, TX, TY>& S, int ly, int lx,
 
 // One block of the fused kernel: tile (tile index lb) of the instance D.
 template <typename F, int TX, int TY>
-__device__ void rhs_body(const Desc& D, int stage, int lb, RhsSmem<F, TX, TY>& S) {
+__device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict__ w, double* __restrict__ R,
+                         int lb, RhsSmem<F, TX, TY>& S) {
   constexpr int LX = TX + 4, LY = TY + 4;
   constexpr int NT = TX * TY;
   constexpr int NH = LX * LY - TX * TY;
@@ -904,8 +903,6 @@ __device__ void rhs_body(const Desc& D, int stage, int lb, RhsSmem<F, TX, TY>& S
   const bool valid = i < D.nx && j < D.ny;
   const bool col_in = valid;
   const bool tile_in = i0 >= 2 && i0 + TX + 2 <= D.nx && j0 >= 2 && j0 + TY + 2 <= D.ny;
-  const double* __restrict__ w = D.win[stage];
-  double* __restrict__ R = D.rcur[stage];
   const size_t N = (size_t)D.N;
   const int jc = j < D.ny ? j : D.ny - 1;
   const F idx = (F)D.idx, idz = (F)D.idz, idx2 = (F)D.idx2, idz2 = (F)D.idz2;
@@ -1207,10 +1204,11 @@ __device__ __forceinline__ int xcd_swizzle(int b, int nb) {
 }
 
 template <typename F, int TX, int TY>
-__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) k_rhs(Desc D, int stage) {
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2)))
+k_rhs(Desc D, const double* __restrict__ w, double* __restrict__ R) {
   __shared__ RhsSmem<F, TX, TY> S;
   const int lb = xcd_swizzle(blockIdx.x, gridDim.x);
-  rhs_body<F, TX, TY>(D, stage, lb, S);
+  rhs_body<F, TX, TY>(D, w, R, lb, S);
 }
 
 // ------------------------------------------------------------------ reductions
@@ -1273,7 +1271,16 @@ __global__ void k_apply_force(Desc D, int stage) {
 }
 
 // ------------------------------------------------------------------ RK3 update
-__device__ __forceinline__ void rk_point(const Desc& D, int stage, long long n, double f) {
+// Low-storage RK3 stage (Sec. 2.2): w' = w + dt (beta_s R_s + alpha_s R_{s-1}),
+// with the bulk force (reduced beforehand) added to R_s, which is stored
+// back for the next stage.  Every load of the thread's points is issued
+// before any store, so the loads of all three input streams are in flight
+// together.
+constexpr int kRkPer = 2;  // points per thread of the update kernel
+
+template <int stage>
+__device__ __forceinline__ void rk_block_s(const Desc& D, long long blk) {
+  const double f = D.forcing ? D.scal[SC_FORCE] : 0.0;  // reduced by the forcing kernel
   const double alpha = stage == 0 ? 0.0 : (stage == 1 ? -17.0 / 60.0 : -5.0 / 12.0);
   const double beta = stage == 0 ? 8.0 / 15.0 : (stage == 1 ? 5.0 / 12.0 : 3.0 / 4.0);
   const double* __restrict__ w = D.win[stage];
@@ -1282,43 +1289,53 @@ __device__ __forceinline__ void rk_point(const Desc& D, int stage, long long n, 
   const double* __restrict__ Rp = D.rprev[stage];
   const size_t N = (size_t)D.N;
   const double dt = D.scal[SC_DT];
-  double q[5], r[5];
+  long long n[kRkPer];
+  double q[kRkPer][5], r[kRkPer][5], rp[kRkPer][5];
 #pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    q[m] = w[m * N + n];
-    r[m] = R[m * N + n];
-  }
-  if (D.forcing) {
-    r[1] += f;
-    r[4] += f * (q[1] * (1.0 / q[0]));
-    if (stage < 2) {
-      R[1 * N + n] = r[1];
-      R[4 * N + n] = r[4];
+  for (int p = 0; p < kRkPer; ++p) {
+    n[p] = (blk * kRkPer + p) * 256 + threadIdx.x;
+    // points past the end load the last point (unconditional loads stay
+    // in flight together) and store nothing
+    const size_t c = (size_t)(n[p] < D.N ? n[p] : D.N - 1);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      q[p][m] = w[m * N + c];
+      r[p][m] = R[m * N + c];
+      if (stage > 0) rp[p][m] = Rp[m * N + c];
     }
   }
-  double o[5];
+  bool bad = false;
 #pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    double acc = beta * r[m];
-    if (stage > 0) acc += alpha * Rp[m * N + n];
-    o[m] = q[m] + dt * acc;
-    wo[m * N + n] = o[m];
+  for (int p = 0; p < kRkPer; ++p) {
+    if (n[p] >= D.N) continue;
+    if (D.forcing) {
+      r[p][1] += f;
+      r[p][4] += f * (q[p][1] * (1.0 / q[p][0]));
+      if (stage < 2) {
+        R[1 * N + n[p]] = r[p][1];
+        R[4 * N + n[p]] = r[p][4];
+      }
+    }
+    double o[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      double acc = beta * r[p][m];
+      if (stage > 0) acc += alpha * rp[p][m];
+      o[m] = q[p][m] + dt * acc;
+      wo[m * N + n[p]] = o[m];
+    }
+    const double ke = 0.5 * (o[1] * o[1] + o[2] * o[2] + o[3] * o[3]) / o[0];
+    const double pe = o[4] - ke;
+    bad |= !(o[0] > 0.0) || !(pe > 0.0) || !(fabs(o[4]) < 1e300);
   }
-  const double ke = 0.5 * (o[1] * o[1] + o[2] * o[2] + o[3] * o[3]) / o[0];
-  const double pe = o[4] - ke;
-  if (!(o[0] > 0.0) || !(pe > 0.0) || !(fabs(o[4]) < 1e300)) atomicOr(D.status, (unsigned)ST_BAD_STATE);
+  if (bad) atomicOr(D.status, (unsigned)ST_BAD_STATE);
 }
-
-constexpr int kRkPer = 4;  // points per thread of the update kernel
 
 __device__ __forceinline__ void rk_block(const Desc& D, int stage, long long blk, double* sm) {
   (void)sm;
-  const double f = D.forcing ? D.scal[SC_FORCE] : 0.0;  // reduced by the forcing kernel
-#pragma unroll
-  for (int r = 0; r < kRkPer; ++r) {
-    const long long n = (blk * kRkPer + r) * 256 + threadIdx.x;
-    if (n < D.N) rk_point(D, stage, n, f);
-  }
+  if (stage == 0) rk_block_s<0>(D, blk);
+  else if (stage == 1) rk_block_s<1>(D, blk);
+  else rk_block_s<2>(D, blk);
 }
 
 __global__ void __launch_bounds__(256) k_rk(Desc D, int stage) {
@@ -1511,8 +1528,8 @@ hipError_t launch_weno(const Desc& D, int stage, hipStream_t st) {
   long long b = nblk(D.N, 256);
   if (b > 4096) b = 4096;
   dim3 grid((unsigned)b, 3);
-  if (D.precision == 1) k_weno<float><<<grid, 256, 0, st>>>(D, stage);
-  else k_weno<double><<<grid, 256, 0, st>>>(D, stage);
+  if (D.precision == 1) k_weno<float><<<grid, 256, 0, st>>>(D, D.win[stage]);
+  else k_weno<double><<<grid, 256, 0, st>>>(D, D.win[stage]);
   return hipGetLastError();
 }
 
@@ -1526,11 +1543,13 @@ bool rhs_tile_supported(int tx, int ty) {
 template <typename F>
 static hipError_t launch_rhs_t(const Desc& D, int stage, hipStream_t st) {
   const unsigned nb = (unsigned)rhs_blocks(D);
-  if (D.tile_x == 64 && D.tile_y == 4) k_rhs<F, 64, 4><<<nb, 256, 0, st>>>(D, stage);
-  else if (D.tile_x == 32 && D.tile_y == 8) k_rhs<F, 32, 8><<<nb, 256, 0, st>>>(D, stage);
-  else if (D.tile_x == 64 && D.tile_y == 2) k_rhs<F, 64, 2><<<nb, 128, 0, st>>>(D, stage);
-  else if (D.tile_x == 128 && D.tile_y == 2) k_rhs<F, 128, 2><<<nb, 256, 0, st>>>(D, stage);
-  else if (D.tile_x == 64 && D.tile_y == 8) k_rhs<F, 64, 8><<<nb, 512, 0, st>>>(D, stage);
+  const double* w = D.win[stage];
+  double* R = D.rcur[stage];
+  if (D.tile_x == 64 && D.tile_y == 4) k_rhs<F, 64, 4><<<nb, 256, 0, st>>>(D, w, R);
+  else if (D.tile_x == 32 && D.tile_y == 8) k_rhs<F, 32, 8><<<nb, 256, 0, st>>>(D, w, R);
+  else if (D.tile_x == 64 && D.tile_y == 2) k_rhs<F, 64, 2><<<nb, 128, 0, st>>>(D, w, R);
+  else if (D.tile_x == 128 && D.tile_y == 2) k_rhs<F, 128, 2><<<nb, 256, 0, st>>>(D, w, R);
+  else if (D.tile_x == 64 && D.tile_y == 8) k_rhs<F, 64, 8><<<nb, 512, 0, st>>>(D, w, R);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -1691,7 +1710,7 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))
                                                   const BatchTable* __restrict__ T, int stage) {
   __shared__ RhsSmem<F, TX, TY> S;
   BATCH_FOR(WK_RHS)
-  rhs_body<F, TX, TY>(D, stage, local, S);
+  rhs_body<F, TX, TY>(D, D.win[stage], D.rcur[stage], local, S);
   BATCH_END
 }
 
