@@ -516,13 +516,6 @@ int sensor_tiles(const Desc& D) {
          ((D.nz + kSenKz - 1) / kSenKz);
 }
 
-__device__ __forceinline__ void vel_of(const double q[5], double& u, double& v, double& w) {
-  const double ir = 1.0 / q[0];
-  u = q[1] * ir;
-  v = q[2] * ir;
-  w = q[3] * ir;
-}
-
 __device__ void sensor_tile(const Desc& D, const double* __restrict__ w, int lb, SenSmem& S,
                             bool export_theta) {
   constexpr int LX = kSenTX + 4;
@@ -538,42 +531,81 @@ __device__ void sensor_tile(const Desc& D, const double* __restrict__ w, int lb,
   const size_t N = (size_t)D.N;
   const double iy = D.iy[j < D.ny ? j : D.ny - 1];
   double U[5], V[5], W[5];
-  auto load = [&](int gi, int gj, int plane, bool fast, double& u, double& v, double& ww) {
-    double q[5];
+  // raw (rho, rho u, rho v, rho w) of a node
+  auto fetch = [&](int gi, int gj, int plane, bool fast, double q[4]) {
     if (fast) {
-      const size_t b = nidx(D, gi, gj, wrap1(plane, D.nz));  // plane in [-2, nz+1]
+      const size_t b = nidx(D, gi, gj, wrap1(plane, D.nz));  // plane in [-2, nz+2]
 #pragma unroll
       for (int m = 0; m < 4; ++m) q[m] = w[(size_t)m * N + b];
     } else {
-      load_node(D, w, gi, gj, plane, q);
-    }
-    vel_of(q, u, v, ww);
-  };
+      double qq[5];
+      load_node(D, w, gi, gj, plane, qq);
 #pragma unroll
-  for (int sl = 0; sl < 4; ++sl) load(i, j, kb - 2 + sl, valid, U[sl], V[sl], W[sl]);
+      for (int m = 0; m < 4; ++m) q[m] = qq[m];
+    }
+  };
+  auto vel = [&](const double q[4], double& u, double& v, double& ww) {
+    const double ir = 1.0 / q[0];
+    u = q[1] * ir;
+    v = q[2] * ir;
+    ww = q[3] * ir;
+  };
+  constexpr int NHS = 4 * kSenTX + 4 * kSenTY;  // halo nodes of a plane
+  constexpr int HPS = (NHS + 255) / 256;        // per thread
+  auto halo_pos = [&](int h, int& lx, int& ly) {
+    if (h < 4 * kSenTX) {  // two rows below and two above the tile
+      const int r = h / kSenTX;
+      ly = r < 2 ? r : kSenTY + r;
+      lx = 2 + h - r * kSenTX;
+    } else {               // two columns left and two right of the tile
+      const int hh = h - 4 * kSenTX;
+      ly = 2 + hh / 4;
+      const int cc = hh & 3;
+      lx = cc < 2 ? cc : kSenTX + cc;
+    }
+  };
+  auto fetch_halo = [&](int plane, double qh[HPS][4]) {
+#pragma unroll
+    for (int r = 0; r < HPS; ++r) {
+      const int h = tid + r * 256;
+      if (h < NHS) {
+        int lx, ly;
+        halo_pos(h, lx, ly);
+        fetch(i0 - 2 + lx, j0 - 2 + ly, plane, tile_in, qh[r]);
+      }
+    }
+  };
+  double qc[4], qh[HPS][4];
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl) {
+    fetch(i, j, kb - 2 + sl, valid, qc);
+    vel(qc, U[sl], V[sl], W[sl]);
+  }
+  // the loads of plane c+1 (own column c+3, halo c+1) are issued during
+  // plane c, before its closing barrier
+  fetch(i, j, kb + 2, valid, qc);
+  fetch_halo(kb, qh);
   for (int c = kb; c < ke; ++c) {
-    load(i, j, c + 2, valid, U[4], V[4], W[4]);
+    vel(qc, U[4], V[4], W[4]);
     S.v[0][ty + 2][tx + 2] = U[2];
     S.v[1][ty + 2][tx + 2] = V[2];
     S.v[2][ty + 2][tx + 2] = W[2];
-    const int kk = c;  // 0 <= c < nz
-    for (int h = tid; h < 4 * kSenTX + 4 * kSenTY; h += 256) {
-      int lx, ly;
-      if (h < 4 * kSenTX) {  // two rows below and two above the tile
-        const int r = h / kSenTX;
-        ly = r < 2 ? r : kSenTY + r;
-        lx = 2 + h - r * kSenTX;
-      } else {               // two columns left and two right of the tile
-        const int hh = h - 4 * kSenTX;
-        ly = 2 + hh / 4;
-        const int cc = hh & 3;
-        lx = cc < 2 ? cc : kSenTX + cc;
+#pragma unroll
+    for (int r = 0; r < HPS; ++r) {
+      const int h = tid + r * 256;
+      if (h < NHS) {
+        int lx, ly;
+        halo_pos(h, lx, ly);
+        double u, v, ww;
+        vel(qh[r], u, v, ww);
+        S.v[0][ly][lx] = u;
+        S.v[1][ly][lx] = v;
+        S.v[2][ly][lx] = ww;
       }
-      double u, v, ww;
-      load(i0 - 2 + lx, j0 - 2 + ly, kk, tile_in, u, v, ww);
-      S.v[0][ly][lx] = u;
-      S.v[1][ly][lx] = v;
-      S.v[2][ly][lx] = ww;
+    }
+    if (c + 1 < ke) {
+      fetch(i, j, c + 3, valid, qc);
+      fetch_halo(c + 1, qh);
     }
     __syncthreads();
     if (valid) {
@@ -609,7 +641,7 @@ __device__ void sensor_tile(const Desc& D, const double* __restrict__ w, int lb,
   }
 }
 
-__global__ void __launch_bounds__(256) k_sensor(Desc D, int stage, int export_theta) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_sensor(Desc D, int stage, int export_theta) {
   __shared__ SenSmem S;
   // the list counters of this stage start at zero (the previous stage's
   // lists were consumed before this kernel starts)
@@ -1671,7 +1703,7 @@ __global__ void __launch_bounds__(256) k_b_ghost_y(const Desc* __restrict__ desc
   BATCH_END
 }
 
-__global__ void __launch_bounds__(256) k_b_sensor(const Desc* __restrict__ descs,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_b_sensor(const Desc* __restrict__ descs,
                                                   const BatchTable* __restrict__ T, int stage) {
   __shared__ SenSmem S;
   BATCH_FOR(WK_SEN)
