@@ -273,6 +273,28 @@ __device__ __forceinline__ double wrcp<double>(double x) {
   return fma(r, e, r);
 }
 
+// Square root of a positive normal x for the splitting constants: the
+// hardware reciprocal-square-root estimate refined by two coupled Newton
+// steps (about one ulp; no scaling for denormals or infinities, which a
+// valid state never produces here).  FP32: the ordinary square root.
+template <typename F>
+__device__ __forceinline__ F wsqrt(F x) {
+  return sqrt(x);
+}
+template <>
+__device__ __forceinline__ double wsqrt<double>(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
 // WENO5-JS reconstruction at i+1/2 from v_{i-2..i+2}.  The argument `eps4`
 // is four times the regulariser: the callers pass twice the split fluxes
 // (the factor 1/2 of the splitting is applied once to the sum), and
@@ -357,7 +379,7 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
     const F mn = (F)qd[PN], m1 = (F)qd[P1], m2 = (F)qd[P2], E = (F)qd[4];
     const F un = mn * ir, t1 = m1 * ir, t2 = m2 * ir;
     const F p = gm1 * (E - F(0.5) * r * (un * un + t1 * t1 + t2 * t2));
-    const F c = sqrt(gam * p * ir);
+    const F c = wsqrt<F>(gam * p * ir);  // enters only the splitting constants
     const F wq[5] = {r, mn, m1, m2, E};
     const F fq[5] = {mn, mn * un + p, mn * t1, mn * t2, un * (E + p)};
     project(wq, v[s]);
