@@ -10,9 +10,10 @@ stages of ghost planes, sensor, flag compaction, WENO on lists, fused
 right-hand side, forcing reduction and update), replayed from a HIP graph.
 
 Prints ONE JSON line with the throughput (Mpoint-RK-steps/s), the roofline
-of the dominant kernel (durations from HIP events on the library's stream
-in the same run) and the FP64 oracle timed on the host cores on a bounded
-sample of the same workload.
+of the dominant kernel (durations from HIP events on the library's stream,
+over a kernel-by-kernel replay of the same timed steps from the same
+state) and the FP64 oracle timed on the host cores on a bounded sample of
+the same workload.
 """
 import argparse
 import hashlib
@@ -34,11 +35,12 @@ FP64_VECTOR_TFLOPS = 78.6
 STEP_BYTES_PER_PT_FORCED = 448.0
 # The fused right-hand-side kernel must read w (40 B) and write R (40 B).
 RHS_BYTES_PER_PT = 80.0
-# FP64 operations of one shock-capturing interface flux (counted from the
-# formula: primitives and fluxes of six nodes, Roe average, left
-# eigenvectors, two projections per node, Lax-Friedrichs split, ten WENO5
-# reconstructions, back-projection); see the design doc.
-WENO_FLOPS_PER_IFACE = 1400.0
+# FP64 operations of one shock-capturing interface flux, counted from the
+# formula (a fused multiply-add counts two, a division or square root one):
+# Roe average and eigenvalue constants 64, six nodes x (primitives, flux,
+# two characteristic projections, eigenvalue bounds) 444, Lax-Friedrichs
+# splitting 100, ten WENO5 reconstructions 690, back-projection 26.
+WENO_FLOPS_PER_IFACE = 1324.0
 
 
 def kernel_source_hash():
@@ -89,7 +91,6 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", choices=["fp64", "fp32flux"], default="fp64")
-    ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -119,6 +120,9 @@ def main():
           flush=True)
     s.advance(args.warmup, cfl=cfl)
     torch.cuda.synchronize()
+    with torch.cuda.stream(s.stream):
+        start_state = s.state.clone()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.advance(args.steps, cfl=cfl)
     torch.cuda.synchronize()
@@ -130,19 +134,24 @@ def main():
     print(f"# timed {args.steps} steps in {el:.3f} s, weno fraction {d['weno_frac']}",
           file=sys.stderr, flush=True)
 
-    # per-kernel durations with HIP events, same state and launch configuration
-    ph = s.time_phases(args.profile_steps, cfl=cfl)
-    per_step = {k: v[0] * v[1] / args.profile_steps for k, v in ph.items()}
+    # per-kernel durations with HIP events over the same steps: the state is
+    # rewound to the start of the timed region and the steps are replayed
+    # kernel by kernel with an event pair around every launch
+    s.set_state(start_state)
+    torch.cuda.synchronize()
+    ph, n_iface_total = s.time_phases(args.steps, cfl=cfl, with_interfaces=True)
+    per_step = {k: v[0] * v[1] / args.steps for k, v in ph.items()}
     dom = max(per_step, key=per_step.get)
     mean_ms = ph[dom][0]
     if dom == "weno":
-        n_iface = sum(d["weno_frac"]) * pr.npts
+        n_iface = n_iface_total / max(ph["weno"][1], 1)
         flops = WENO_FLOPS_PER_IFACE * n_iface
         achieved = flops / (mean_ms * 1e-3) / 1e12
         roof = {"kernel": "k_weno", "bound": "alu", "achieved": achieved,
                 "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_TFLOPS,
                 "traffic": load_traffic("k_weno"),
-                "algorithmic_per_launch": f"{WENO_FLOPS_PER_IFACE:.0f} flop x {n_iface:.0f} interfaces"}
+                "algorithmic_per_launch": f"{WENO_FLOPS_PER_IFACE:.0f} flop x {n_iface:.0f} "
+                                          f"interfaces (mean over the timed launches)"}
     else:
         nbytes = RHS_BYTES_PER_PT * pr.npts
         achieved = nbytes / (ph["rhs"][0] * 1e-3) / 1e9
@@ -170,7 +179,8 @@ def main():
                    "points": pr.npts, "parallelism": "single GPU"},
         "hbm_frac_step_algorithmic": hbm_frac_step,
         "phase_ms_per_step": per_step,
-        "weno_frac": d["weno_frac"],
+        "weno_frac_last_stage": d["weno_frac"],
+        "weno_interfaces_per_step": n_iface_total / args.steps,
         "roofline": roof,
     }
     s.close()

@@ -192,11 +192,13 @@ cdns_status cdns_export_iface_flux(cdns_ctx* ctx, int32_t dir, double* out_dev);
  * of HIP events recorded on the context's stream around every phase.
  * ms_out[CDNS_NPHASES] receives the mean duration (ms) of one launch of
  * each phase, launches_out[CDNS_NPHASES] (may be NULL) the number of
- * launches timed.  Advances the state like cdns_rk_step; synchronises. */
+ * launches timed, weno_ifaces_out (may be NULL) the total number of
+ * shock-capturing interfaces (all directions) processed by the timed WENO
+ * launches.  Advances the state like cdns_rk_step; synchronises. */
 enum { CDNS_PH_DT = 0, CDNS_PH_GHOSTS, CDNS_PH_SENSOR, CDNS_PH_IFLAGS, CDNS_PH_WENO,
        CDNS_PH_RHS, CDNS_PH_FORCE, CDNS_PH_RK, CDNS_NPHASES };
 cdns_status cdns_time_phases(cdns_ctx* ctx, int32_t nsteps, double cfl, double dt_fixed,
-                             double* ms_out, int32_t* launches_out);
+                             double* ms_out, int32_t* launches_out, int64_t* weno_ifaces_out);
 
 /* Last error message of the context (valid until the next call on it). */
 const char* cdns_last_error(const cdns_ctx* ctx);

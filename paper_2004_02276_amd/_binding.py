@@ -97,7 +97,8 @@ def load() -> ctypes.CDLL:
     lib.cdns_export_sensor.restype = i32
     lib.cdns_export_iface_flux.argtypes = [vp, i32, dp]
     lib.cdns_export_iface_flux.restype = i32
-    lib.cdns_time_phases.argtypes = [vp, i32, f64, f64, ctypes.POINTER(f64), ctypes.POINTER(i32)]
+    lib.cdns_time_phases.argtypes = [vp, i32, f64, f64, ctypes.POINTER(f64), ctypes.POINTER(i32),
+                                     ctypes.POINTER(ctypes.c_int64)]
     lib.cdns_time_phases.restype = i32
     lib.cdns_last_error.argtypes = [vp]
     lib.cdns_last_error.restype = ctypes.c_char_p

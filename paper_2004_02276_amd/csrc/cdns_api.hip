@@ -506,7 +506,7 @@ cdns_status cdns_export_iface_flux(cdns_ctx* c, int32_t dir, double* out_dev) {
 }
 
 cdns_status cdns_time_phases(cdns_ctx* c, int32_t nsteps, double cfl, double dt_fixed,
-                             double* ms_out, int32_t* launches_out) {
+                             double* ms_out, int32_t* launches_out, int64_t* weno_ifaces_out) {
   if (!c) return CDNS_EINVAL;
   if (nsteps < 1 || !ms_out) return fail(c, CDNS_EINVAL, "need nsteps >= 1 and an output array");
   if (!(dt_fixed > 0.0) && !(cfl > 0.0)) return fail(c, CDNS_EINVAL, "need cfl > 0 or dt > 0");
@@ -530,6 +530,7 @@ cdns_status cdns_time_phases(cdns_ctx* c, int32_t nsteps, double cfl, double dt_
     if ((e = fn()) != hipSuccess) return;
     e = hipEventRecord(r.b, st);
   };
+  if (D.sensor_mode > 0) e = cdns::launch_count_iface(D, true, st);
   for (int step = 0; step < nsteps && e == hipSuccess; ++step) {
     timed(CDNS_PH_DT, [&] { return cdns::launch_dt(D, st); });
     for (int stage = 0; stage < 3; ++stage) {
@@ -541,6 +542,7 @@ cdns_status cdns_time_phases(cdns_ctx* c, int32_t nsteps, double cfl, double dt_
       if (D.sensor_mode > 0) {
         timed(CDNS_PH_IFLAGS, [&] { return cdns::launch_iflags(D, st); });
         timed(CDNS_PH_WENO, [&] { return cdns::launch_weno(D, stage, st); });
+        if (e == hipSuccess) e = cdns::launch_count_iface(D, false, st);  // outside the events
       }
       timed(CDNS_PH_RHS, [&] { return cdns::launch_rhs(D, stage, st); });
       if (D.forcing) timed(CDNS_PH_FORCE, [&] { return cdns::launch_force(D, st); });
@@ -562,6 +564,15 @@ cdns_status cdns_time_phases(cdns_ctx* c, int32_t nsteps, double cfl, double dt_
   for (int p = 0; p < CDNS_NPHASES; ++p) {
     ms_out[p] = cnt[p] ? tot[p] / cnt[p] : 0.0;
     if (launches_out) launches_out[p] = cnt[p];
+  }
+  if (weno_ifaces_out) {
+    double acc = 0.0;
+    if (D.sensor_mode > 0 &&
+        ((e = hipMemcpyAsync(&acc, D.scal + cdns::SC_WACC, sizeof(double), hipMemcpyDeviceToHost,
+                             st)) != hipSuccess ||
+         (e = hipStreamSynchronize(st)) != hipSuccess))
+      return hip_fail(c, e, "interface count");
+    *weno_ifaces_out = (int64_t)acc;
   }
   return CDNS_OK;
 }

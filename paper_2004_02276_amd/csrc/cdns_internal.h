@@ -19,7 +19,7 @@ enum { BC_PERIODIC = 0, BC_WALL_ISO = 1, BC_WALL_ADIA = 2, BC_DIRICHLET = 3,
 enum { ST_BAD_STATE = 1u, ST_BAD_GHOST = 2u };
 
 // Scalar slots in Desc::scal.
-enum { SC_DT = 0, SC_FORCE = 1, SC_TIME = 2, SC_STEP = 3, SC_COUNT = 8 };
+enum { SC_DT = 0, SC_FORCE = 1, SC_TIME = 2, SC_STEP = 3, SC_WACC = 4, SC_COUNT = 8 };
 
 // Diagnostics slots in Desc::diag.
 enum { DG_MASS = 0, DG_MX, DG_MY, DG_MZ, DG_E, DG_K, DG_RHOMIN, DG_PMIN, DG_MACHMAX,
@@ -89,6 +89,7 @@ hipError_t launch_rk(const Desc& D, int stage, hipStream_t st);
 hipError_t launch_dt(const Desc& D, hipStream_t st);
 hipError_t launch_diag(const Desc& D, hipStream_t st);
 hipError_t launch_export_iflags(const Desc& D, uint8_t* out, hipStream_t st);
+hipError_t launch_count_iface(const Desc& D, bool reset, hipStream_t st);  // scal[SC_WACC]
 hipError_t launch_export_iface(const Desc& D, int dir, double* out, hipStream_t st);
 bool rhs_tile_supported(int tx, int ty);
 int rhs_blocks(const Desc& D);

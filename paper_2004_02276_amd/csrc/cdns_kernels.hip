@@ -1563,6 +1563,19 @@ __global__ void k_export_iface(Desc D, int dir, double* __restrict__ out) {
   for (int m = 0; m < 5; ++m) out[(size_t)m * D.N + n] = e >= 0 ? D.Fw[dir][(size_t)m * D.N + e] : 0.0;
 }
 
+// Running total of listed interfaces (profiling): adds the three list
+// lengths of the current stage to scal[SC_WACC] (or restarts it).
+__global__ void k_count_iface(Desc D, int reset) {
+  if (threadIdx.x != 0) return;
+  const double prev = reset ? 0.0 : D.scal[SC_WACC];
+  D.scal[SC_WACC] = reset ? 0.0 : prev + (double)D.count[0] + (double)D.count[1] + (double)D.count[2];
+}
+
+hipError_t launch_count_iface(const Desc& D, bool reset, hipStream_t st) {
+  k_count_iface<<<1, 64, 0, st>>>(D, reset ? 1 : 0);
+  return hipGetLastError();
+}
+
 hipError_t launch_export_iflags(const Desc& D, uint8_t* out, hipStream_t st) {
   k_export_iflags<<<nblk(D.N, 256), 256, 0, st>>>(D, out);
   return hipGetLastError();

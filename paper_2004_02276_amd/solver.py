@@ -133,17 +133,22 @@ class Solver:
                 "cdns_export_iface_flux")
         return out
 
-    def time_phases(self, nsteps: int, cfl: Optional[float] = None, dt_fixed: float = 0.0):
+    def time_phases(self, nsteps: int, cfl: Optional[float] = None, dt_fixed: float = 0.0,
+                    with_interfaces: bool = False):
         """Mean duration (ms) and count of one launch of each kernel phase over
-        nsteps eagerly launched steps, timed with HIP events on the stream."""
+        nsteps eagerly launched steps, timed with HIP events on the stream.
+        With with_interfaces, also the total number of shock-capturing
+        interfaces processed by the timed WENO launches: (phases, total)."""
         cfl = self.pr.cfl if cfl is None else cfl
         n = len(B.PHASES)
         ms = (ctypes.c_double * n)()
         cnt = (ctypes.c_int32 * n)()
+        nif = ctypes.c_int64(0)
         B.check(self.lib, self.ctx,
                 self.lib.cdns_time_phases(self.ctx, int(nsteps), float(cfl), float(dt_fixed), ms,
-                                          cnt), "cdns_time_phases")
-        return {B.PHASES[i]: (ms[i], cnt[i]) for i in range(n)}
+                                          cnt, ctypes.byref(nif)), "cdns_time_phases")
+        ph = {B.PHASES[i]: (ms[i], cnt[i]) for i in range(n)}
+        return (ph, int(nif.value)) if with_interfaces else ph
 
     def close(self) -> None:
         if self.ctx:
