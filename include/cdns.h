@@ -155,8 +155,10 @@ cdns_status cdns_set_bc(cdns_ctx* ctx, int32_t face, int32_t kind, const double*
                         int64_t nparams);
 
 /* Tile shape of the fused right-hand-side kernel: (tile_x, tile_y) must be
- * one of the compiled variants (64x4, 32x8, 64x2, 128x2), kz >= 1 planes per
- * block.  Results do not depend on the choice. */
+ * one of the compiled variants (64x4, 32x8, 64x2, 128x2, 64x8), kz >= 1
+ * planes per block.  Results are bitwise independent of the choice except
+ * for the rounding of the bulk-force sum, whose per-tile partial sums follow
+ * the tiling.  Returns CDNS_EINVAL for other shapes. */
 cdns_status cdns_set_tiling(cdns_ctx* ctx, int32_t tile_x, int32_t tile_y, int32_t kz);
 
 /* Full right-hand side R(w) of dw/dt = R(w) (Sec. 2.2) for the device

@@ -938,7 +938,9 @@ __device__ __forceinline__ void lds_store(RhsSmem<F, TX, TY>& S, int ly, int lx,
 }
 
 // One block of the fused kernel: tile (tile index lb) of the instance D.
-template <typename F, int TX, int TY>
+// VISC_ON false compiles the viscous terms out (inviscid problems: fewer
+// registers); true evaluates them when the instance is viscous.
+template <typename F, int TX, int TY, bool VISC_ON = true>
 __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict__ w, double* __restrict__ R,
                          int lb, RhsSmem<F, TX, TY>& S) {
   constexpr int LX = TX + 4, LY = TY + 4;
@@ -963,7 +965,7 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
   const F iy = (F)D.iy[jc], iye2 = (F)D.iye2[jc], yee = (F)D.y_etaeta[jc];
   const F ideta2 = (F)D.ideta2;
   const F kfac = (F)D.kfac;
-  const bool visc = D.viscous != 0;
+  const bool visc = VISC_ON && D.viscous != 0;
   const bool hybrid = D.sensor_mode != 0;
   const bool wall_lo = D.wall_lo && j == 0;
   const bool wall_hi = D.wall_hi && j == D.ny - 1;
@@ -1257,12 +1259,12 @@ __device__ __forceinline__ int xcd_swizzle(int b, int nb) {
   return (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
 }
 
-template <typename F, int TX, int TY>
+template <typename F, int TX, int TY, bool VISC_ON>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2)))
 k_rhs(Desc D, const double* __restrict__ w, double* __restrict__ R) {
   __shared__ RhsSmem<F, TX, TY> S;
   const int lb = xcd_swizzle(blockIdx.x, gridDim.x);
-  rhs_body<F, TX, TY>(D, w, R, lb, S);
+  rhs_body<F, TX, TY, VISC_ON>(D, w, R, lb, S);
 }
 
 // ------------------------------------------------------------------ reductions
@@ -1607,18 +1609,23 @@ bool rhs_tile_supported(int tx, int ty) {
          (tx == 128 && ty == 2) || (tx == 64 && ty == 8);
 }
 
-template <typename F>
-static hipError_t launch_rhs_t(const Desc& D, int stage, hipStream_t st) {
+template <typename F, bool VISC_ON>
+static hipError_t launch_rhs_v(const Desc& D, int stage, hipStream_t st) {
   const unsigned nb = (unsigned)rhs_blocks(D);
   const double* w = D.win[stage];
   double* R = D.rcur[stage];
-  if (D.tile_x == 64 && D.tile_y == 4) k_rhs<F, 64, 4><<<nb, 256, 0, st>>>(D, w, R);
-  else if (D.tile_x == 32 && D.tile_y == 8) k_rhs<F, 32, 8><<<nb, 256, 0, st>>>(D, w, R);
-  else if (D.tile_x == 64 && D.tile_y == 2) k_rhs<F, 64, 2><<<nb, 128, 0, st>>>(D, w, R);
-  else if (D.tile_x == 128 && D.tile_y == 2) k_rhs<F, 128, 2><<<nb, 256, 0, st>>>(D, w, R);
-  else if (D.tile_x == 64 && D.tile_y == 8) k_rhs<F, 64, 8><<<nb, 512, 0, st>>>(D, w, R);
+  if (D.tile_x == 64 && D.tile_y == 4) k_rhs<F, 64, 4, VISC_ON><<<nb, 256, 0, st>>>(D, w, R);
+  else if (D.tile_x == 32 && D.tile_y == 8) k_rhs<F, 32, 8, VISC_ON><<<nb, 256, 0, st>>>(D, w, R);
+  else if (D.tile_x == 64 && D.tile_y == 2) k_rhs<F, 64, 2, VISC_ON><<<nb, 128, 0, st>>>(D, w, R);
+  else if (D.tile_x == 128 && D.tile_y == 2) k_rhs<F, 128, 2, VISC_ON><<<nb, 256, 0, st>>>(D, w, R);
+  else if (D.tile_x == 64 && D.tile_y == 8) k_rhs<F, 64, 8, VISC_ON><<<nb, 512, 0, st>>>(D, w, R);
   else return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+template <typename F>
+static hipError_t launch_rhs_t(const Desc& D, int stage, hipStream_t st) {
+  return D.viscous ? launch_rhs_v<F, true>(D, stage, st) : launch_rhs_v<F, false>(D, stage, st);
 }
 
 hipError_t launch_rhs(const Desc& D, int stage, hipStream_t st) {

@@ -6,6 +6,7 @@ of RK steps within 1e-10, per conserved field, relative L-infinity
 flag masks exactly (both sides compute the sensor in FP64 with the same
 operation order and no contraction).
 """
+import dataclasses
 import sys
 
 import numpy as np
@@ -71,6 +72,9 @@ RHS_CASES = {
     "channel_70x22x10": lambda: P.small_channel(70, 22, 10),
     "sbli_64x32x8": lambda: P.small_sbli(64, 32, 8),
     "sbli_100x36x6": lambda: P.small_sbli(100, 36, 6, theta_star=0.02),
+    # inviscid instance of the fused kernel (viscous terms compiled out)
+    "dit24_inviscid_hybrid": lambda: dataclasses.replace(
+        P.decaying_turbulence(24, mach=1.5, re=800.0, seed=13), viscous=False),
 }
 
 
@@ -151,6 +155,8 @@ STEP_CASES = {
     "sbli_64x32x8_100steps": (lambda: P.small_sbli(64, 32, 8), 100, True),
     "dit24_hybrid_50steps": (lambda: P.decaying_turbulence(24, mach=0.5, re=800.0, seed=11), 50,
                              False),
+    "dit24_inviscid_30steps": (lambda: dataclasses.replace(
+        P.decaying_turbulence(24, mach=0.5, re=800.0, seed=14), viscous=False), 30, False),
 }
 
 
