@@ -5,14 +5,16 @@
 // Per stage (all on one stream, no host synchronisation):
 //   ghosts   x-face then y-face ghost planes of non-periodic faces
 //   sensor   Ducros sensor in FP64 with the node flag theta > theta*
-//   iflags   interface flags (OR over the central stencil) and compaction
-//            into one list of interfaces per direction
+//   iflags   interface flags (OR over the central stencil), compaction
+//            into one node-ordered list of interfaces per direction and a
+//            per-node slot (list position or -1)
 //   weno     Lax-Friedrichs characteristic WENO5 flux on the listed
-//            interfaces, stored densely per interface
+//            interfaces, stored compacted at the list position
 //   rhs      fused central convective + pressure flux in x, y, z and
 //            Laplacian-form viscous/heat terms, 2.5-D tiling: an (x,y) tile
 //            with a 2-node halo is staged in LDS plane by plane while each
-//            thread keeps its own z column in registers
+//            thread keeps its own z column in registers; flagged interfaces
+//            take the compacted WENO flux through their slot
 //   force    bulk force from the per-block partial sums (fixed order)
 //   rk       w' = w + dt (alpha R_prev + beta R), forcing applied here
 //
