@@ -304,9 +304,10 @@ __device__ __forceinline__ double wsqrt<double>(double x) {
 // so the weights are those of the unscaled reconstruction.
 template <typename F>
 __device__ __forceinline__ F weno5(F vm2, F vm1, F v0, F vp1, F vp2, F eps4) {
-  const F q0 = (F(2) * vm2 - F(7) * vm1 + F(11) * v0) * F(1.0 / 6.0);
-  const F q1 = (-vm1 + F(5) * v0 + F(2) * vp1) * F(1.0 / 6.0);
-  const F q2 = (F(2) * v0 + F(5) * vp1 - vp2) * F(1.0 / 6.0);
+  // candidate reconstructions, times 6 (the 1/6 is applied with the weights)
+  const F q0 = F(2) * vm2 - F(7) * vm1 + F(11) * v0;
+  const F q1 = -vm1 + F(5) * v0 + F(2) * vp1;
+  const F q2 = F(2) * v0 + F(5) * vp1 - vp2;
   const F d0 = vm2 - F(2) * vm1 + v0, e0 = vm2 - F(4) * vm1 + F(3) * v0;
   const F d1 = vm1 - F(2) * v0 + vp1, e1 = vm1 - vp1;
   const F d2 = v0 - F(2) * vp1 + vp2, e2 = F(3) * v0 - F(4) * vp1 + vp2;
@@ -314,12 +315,13 @@ __device__ __forceinline__ F weno5(F vm2, F vm1, F v0, F vp1, F vp2, F eps4) {
   const F s1 = eps4 + F(13.0 / 12.0) * d1 * d1 + F(0.25) * e1 * e1;
   const F s2 = eps4 + F(13.0 / 12.0) * d2 * d2 + F(0.25) * e2 * e2;
   // weights d_k/(eps+beta_k)^2 normalised, with numerator and denominator
-  // multiplied by the product of the three squares: one division
+  // multiplied by 10 times the product of the three squares (d = 0.1, 0.6,
+  // 0.3 become 1, 6, 3): a = (t1 t2, 6 t0 t2, 3 t0 t1), one reciprocal
   const F t0 = s0 * s0, t1 = s1 * s1, t2 = s2 * s2;
-  const F a0 = F(0.1) * (t1 * t2);
-  const F a1 = F(0.6) * (t0 * t2);
-  const F a2 = F(0.3) * (t0 * t1);
-  return (a0 * q0 + a1 * q1 + a2 * q2) * wrcp<F>(a0 + a1 + a2);
+  const F P = t1 * t2, B = F(3) * t1, C = F(6) * t2;
+  const F num = P * q0 + t0 * (C * q1 + B * q2);
+  const F den = P + t0 * (C + B);
+  return num * wrcp<F>(F(6) * den);
 }
 
 // Lax-Friedrichs split characteristic WENO5 flux at interface i+1/2 along
@@ -360,14 +362,16 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
   // m_t2, E).  With X = b2 q0 - b1 (u q1 + v q2 + w q3) + b1 q4 and
   // Y = (u q0 - q1)/c the rows are: (X + Y)/2, q0 - X, q2 - v q0,
   // q3 - w q0, (X - Y)/2.
+  // (evaluated with X/2 and Y/2, which saves the two halvings)
+  const F hb1 = F(0.5) * b1, hb2 = F(0.5) * b2, hic = F(0.5) * ic;
   auto project = [&](const F* q, F out[5]) {
-    const F X = b2 * q[0] - b1 * (ur * q[1] + vr * q[2] + wr * q[3]) + b1 * q[4];
-    const F Y = (ur * q[0] - q[1]) * ic;
-    out[0] = F(0.5) * (X + Y);
-    out[1] = q[0] - X;
+    const F Xh = hb2 * q[0] - hb1 * (ur * q[1] + vr * q[2] + wr * q[3]) + hb1 * q[4];
+    const F Yh = (ur * q[0] - q[1]) * hic;
+    out[0] = Xh + Yh;
+    out[1] = q[0] - F(2) * Xh;
     out[2] = q[2] - vr * q[0];
     out[3] = q[3] - wr * q[0];
-    out[4] = F(0.5) * (X - Y);
+    out[4] = Xh - Yh;
   };
   // stencil nodes: physical flux, eigenvalue bounds, characteristic projections
   F v[6][5], g[6][5];
