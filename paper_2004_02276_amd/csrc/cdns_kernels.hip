@@ -275,10 +275,11 @@ __device__ __forceinline__ double wrcp<double>(double x) {
   return fma(r, e, r);
 }
 
-// Square root of a positive normal x for the splitting constants: the
+// Square root of a positive normal x for the shock-capturing flux: the
 // hardware reciprocal-square-root estimate refined by two coupled Newton
-// steps (about one ulp; no scaling for denormals or infinities, which a
-// valid state never produces here).  FP32: the ordinary square root.
+// steps and a final residual correction (about one ulp; no scaling for
+// denormals or infinities, which a valid state never produces here; a
+// negative argument gives NaN like sqrt).  FP32: the ordinary square root.
 template <typename F>
 __device__ __forceinline__ F wsqrt(F x) {
   return sqrt(x);
@@ -346,7 +347,7 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
     const F pa = gm1 * (Ea - F(0.5) * ra * (una * una + t1a * t1a + t2a * t2a));
     const F pb = gm1 * (Eb - F(0.5) * rb * (unb * unb + t1b * t1b + t2b * t2b));
     const F Ha = (Ea + pa) * ira, Hb = (Eb + pb) * irb;
-    const F sl = sqrt(ra), sr = sqrt(rb);
+    const F sl = wsqrt<F>(ra), sr = wsqrt<F>(rb);
     const F iw = wrcp<F>(sl + sr);
     ur = (sl * una + sr * unb) * iw;
     vr = (sl * t1a + sr * t1b) * iw;
@@ -354,7 +355,7 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
     Hr = (sl * Ha + sr * Hb) * iw;
   }
   const F q2 = ur * ur + vr * vr + wr * wr;
-  const F cr = sqrt(gm1 * (Hr - F(0.5) * q2));
+  const F cr = wsqrt<F>(gm1 * (Hr - F(0.5) * q2));
   const F ic = wrcp<F>(cr);
   const F b1 = gm1 * ic * ic;
   const F b2 = F(0.5) * q2 * b1;
@@ -385,7 +386,7 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
     const F mn = (F)qd[PN], m1 = (F)qd[P1], m2 = (F)qd[P2], E = (F)qd[4];
     const F un = mn * ir, t1 = m1 * ir, t2 = m2 * ir;
     const F p = gm1 * (E - F(0.5) * r * (un * un + t1 * t1 + t2 * t2));
-    const F c = wsqrt<F>(gam * p * ir);  // enters only the splitting constants
+    const F c = wsqrt<F>(gam * p * ir);
     const F wq[5] = {r, mn, m1, m2, E};
     const F fq[5] = {mn, mn * un + p, mn * t1, mn * t2, un * (E + p)};
     project(wq, v[s]);
