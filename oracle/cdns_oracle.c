@@ -471,10 +471,9 @@ static void interface_flags(const ora_problem* P, work_t* a) {
 }
 
 /* ------------------------------------------------------------ Euler fluxes
- * Three-point average operator (Sec. 2.1, eq. avg_operator). */
-static inline double tavg(double Fa, double Fb, double Ga, double Gb, double Ha, double Hb) {
-  return 0.125 * (Fa + Fb) * (Ga + Gb) * (Ha + Hb);
-}
+ * The three-point average operator of Sec. 2.1 (eq. avg_operator),
+ * (1/8)(F_a + F_b)(G_a + G_b)(H_a + H_b), appears below with F = rho,
+ * G = u_n and H = phi. */
 
 /* Energy-preserving central flux of order 4 (L = 2) at interface i+1/2,
  * node i at padded index q, stride s along the direction d (eq. encflux):
@@ -482,7 +481,14 @@ static inline double tavg(double Fa, double Fb, double Ga, double Gb, double Ha,
  * phi = 1, u, v, w, H.  The pressure term of the momentum equation is put
  * in the same conservative form with two-point averages,
  * 2 sum_l a_l sum_m (p_{i-m} + p_{i-m+l})/2.  Output in natural order;
- * conv/pres select the two parts (both for the full operator). */
+ * conv/pres select the two parts (both for the full operator).
+ *
+ * Evaluation order (fixed, so that results can be compared bit for bit at
+ * low Mach number, where the residual is a small difference of large
+ * fluxes): per pair t the mass-flux factor M_t = (2 a_t) (1/8)(rho_a +
+ * rho_b)(u_a + u_b); per component f = M_0 (phi_a + phi_b)_0, then
+ * f = fma(M_t, (phi_a + phi_b)_t, f) for t = 1, 2; the pressure part
+ * a_0 (p_a + p_b)_0 accumulated the same way. */
 static void central_flux(const work_t* a, size_t q, size_t s, int d, int conv, int pres,
                          double f[5]) {
   const double* un = d == 0 ? a->u : (d == 1 ? a->v : a->w);
@@ -492,19 +498,23 @@ static void central_flux(const work_t* a, size_t q, size_t s, int d, int conv, i
   size_t pa[3] = {q, q, q - s};
   size_t pb[3] = {q + s, q + 2 * s, q + s};
   double al[3] = {A1, A2, A2};
+  double M[3];
+  for (int t = 0; t < 3; ++t)
+    M[t] = (2.0 * al[t]) * (0.125 * (r[pa[t]] + r[pb[t]]) * (un[pa[t]] + un[pb[t]]));
   for (int c = 0; c < 5; ++c) {
-    double acc = 0.0;
-    for (int t = 0; t < 3; ++t) {
-      double phia = c == 0 ? 1.0 : phis[c][pa[t]];
-      double phib = c == 0 ? 1.0 : phis[c][pb[t]];
-      acc += al[t] * tavg(r[pa[t]], r[pb[t]], un[pa[t]], un[pb[t]], phia, phib);
-    }
-    f[c] = conv ? 2.0 * acc : 0.0;
+    double sum[3];
+    for (int t = 0; t < 3; ++t)
+      sum[t] = c == 0 ? 2.0 : phis[c][pa[t]] + phis[c][pb[t]];
+    double acc = M[0] * sum[0];
+    acc = fma(M[1], sum[1], acc);
+    acc = fma(M[2], sum[2], acc);
+    f[c] = conv ? acc : 0.0;
   }
   if (pres) {
-    double acc = 0.0;
-    for (int t = 0; t < 3; ++t) acc += al[t] * 0.5 * (a->p[pa[t]] + a->p[pb[t]]);
-    f[1 + d] += 2.0 * acc;
+    double acc = al[0] * (a->p[pa[0]] + a->p[pb[0]]);
+    acc = fma(al[1], a->p[pa[1]] + a->p[pb[1]], acc);
+    acc = fma(al[2], a->p[pa[2]] + a->p[pb[2]], acc);
+    f[1 + d] += acc;
   }
 }
 

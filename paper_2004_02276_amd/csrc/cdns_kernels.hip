@@ -68,6 +68,11 @@ __device__ __forceinline__ size_t nidx(const Desc& D, int i, int j, int k) {
   return ((size_t)k * D.ny + (size_t)j) * D.nx + (size_t)i;
 }
 
+// 32-bit node index (the point count is below 2^31, checked at creation)
+__device__ __forceinline__ int nidx32(const Desc& D, int i, int j, int k) {
+  return (k * D.ny + j) * D.nx + i;
+}
+
 __device__ __forceinline__ void from_prim(const Desc& D, double r, double u, double v, double w,
                                           double p, double q[5]) {
   q[0] = r;
@@ -203,9 +208,11 @@ __device__ __forceinline__ void central_flux(const PV<F>& a, const PV<F>& b, con
   f[1 + DIR] += F(CA1) * (b.p + c.p) + F(CA2) * ((b.p + d.p) + (a.p + c.p));
 }
 
-// FP64 version: the split-form triple products (1/8)(F_a+F_b)(G_a+G_b)(H_a+H_b)
-// are accumulated over the pairs (i,i+1), (i,i+2), (i-1,i+1) with the weights
-// a_1, a_2, a_2, then doubled, in a fixed order without contraction.
+// FP64 version in a fixed evaluation order without contraction: per pair
+// (i,i+1), (i,i+2), (i-1,i+1) the mass-flux factor M = (2 a_l)(1/8)(rho_a +
+// rho_b)(u_a + u_b) (a_l = a_1, a_2, a_2), each component the sum of
+// M (phi_a + phi_b) over the pairs in that order with fused multiply-adds,
+// the pressure part sum a_l (p_a + p_b) the same way.
 template <int DIR>
 __device__ __forceinline__ void central_flux_f64(const PV<double>& a, const PV<double>& b,
                                                  const PV<double>& c, const PV<double>& d,
@@ -215,16 +222,16 @@ __device__ __forceinline__ void central_flux_f64(const PV<double>& a, const PV<d
   const double nb = DIR == 0 ? b.u : (DIR == 1 ? b.v : b.w);
   const double nc = DIR == 0 ? c.u : (DIR == 1 ? c.v : c.w);
   const double nd = DIR == 0 ? d.u : (DIR == 1 ? d.v : d.w);
-  const double m1 = 0.125 * (b.r + c.r) * (nb + nc);
-  const double m2 = 0.125 * (b.r + d.r) * (nb + nd);
-  const double m3 = 0.125 * (a.r + c.r) * (na + nc);
-  f[0] = 2.0 * (CA1 * (m1 * 2.0) + CA2 * (m2 * 2.0) + CA2 * (m3 * 2.0));
-  f[1] = 2.0 * (CA1 * (m1 * (b.u + c.u)) + CA2 * (m2 * (b.u + d.u)) + CA2 * (m3 * (a.u + c.u)));
-  f[2] = 2.0 * (CA1 * (m1 * (b.v + c.v)) + CA2 * (m2 * (b.v + d.v)) + CA2 * (m3 * (a.v + c.v)));
-  f[3] = 2.0 * (CA1 * (m1 * (b.w + c.w)) + CA2 * (m2 * (b.w + d.w)) + CA2 * (m3 * (a.w + c.w)));
-  f[4] = 2.0 * (CA1 * (m1 * (b.h + c.h)) + CA2 * (m2 * (b.h + d.h)) + CA2 * (m3 * (a.h + c.h)));
-  const double pf = (CA1 * 0.5) * (b.p + c.p) + (CA2 * 0.5) * (b.p + d.p) + (CA2 * 0.5) * (a.p + c.p);
-  f[1 + DIR] = f[1 + DIR] + 2.0 * pf;
+  const double m1 = (2.0 * CA1) * (0.125 * (b.r + c.r) * (nb + nc));
+  const double m2 = (2.0 * CA2) * (0.125 * (b.r + d.r) * (nb + nd));
+  const double m3 = (2.0 * CA2) * (0.125 * (a.r + c.r) * (na + nc));
+  f[0] = fma(m3, 2.0, fma(m2, 2.0, m1 * 2.0));
+  f[1] = fma(m3, a.u + c.u, fma(m2, b.u + d.u, m1 * (b.u + c.u)));
+  f[2] = fma(m3, a.v + c.v, fma(m2, b.v + d.v, m1 * (b.v + c.v)));
+  f[3] = fma(m3, a.w + c.w, fma(m2, b.w + d.w, m1 * (b.w + c.w)));
+  f[4] = fma(m3, a.h + c.h, fma(m2, b.h + d.h, m1 * (b.h + c.h)));
+  const double pf = fma(CA2, a.p + c.p, fma(CA2, b.p + d.p, CA1 * (b.p + c.p)));
+  f[1 + DIR] = f[1 + DIR] + pf;
 }
 
 // Pressure-only flux at a staggered wall (convective fluxes vanish there).
@@ -241,8 +248,7 @@ __device__ __forceinline__ void wall_flux_f64(const PV<double>& a, const PV<doub
                                               double f[5]) {
 #pragma clang fp contract(off)
   f[0] = f[1] = f[2] = f[3] = f[4] = 0.0;
-  const double pf = (CA1 * 0.5) * (b.p + c.p) + (CA2 * 0.5) * (b.p + d.p) + (CA2 * 0.5) * (a.p + c.p);
-  f[1 + DIR] = 2.0 * pf;
+  f[1 + DIR] = fma(CA2, a.p + c.p, fma(CA2, b.p + d.p, CA1 * (b.p + c.p)));
 }
 
 // Dispatch: FP64 uses the fixed-order forms above.
@@ -997,7 +1003,7 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
   auto load_col = [&](int plane, PV<F>& s) {
     double q[5];
     if (col_in) {
-      const size_t b = nidx(D, i, j, wrap1(plane, D.nz));  // plane in [-2, nz+3], nz >= 4
+      const int b = nidx32(D, i, j, wrap1(plane, D.nz));  // plane in [-2, nz+3], nz >= 4
 #pragma unroll
       for (int m = 0; m < 5; ++m) q[m] = w[(size_t)m * N + b];
     } else {
@@ -1046,7 +1052,7 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
         const int gi = i0 - 2 + lx, gj = j0 - 2 + ly;
         double q[5];
         if (tile_in) {
-          const size_t b = nidx(D, gi, gj, kk);
+          const int b = nidx32(D, gi, gj, kk);
 #pragma unroll
           for (int m = 0; m < 5; ++m) q[m] = w[(size_t)m * N + b];
         } else {
@@ -1073,7 +1079,7 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
     F Fzp[5] = {F(0), F(0), F(0), F(0), F(0)};
     if (c >= kb - 1 && c < ke && valid) {
       int ez = -1;
-      if (hybrid) ez = D.slot[2][nidx(D, i, j, wrap1(c, D.nz))];
+      if (hybrid) ez = D.slot[2][nidx32(D, i, j, wrap1(c, D.nz))];
       if (ez >= 0) {
 #pragma unroll
         for (int m = 0; m < 5; ++m) Fzp[m] = (F)D.Fw[2][(size_t)m * N + ez];
@@ -1084,7 +1090,7 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
     if (c >= kb && c < ke && valid) {
       const double didx = D.idx, diy = D.iy[j], didz = D.idz;
       double acc[5];
-      const size_t n0 = nidx(D, i, j, c);
+      const int n0 = nidx32(D, i, j, c);
       // x direction: interfaces i-1/2, i+1/2 from the LDS row
       {
         F fr[5], fl[5];
@@ -1136,7 +1142,7 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
             for (int m = 0; m < 5; ++m) fr[m] = (F)D.Fw[1][(size_t)m * N + er];
           }
           if (j > 0 || D.per_y) {
-            const int el = D.slot[1][j > 0 ? n0 - D.nx : n0 + (size_t)(D.ny - 1) * D.nx];
+            const int el = D.slot[1][j > 0 ? n0 - D.nx : n0 + (D.ny - 1) * D.nx];
             if (el >= 0) {
 #pragma unroll
               for (int m = 0; m < 5; ++m) fl[m] = (F)D.Fw[1][(size_t)m * N + el];
@@ -1233,7 +1239,7 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
         Ra2[3] += (double)az;
         Ra2[4] += (double)(o2.u * ax + o2.v * ay + o2.w * az);
       }
-      const size_t no = nidx(D, i, j, m2);
+      const int no = nidx32(D, i, j, m2);
 #pragma unroll
       for (int m = 0; m < 5; ++m) R[(size_t)m * N + no] = Ra2[m];
       fsum += Ra2[1] * D.y_eta[j];
