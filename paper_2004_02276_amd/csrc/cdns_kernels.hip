@@ -143,6 +143,46 @@ __device__ __forceinline__ void load_node(const Desc& D, const double* __restric
   for (int m = 0; m < 5; ++m) q[m] = w[(size_t)m * D.N + b];
 }
 
+// Reciprocal for the shock-capturing flux and the viscosity: in FP64 the
+// hardware estimate refined by two Newton steps (within one ulp of 1/x for
+// normal x, not correctly rounded), in FP32 the ordinary division.
+template <typename F>
+__device__ __forceinline__ F wrcp(F x) {
+  return F(1) / x;
+}
+template <>
+__device__ __forceinline__ double wrcp<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Square root of a positive normal x for the shock-capturing flux and the
+// viscosity: the
+// hardware reciprocal-square-root estimate refined by two coupled Newton
+// steps and a final residual correction (about one ulp; no scaling for
+// denormals or infinities, which a valid state never produces here; a
+// negative argument gives NaN like sqrt).  FP32: the ordinary square root.
+template <typename F>
+__device__ __forceinline__ F wsqrt(F x) {
+  return sqrt(x);
+}
+template <>
+__device__ __forceinline__ double wsqrt<double>(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
 // Primitive variables in the flux arithmetic F.
 template <typename F>
 struct PV {
@@ -184,7 +224,9 @@ __device__ __forceinline__ void to_prim<double>(const Desc& D, const double q[5]
   s.p = s.r * D.R * s.t;
   s.h = E + s.p * ir;
   const double tt = s.t * D.iTref;
-  s.mu = D.mu_ref * tt * sqrt(tt) * (1.0 + D.S) / (tt + D.S);
+  // viscosity: enters only the viscous terms, whose rounding is far below
+  // the tolerance, so the refined estimates are used here
+  s.mu = D.mu_ref * tt * wsqrt<double>(tt) * (1.0 + D.S) * wrcp<double>(tt + D.S);
 }
 
 // Energy-preserving central flux (eq. encflux with L = 2) at the interface
@@ -263,45 +305,6 @@ __device__ __forceinline__ void wflux(const PV<F>& a, const PV<F>& b, const PV<F
                                       const PV<F>& d, F f[5]) {
   if constexpr (sizeof(F) == 8) wall_flux_f64<DIR>(a, b, c, d, f);
   else wall_flux<F, DIR>(a, b, c, d, f);
-}
-
-// Reciprocal used by the shock-capturing flux: in FP64 the hardware estimate
-// refined by two Newton steps (within one ulp of 1/x for normal x, not
-// correctly rounded), in FP32 the ordinary division.
-template <typename F>
-__device__ __forceinline__ F wrcp(F x) {
-  return F(1) / x;
-}
-template <>
-__device__ __forceinline__ double wrcp<double>(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
-
-// Square root of a positive normal x for the shock-capturing flux: the
-// hardware reciprocal-square-root estimate refined by two coupled Newton
-// steps and a final residual correction (about one ulp; no scaling for
-// denormals or infinities, which a valid state never produces here; a
-// negative argument gives NaN like sqrt).  FP32: the ordinary square root.
-template <typename F>
-__device__ __forceinline__ F wsqrt(F x) {
-  return sqrt(x);
-}
-template <>
-__device__ __forceinline__ double wsqrt<double>(double x) {
-  const double y = __builtin_amdgcn_rsq(x);
-  double g = x * y, h = 0.5 * y;
-  double r = fma(-g, h, 0.5);
-  g = fma(g, r, g);
-  h = fma(h, r, h);
-  r = fma(-g, h, 0.5);
-  g = fma(g, r, g);
-  h = fma(h, r, h);
-  const double d = fma(-g, g, x);
-  return fma(d, h, g);
 }
 
 // WENO5-JS reconstruction at i+1/2 from v_{i-2..i+2}.  The argument `eps4`
