@@ -2,10 +2,12 @@
 """Throughput benchmark of the RK3 step of the compressible Navier-Stokes
 solver on one MI355X.
 
-Workload: the compressible channel 256x128x128 (4.19 M points, FP64 state,
-isothermal staggered walls on a tanh-stretched grid, bulk Mach 1.5,
-Re_b = 3000, hybrid central/WENO with the Ducros sensor, bulk forcing),
-synthetic seeded initial field.  A step is one full RK3 step (three
+Workload (default): the compressible channel 256x128x128 (4.19 M points,
+FP64 state, isothermal staggered walls on a tanh-stretched grid, bulk Mach
+1.5, Re_b = 3000, hybrid central/WENO with the Ducros sensor, bulk
+forcing), synthetic seeded initial field.  --workload sbli (shock on a
+boundary layer, 1024x256x128) and --workload tgv (32^3) give reference
+figures on the other two configurations.  A step is one full RK3 step (three
 stages of ghost planes, sensor, flag compaction, WENO on lists, fused
 right-hand side, forcing reduction and update), replayed from a HIP graph.
 
@@ -41,6 +43,17 @@ RHS_BYTES_PER_PT = 80.0
 # two characteristic projections, eigenvalue bounds) 444, Lax-Friedrichs
 # splitting 100, ten WENO5 reconstructions 690, back-projection 26.
 WENO_FLOPS_PER_IFACE = 1324.0
+
+
+# name -> (problem constructor name, description)
+WORKLOADS = {
+    "channel": ("channel", "compressible channel 256x128x128, FP64 state, hybrid central/WENO "
+                           "(Ducros sensor), bulk forcing, tanh-stretched walls, CFL 0.8"),
+    "sbli": ("sbli", "oblique shock on a laminar boundary layer 1024x256x128, FP64 state, hybrid "
+                     "central/WENO, Dirichlet inflow, characteristic outflow, adiabatic wall, "
+                     "imposed shock, CFL 0.8"),
+    "tgv": ("taylor_green", "Taylor-Green vortex 32^3, FP64 state, central only, CFL 0.8"),
+}
 
 
 def kernel_source_hash():
@@ -81,8 +94,8 @@ def cpu_baseline(pr):
             break
     rate = pr.npts * steps / el / 1e6
     return {"value": rate, "unit": "Mpoint-RK-steps/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"{steps} RK3 step(s) of the full {pr.nx}x{pr.ny}x{pr.nz} channel from the "
-                      f"same seeded initial field, {el:.1f} s wall"}
+            "sample": f"{steps} RK3 step(s) of the full {pr.name} workload from the same seeded "
+                      f"initial field, {el:.1f} s wall"}
 
 
 def main():
@@ -92,6 +105,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", choices=["fp64", "fp32flux"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=list(WORKLOADS), default="channel",
+                    help="channel (the headline workload), sbli or tgv (reference figures)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path (one simulation "
@@ -112,7 +127,7 @@ def main():
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
-    pr = P.channel()
+    pr = getattr(P, WORKLOADS[args.workload][0])()
     precision = 0 if args.precision == "fp64" else 1
     s = Solver(pr, precision=precision)
     cfl = pr.cfl
@@ -174,8 +189,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if precision == 0 else "f32-flux/f64-state",
         "data": "synthetic",
-        "config": {"workload": "compressible channel 256x128x128, FP64 state, hybrid central/WENO "
-                               "(Ducros sensor), bulk forcing, tanh-stretched walls, CFL 0.8",
+        "config": {"workload": WORKLOADS[args.workload][1],
                    "points": pr.npts, "parallelism": "single GPU"},
         "hbm_frac_step_algorithmic": hbm_frac_step,
         "phase_ms_per_step": per_step,
