@@ -78,7 +78,7 @@ enum { CDNS_SENSOR_OFF = 0, CDNS_SENSOR_HYBRID = 1, CDNS_SENSOR_WENO_ALL = 2 };
  *  DIRICHLET       x faces; params = primitive profile (rho,u,v,w,p) as
  *                  5 rows of ny values (row-major [5][ny]) imposed at the
  *                  ghost nodes (inflow).
- *  OUTFLOW_CHAR    x faces; characteristic extrapolation: the wave
+ *  OUTFLOW_CHAR    x and y faces; characteristic extrapolation: the wave
  *                  amplitudes of (w_b - w_{b-1}) travelling out of the
  *                  domain are extrapolated linearly, incoming ones are held
  *                  (Sec. 3.2: non-reflecting treatment by characteristic
@@ -87,14 +87,32 @@ enum { CDNS_SENSOR_OFF = 0, CDNS_SENSOR_HYBRID = 1, CDNS_SENSOR_WENO_ALL = 2 };
  *  SHOCK_TOP       y faces; params = {i_shock, rho1,u1,v1,w1,p1,
  *                  rho2,u2,v2,w2,p2}: ghost nodes take state 1 for
  *                  i < i_shock and state 2 otherwise (imposed inviscid
- *                  oblique-shock solution, Sec. 3.3). */
+ *                  oblique-shock solution, Sec. 3.3).
+ *  DF_INFLOW       x- face only; synthetic inflow turbulence by digital
+ *                  filtering (Sec. 3.2).  params = {Ny, Nz, T, seed,
+ *                  b_y[2Ny+1], b_z[2Nz+1], mean (rho,u,v,w,p) [5][ny],
+ *                  lower Cholesky factor of the Reynolds stresses
+ *                  (a11,a21,a22,a31,a32,a33) [6][ny]}.  Deviates uniform
+ *                  on [-sqrt 3, sqrt 3) from SplitMix64 (output n of the
+ *                  generator seeded with `seed`, n = 1 + (((key*3 + c)*nz +
+ *                  k)*(ny + 2Ny) + jj) for component c, plane k, extended
+ *                  row jj; key 0 for the initial plane made by this call,
+ *                  key s + 1 at the start of step s); filtered along y then
+ *                  z (periodic) with the given coefficients; time
+ *                  correlation psi = psi E + psi_hat sqrt(1 - E^2),
+ *                  E = exp(-pi dt/(2T)); fluctuations u'_i = a_ij psi_j;
+ *                  T' = -u_mean u'/c_p at constant pressure (strong
+ *                  Reynolds analogy).  The plane is refreshed once per RK
+ *                  step and imposed on the three ghost layers.  Not
+ *                  accepted by batches. */
 enum {
   CDNS_BC_PERIODIC = 0,
   CDNS_BC_WALL_ISOTHERMAL = 1,
   CDNS_BC_WALL_ADIABATIC = 2,
   CDNS_BC_DIRICHLET = 3,
   CDNS_BC_OUTFLOW_CHAR = 4,
-  CDNS_BC_SHOCK_TOP = 5
+  CDNS_BC_SHOCK_TOP = 5,
+  CDNS_BC_DF_INFLOW = 6
 };
 
 typedef struct {
@@ -218,6 +236,9 @@ cdns_status cdns_destroy(cdns_ctx* ctx);
 cdns_status cdns_batch_create(int32_t max_slots, void* workspace_dev, size_t workspace_bytes,
                               void* hip_stream, cdns_batch** out);
 size_t cdns_batch_workspace_bytes(int32_t max_slots);
+/* Attach a context (its tile shape and precision must match the batch's);
+ * *slot receives its slot.  CDNS_EBUSY: already attached or no free slot;
+ * CDNS_EUNSUP: the context uses digital-filter inflow. */
 cdns_status cdns_batch_attach(cdns_batch* b, cdns_ctx* ctx, int32_t* slot);
 cdns_status cdns_batch_detach(cdns_batch* b, int32_t slot);
 /* nsteps RK3 steps of every attached instance; each uses its own cfl /

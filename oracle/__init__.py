@@ -9,7 +9,11 @@ sides receive the same seeded inputs from the `problems` package.
 Parity status: every operator is pinned by CPU tests against closed forms,
 invariants or exact solutions (see tests/test_oracle_*.py); the
 characteristic outflow boundary is pinned only by a behaviour check
-(acoustic pulse reflection), so it is "parity unpinned" against the paper.
+(acoustic pulse reflection), so it is "parity unpinned" against the paper;
+the digital-filter inflow generator is pinned by the published SplitMix64
+reference outputs and by its statistics (unit variance of the filtered
+field, prescribed Reynolds stresses, filter and time correlations), its
+constants are readings (the paper gives the method only).
 """
 from __future__ import annotations
 
@@ -58,6 +62,7 @@ class _Problem(ctypes.Structure):
         ("bc_kind", ctypes.c_int32 * 6),
         ("bc_params", ctypes.POINTER(ctypes.c_double) * 6),
         ("bc_nparams", ctypes.c_int32 * 6),
+        ("df_plane", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -92,6 +97,11 @@ def _load():
         lib.ora_iface_flux.restype = ctypes.c_int
         lib.ora_num_threads.argtypes = []
         lib.ora_num_threads.restype = ctypes.c_int
+        lib.ora_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        lib.ora_splitmix64.restype = ctypes.c_uint64
+        lib.ora_df_update.argtypes = [pp, ctypes.c_uint64, ctypes.c_double, ctypes.c_int, dp, dp,
+                                      dp]
+        lib.ora_df_update.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -234,3 +244,22 @@ def iface_flux(pr, d: int, w: Optional[np.ndarray] = None) -> np.ndarray:
 
 def num_threads() -> int:
     return _load().ora_num_threads()
+
+
+def splitmix64(seed: int, n: int) -> int:
+    """Output n (n >= 1) of the SplitMix64 generator seeded with `seed`."""
+    return int(_load().ora_splitmix64(ctypes.c_uint64(seed), ctypes.c_uint64(n)))
+
+
+def df_update(pr, key: int, dt: float, first: bool, psi: Optional[np.ndarray] = None):
+    """One update of the digital-filter inflow generator of `pr` (face x-).
+    Returns (psi [3][nz][ny], conserved plane [5][nz][ny], velocity
+    fluctuations [3][nz][ny])."""
+    lib = _load()
+    psi = np.zeros((3, pr.nz, pr.ny)) if psi is None else np.ascontiguousarray(psi, np.float64).copy()
+    plane = np.zeros((5, pr.nz, pr.ny))
+    fl = np.zeros((3, pr.nz, pr.ny))
+    m = _Marshalled(pr)
+    _check(lib.ora_df_update(ctypes.byref(m.s), ctypes.c_uint64(key), float(dt), int(bool(first)),
+                             _dptr(psi), _dptr(plane), _dptr(fl)), "ora_df_update")
+    return psi, plane, fl

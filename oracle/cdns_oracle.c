@@ -32,7 +32,7 @@
 #define H 3
 
 enum { BC_PERIODIC = 0, BC_WALL_ISO = 1, BC_WALL_ADIA = 2, BC_DIRICHLET = 3,
-       BC_OUTFLOW = 4, BC_SHOCK_TOP = 5 };
+       BC_OUTFLOW = 4, BC_SHOCK_TOP = 5, BC_DF_INFLOW = 6 };
 enum { T_CONV = 1, T_PRES = 2, T_VISC = 4, T_FORCE = 8, T_ALL = 15 };
 enum { ORA_OK = 0, ORA_EINVAL = -1, ORA_ENOMEM = -2, ORA_ESTATE = -4, ORA_EUNSUP = -5 };
 
@@ -49,6 +49,9 @@ typedef struct {
   int32_t bc_kind[6];
   const double* bc_params[6];
   int32_t bc_nparams[6];
+  /* digital-filter inflow plane to use (conserved [5][nz][ny]); NULL: the
+   * initial plane of the generator (see df_plane) */
+  const double* df_plane;
 } ora_problem;
 
 /* Standard 4th-order central coefficients (Sec. 2.1): first derivative
@@ -200,6 +203,146 @@ double ora_weno5(const double* v) {
   return (a0 * q0 + a1 * q1 + a2 * q2) / sum;
 }
 
+/* ------------------------------------------------------------ inflow turbulence
+ * Synthetic inflow turbulence by digital filtering (Sec. 3.2: the DF method
+ * with the filtering split into one-dimensional convolutions and the
+ * strong Reynolds analogy for the thermodynamic fluctuations).  Readings
+ * (the paper gives the method, not its constants):
+ *  - deviates: zero mean, unit variance, uniform on [-sqrt 3, sqrt 3) from
+ *    the counter-based SplitMix64 generator (output n of the generator
+ *    seeded with `seed`), n = 1 + (((key*3 + c)*nz + k)*(ny + 2 Ny) + jj)
+ *    for velocity component c, plane k, extended row jj, and key = 0 for
+ *    the initial plane, key = s + 1 at the start of step s;
+ *  - filters: Gaussian coefficients b_l (l = -N..N), normalised to unit
+ *    sum of squares, supplied by the caller; applied along y (over the
+ *    extended rows) and then along z (periodic), each as a sum in
+ *    increasing l;
+ *  - time correlation: psi = psi E + psi_hat sqrt(1 - E^2) with
+ *    E = exp(-pi dt / (2 T)); the initial plane takes psi = psi_hat;
+ *  - fluctuations u'_i = a_ij psi_j with a the lower Cholesky factor of
+ *    the Reynolds stresses (supplied per row j), temperature from the
+ *    strong Reynolds analogy with constant total enthalpy, T' = -u_mean u'/c_p,
+ *    constant pressure, so rho = p/(R (T_mean + T')).
+ * Parameters (face x-): [Ny, Nz, T, seed, b_y[2Ny+1], b_z[2Nz+1],
+ * mean rho, u, v, w, p [5][ny], a11, a21, a22, a31, a32, a33 [6][ny]]. */
+uint64_t ora_splitmix64(uint64_t seed, uint64_t n) {
+  uint64_t z = seed + n * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+static double df_deviate(uint64_t seed, uint64_t n) {
+  const double u = (double)(ora_splitmix64(seed, n) >> 11) * 0x1.0p-53;
+  return (2.0 * u - 1.0) * 1.7320508075688772;
+}
+
+static int df_layout(const ora_problem* P, int* Ny, int* Nz) {
+  const double* pr = P->bc_params[0];
+  if (P->bc_nparams[0] < 4) return ORA_EINVAL;
+  *Ny = (int)pr[0];
+  *Nz = (int)pr[1];
+  if (*Ny < 0 || *Nz < 0 || !(pr[2] > 0.0)) return ORA_EINVAL;
+  if (P->bc_nparams[0] != 4 + (2 * *Ny + 1) + (2 * *Nz + 1) + 11 * P->ny) return ORA_EINVAL;
+  return ORA_OK;
+}
+
+/* One update of the filtered field psi[3][nz][ny] (first: psi = psi_hat)
+ * and the resulting conserved inflow plane[5][nz][ny]; fl (may be NULL)
+ * receives the velocity fluctuations [3][nz][ny]. */
+int ora_df_update(const ora_problem* P, uint64_t key, double dt, int first, double* psi,
+                  double* plane, double* fl) {
+  int Ny, Nz;
+  int st = df_layout(P, &Ny, &Nz);
+  if (st) return st;
+  const int ny = P->ny, nz = P->nz, nyr = ny + 2 * Ny;
+  const double* pr = P->bc_params[0];
+  const double TL = pr[2];
+  const uint64_t seed = (uint64_t)pr[3];
+  const double* by = pr + 4;
+  const double* bz = by + 2 * Ny + 1;
+  const double* mean = bz + 2 * Nz + 1;
+  const double* chol = mean + 5 * ny;
+  double* fy = malloc((size_t)3 * nz * ny * sizeof(double));
+  if (!fy) return ORA_ENOMEM;
+  for (int c = 0; c < 3; ++c)
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < ny; ++j) {
+        double acc = 0.0;
+        for (int l = -Ny; l <= Ny; ++l) {
+          uint64_t n = 1 + (((key * 3 + (uint64_t)c) * (uint64_t)nz + (uint64_t)k) * (uint64_t)nyr +
+                            (uint64_t)(j + l + Ny));
+          acc += by[l + Ny] * df_deviate(seed, n);
+        }
+        fy[((size_t)c * nz + k) * ny + j] = acc;
+      }
+  const double E = exp(-3.141592653589793 * dt / (2.0 * TL));
+  const double F = sqrt(1.0 - E * E);
+  const double cp = P->gamma * P->R_gas / (P->gamma - 1.0);
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j) {
+      double ps[3];
+      for (int c = 0; c < 3; ++c) {
+        double acc = 0.0;
+        for (int m = -Nz; m <= Nz; ++m) {
+          int kk = ((k + m) % nz + nz) % nz;
+          acc += bz[m + Nz] * fy[((size_t)c * nz + kk) * ny + j];
+        }
+        size_t q = ((size_t)c * nz + k) * ny + j;
+        psi[q] = first ? acc : psi[q] * E + acc * F;
+        ps[c] = psi[q];
+      }
+      const double a11 = chol[j], a21 = chol[ny + j], a22 = chol[2 * ny + j];
+      const double a31 = chol[3 * ny + j], a32 = chol[4 * ny + j], a33 = chol[5 * ny + j];
+      const double du = a11 * ps[0];
+      const double dv = a21 * ps[0] + a22 * ps[1];
+      const double dw = a31 * ps[0] + a32 * ps[1] + a33 * ps[2];
+      const double rm = mean[j], um = mean[ny + j], vm = mean[2 * ny + j], wm = mean[3 * ny + j];
+      const double pm = mean[4 * ny + j];
+      const double Tm = pm / (rm * P->R_gas);
+      const double T = Tm - um * du / cp;
+      double qc[5];
+      from_prim(P, pm / (P->R_gas * T), um + du, vm + dv, wm + dw, pm, qc);
+      for (int m = 0; m < 5; ++m) plane[((size_t)m * nz + k) * ny + j] = qc[m];
+      if (fl) {
+        fl[((size_t)0 * nz + k) * ny + j] = du;
+        fl[((size_t)1 * nz + k) * ny + j] = dv;
+        fl[((size_t)2 * nz + k) * ny + j] = dw;
+      }
+    }
+  free(fy);
+  return ORA_OK;
+}
+
+/* Characteristic extrapolation through a face (Sec. 3.2, non-reflecting
+ * boundaries): only waves leaving the domain are extrapolated from the two
+ * nodes next to the face, incoming ones are held; d is the face normal,
+ * qb the boundary node, qi its interior neighbour, out[s-1] ghost s. */
+static void char_ghosts(const ora_problem* P, const geom* g, int d, int hi, const double qb[5],
+                        const double qi[5], double out[H][5]) {
+  double dq[5];
+  for (int m = 0; m < 5; ++m) dq[m] = qb[m] - qi[m];
+  prim_t s0 = to_prim(P, g, qb);
+  double c = sqrt(P->gamma * s0.p / s0.rho);
+  double Rn[25], Ln[25];
+  ora_eigenvectors(P->gamma, d, s0.u, s0.v, s0.w, s0.Ht, Rn, Ln);
+  double un = d == 0 ? s0.u : (d == 1 ? s0.v : s0.w);
+  double lam[5] = {un - c, un, un, un, un + c};
+  double dv[5];
+  for (int a = 0; a < 5; ++a) {
+    double acc = 0.0;
+    for (int b = 0; b < 5; ++b) acc += Ln[a * 5 + b] * dq[b];
+    int outgoing = hi ? (lam[a] > 0.0) : (lam[a] < 0.0);
+    dv[a] = outgoing ? acc : 0.0;
+  }
+  for (int s = 1; s <= H; ++s)
+    for (int m = 0; m < 5; ++m) {
+      double acc = 0.0;
+      for (int a = 0; a < 5; ++a) acc += Rn[m * 5 + a] * dv[a];
+      out[s - 1][m] = qb[m] + (double)s * acc;
+    }
+}
+
 /* ------------------------------------------------------------ ghost nodes */
 static int fill_ghosts(const ora_problem* P, const geom* g, double* W[5]) {
   const int nx = g->nx, ny = g->ny, nz = g->nz;
@@ -225,36 +368,23 @@ static int fill_ghosts(const ora_problem* P, const geom* g, double* W[5]) {
             for (int m = 0; m < 5; ++m) W[m][pidx(g, gi, j, k)] = q[m];
           }
         } else if (kind == BC_OUTFLOW) {
-          /* characteristic extrapolation: only waves leaving the domain are
-           * extrapolated from the two boundary nodes, incoming ones are held */
           int ib = side == 0 ? 0 : nx - 1;
           int ii = side == 0 ? 1 : nx - 2;
-          double qb[5], qi[5], dq[5];
+          double qb[5], qi[5], gq[H][5];
           for (int m = 0; m < 5; ++m) {
             qb[m] = W[m][pidx(g, ib, j, k)];
             qi[m] = W[m][pidx(g, ii, j, k)];
-            dq[m] = qb[m] - qi[m];
           }
-          prim_t s0 = to_prim(P, g, qb);
-          double c = sqrt(P->gamma * s0.p / s0.rho);
-          double Rn[25], Ln[25];
-          ora_eigenvectors(P->gamma, 0, s0.u, s0.v, s0.w, s0.Ht, Rn, Ln);
-          double lam[5] = {s0.u - c, s0.u, s0.u, s0.u, s0.u + c};
-          double dv[5];
-          for (int a = 0; a < 5; ++a) {
-            double acc = 0.0;
-            for (int b = 0; b < 5; ++b) acc += Ln[a * 5 + b] * dq[b];
-            int outgoing = side == 0 ? (lam[a] < 0.0) : (lam[a] > 0.0);
-            dv[a] = outgoing ? acc : 0.0;
-          }
+          char_ghosts(P, g, 0, side, qb, qi, gq);
           for (int s = 1; s <= H; ++s) {
             int gi = side == 0 ? -s : nx - 1 + s;
-            for (int m = 0; m < 5; ++m) {
-              double acc = 0.0;
-              for (int a = 0; a < 5; ++a) acc += Rn[m * 5 + a] * dv[a];
-              W[m][pidx(g, gi, j, k)] = qb[m] + (double)s * acc;
-            }
+            for (int m = 0; m < 5; ++m) W[m][pidx(g, gi, j, k)] = gq[s - 1][m];
           }
+        } else if (kind == BC_DF_INFLOW && side == 0) {
+          /* the inflow plane of the current step, the same on every layer */
+          for (int s = 1; s <= H; ++s)
+            for (int m = 0; m < 5; ++m)
+              W[m][pidx(g, -s, j, k)] = P->df_plane[((size_t)m * nz + k) * ny + j];
         } else {
           return ORA_EUNSUP;
         }
@@ -287,6 +417,16 @@ static int fill_ghosts(const ora_problem* P, const geom* g, double* W[5]) {
             int ish = (int)pr[0];
             const double* st = i < ish ? pr + 1 : pr + 6;
             from_prim(P, st[0], st[1], st[2], st[3], st[4], q);
+          } else if (kind == BC_OUTFLOW) {
+            int jb = side == 0 ? 0 : ny - 1;
+            int ji = side == 0 ? 1 : ny - 2;
+            double qb[5], qi[5], gq[H][5];
+            for (int m = 0; m < 5; ++m) {
+              qb[m] = W[m][pidx(g, i, jb, k)];
+              qi[m] = W[m][pidx(g, i, ji, k)];
+            }
+            char_ghosts(P, g, 1, side, qb, qi, gq);
+            for (int m = 0; m < 5; ++m) q[m] = gq[s - 1][m];
           } else {
             return ORA_EUNSUP;
           }
@@ -317,8 +457,14 @@ static int validate(const ora_problem* P) {
     int ax = f / 2;
     if (k == BC_PERIODIC) continue;
     if (ax == 2) return ORA_EUNSUP;
-    if (ax == 0 && !(k == BC_DIRICHLET || k == BC_OUTFLOW)) return ORA_EUNSUP;
-    if (ax == 1 && !(k == BC_WALL_ISO || k == BC_WALL_ADIA || k == BC_SHOCK_TOP)) return ORA_EUNSUP;
+    if (ax == 0 && !(k == BC_DIRICHLET || k == BC_OUTFLOW || (k == BC_DF_INFLOW && f == 0)))
+      return ORA_EUNSUP;
+    if (ax == 1 && !(k == BC_WALL_ISO || k == BC_WALL_ADIA || k == BC_SHOCK_TOP || k == BC_OUTFLOW))
+      return ORA_EUNSUP;
+    if (k == BC_DF_INFLOW) {
+      int Ny, Nz;
+      if (df_layout(P, &Ny, &Nz)) return ORA_EINVAL;
+    }
     if (k == BC_DIRICHLET && P->bc_nparams[f] != 5 * P->ny) return ORA_EINVAL;
     if (k == BC_WALL_ISO && P->bc_nparams[f] != 1) return ORA_EINVAL;
     if (k == BC_SHOCK_TOP && P->bc_nparams[f] != 11) return ORA_EINVAL;
@@ -788,7 +934,21 @@ static int rhs_core(const ora_problem* P, const double* w, double* r, double* th
  * optional outputs; forcing_out receives the bulk force. */
 int ora_rhs(const ora_problem* P, const double* w, double* r, double* theta,
             unsigned char* nflags, unsigned char* iflags, double* forcing_out) {
-  return rhs_core(P, w, r, theta, nflags, iflags, forcing_out);
+  if (P->bc_kind[0] != BC_DF_INFLOW || P->df_plane)
+    return rhs_core(P, w, r, theta, nflags, iflags, forcing_out);
+  /* digital-filter inflow without a plane: the initial plane (key 0) */
+  int st = validate(P);
+  if (st) return st;
+  size_t np = (size_t)P->nz * P->ny;
+  double* psi = malloc(3 * np * sizeof(double));
+  double* plane = malloc(5 * np * sizeof(double));
+  if (!psi || !plane) { free(psi); free(plane); return ORA_ENOMEM; }
+  ora_problem Q = *P;
+  st = ora_df_update(P, 0, 0.0, 1, psi, plane, NULL);
+  Q.df_plane = plane;
+  if (!st) st = rhs_core(&Q, w, r, theta, nflags, iflags, forcing_out);
+  free(psi); free(plane);
+  return st;
 }
 
 /* Time step (the paper gives no rule): dt = CFL * min(1/max_i sum_d (|u_d|+c)/dx_d,
@@ -840,7 +1000,10 @@ void ora_rk_stage(size_t n, const double* w, const double* r, const double* rpre
 
 /* Advance nsteps RK3 steps in place.  dt_fixed > 0 overrides the CFL rule;
  * otherwise dt is taken from the state at the start of each step.  dts (if
- * not NULL, length nsteps) receives the steps used. */
+ * not NULL, length nsteps) receives the steps used.  With digital-filter
+ * inflow the generator starts from its initial plane (key 0) and is
+ * updated at the start of every step s with key s + 1, so one call of
+ * nsteps steps is the reference for a fresh GPU context. */
 int ora_advance(const ora_problem* P, double* w, int nsteps, double cfl, double dt_fixed,
                 double* dts) {
   int st = validate(P);
@@ -849,7 +1012,19 @@ int ora_advance(const ora_problem* P, double* w, int nsteps, double cfl, double 
   double* r = malloc(n5 * sizeof(double));
   double* rp = malloc(n5 * sizeof(double));
   double* ws = malloc(n5 * sizeof(double));
-  if (!r || !rp || !ws) { free(r); free(rp); free(ws); return ORA_ENOMEM; }
+  const int df = P->bc_kind[0] == BC_DF_INFLOW;
+  size_t np = (size_t)P->nz * P->ny;
+  double* psi = df ? malloc(3 * np * sizeof(double)) : NULL;
+  double* plane = df ? malloc(5 * np * sizeof(double)) : NULL;
+  if (!r || !rp || !ws || (df && (!psi || !plane))) {
+    free(r); free(rp); free(ws); free(psi); free(plane);
+    return ORA_ENOMEM;
+  }
+  ora_problem Q = *P;
+  if (df) {
+    st = ora_df_update(P, 0, 0.0, 1, psi, plane, NULL);
+    Q.df_plane = plane;
+  }
   for (int step = 0; step < nsteps && st == ORA_OK; ++step) {
     double dt = dt_fixed;
     if (!(dt_fixed > 0.0)) {
@@ -857,15 +1032,16 @@ int ora_advance(const ora_problem* P, double* w, int nsteps, double cfl, double 
       if (st) break;
     }
     if (dts) dts[step] = dt;
+    if (df && (st = ora_df_update(P, (uint64_t)step + 1, dt, 0, psi, plane, NULL))) break;
     for (int l = 0; l < 3; ++l) {
-      st = rhs_core(P, w, r, NULL, NULL, NULL, NULL);
+      st = rhs_core(&Q, w, r, NULL, NULL, NULL, NULL);
       if (st) break;
       ora_rk_stage(n5, w, r, rp, dt, l, ws);
       memcpy(w, ws, n5 * sizeof(double));
       double* t = rp; rp = r; r = t;
     }
   }
-  free(r); free(rp); free(ws);
+  free(r); free(rp); free(ws); free(psi); free(plane);
   return st;
 }
 

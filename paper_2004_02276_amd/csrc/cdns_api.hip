@@ -40,7 +40,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t metric, bcp, w1, w2, ra, rb, nflag, slot, theta, fw, list, count, gx, gy, part, red,
+  size_t metric, bcp, w1, w2, ra, rb, nflag, slot, theta, fw, list, count, gx, gy, df, part, red,
       redd, scal, status, diag, total;
   size_t bcp_cap, part_cap;
 };
@@ -55,7 +55,10 @@ Layout layout_of(const cdns_grid* g) {
   const size_t nx = g->nx, ny = g->ny, nz = g->nz;
   const size_t N = nx * ny * nz;
   const size_t nxg = nx + 2 * cdns::kHalo;
+  // largest parameter set: the digital-filter inflow, 4 + (2 Ny + 1) +
+  // (2 Nz + 1) + 11 ny values with filter half-widths Ny <= ny, Nz <= nz
   L.bcp_cap = std::max<size_t>(16, 5 * std::max(nx, ny));
+  L.bcp_cap = std::max<size_t>(L.bcp_cap, 6 + 13 * ny + 2 * nz);
   // largest number of fused-kernel blocks over the compiled tile shapes (kz >= 1)
   L.part_cap = ((nx + 31) / 32) * ((ny + 1) / 2) * nz;
   size_t o = 0;
@@ -78,6 +81,7 @@ Layout layout_of(const cdns_grid* g) {
   L.count = take(4 * sizeof(unsigned));
   L.gx = take(2 * 5 * cdns::kHalo * nz * ny * sizeof(double));
   L.gy = take(2 * 5 * cdns::kHalo * nz * nxg * sizeof(double));
+  L.df = take(2 * 3 * nz * ny * sizeof(double));
   L.part = take(L.part_cap * sizeof(double));
   L.red = take(2 * cdns::kRedBlocks * sizeof(double));
   L.redd = take((size_t)cdns::DG_COUNT * cdns::kRedBlocks * sizeof(double));
@@ -143,6 +147,8 @@ hipError_t enqueue_rhs_phases(const Desc& D, int stage, bool export_theta, hipSt
 hipError_t enqueue_step(const Desc& D, hipStream_t st) {
   hipError_t e;
   if ((e = cdns::launch_dt(D, st)) != hipSuccess) return e;
+  // inflow plane of this step (needs the step's dt and counter)
+  if (D.bc[0] == cdns::BC_DF_INFLOW && (e = cdns::launch_df(D, false, st)) != hipSuccess) return e;
   for (int stage = 0; stage < 3; ++stage) {
     if ((e = enqueue_rhs_phases(D, stage, false, st)) != hipSuccess) return e;
     if ((e = cdns::launch_rk(D, stage, st)) != hipSuccess) return e;
@@ -266,6 +272,8 @@ cdns_status cdns_create(const cdns_grid* grid, const cdns_phys* phys, int32_t pr
   const size_t gys = (size_t)5 * cdns::kHalo * nz * D.nxg;
   D.gx[0] = (double*)(ws + L.gx);
   D.gx[1] = D.gx[0] + gxs;
+  D.dfpsi = (double*)(ws + L.df);
+  D.dffy = D.dfpsi + (size_t)3 * nz * ny;
   D.gy[0] = (double*)(ws + L.gy);
   D.gy[1] = D.gy[0] + gys;
   D.part = (double*)(ws + L.part);
@@ -308,17 +316,30 @@ cdns_status cdns_set_bc(cdns_ctx* c, int32_t face, int32_t kind, const double* p
                         int64_t nparams) {
   if (!c) return CDNS_EINVAL;
   if (face < 0 || face > 5) return fail(c, CDNS_EINVAL, "face out of range");
-  if (kind < 0 || kind > 5) return fail(c, CDNS_EINVAL, "unknown boundary kind");
+  if (kind < 0 || kind > 6) return fail(c, CDNS_EINVAL, "unknown boundary kind");
   if (nparams < 0 || (nparams > 0 && !params)) return fail(c, CDNS_EINVAL, "bad parameters");
   const int ax = face / 2;
   Desc& D = c->D;
   if (kind != cdns::BC_PERIODIC) {
     if (ax == 2) return fail(c, CDNS_EUNSUP, "z faces must be periodic");
-    if (ax == 0 && !(kind == cdns::BC_DIRICHLET || kind == cdns::BC_OUTFLOW))
-      return fail(c, CDNS_EUNSUP, "x faces accept periodic, Dirichlet or characteristic outflow");
+    if (ax == 0 && !(kind == cdns::BC_DIRICHLET || kind == cdns::BC_OUTFLOW ||
+                     (kind == cdns::BC_DF_INFLOW && face == 0)))
+      return fail(c, CDNS_EUNSUP,
+                  "x faces accept periodic, Dirichlet, characteristic outflow or (x-) digital-filter inflow");
     if (ax == 1 && !(kind == cdns::BC_WALL_ISO || kind == cdns::BC_WALL_ADIA ||
-                     kind == cdns::BC_SHOCK_TOP))
-      return fail(c, CDNS_EUNSUP, "y faces accept periodic, walls or an imposed shock state");
+                     kind == cdns::BC_SHOCK_TOP || kind == cdns::BC_OUTFLOW))
+      return fail(c, CDNS_EUNSUP,
+                  "y faces accept periodic, walls, an imposed shock state or characteristic outflow");
+    if (kind == cdns::BC_DF_INFLOW) {
+      if (nparams < 4) return fail(c, CDNS_EINVAL, "digital-filter inflow needs parameters");
+      const double nyh = params[0], nzh = params[1];
+      if (!(nyh >= 0.0 && nyh <= D.ny && nzh >= 0.0 && nzh <= D.nz) || nyh != (double)(int)nyh ||
+          nzh != (double)(int)nzh || !(params[2] > 0.0) || !(params[3] >= 0.0) ||
+          params[3] != (double)(uint64_t)params[3])
+        return fail(c, CDNS_EINVAL, "digital-filter half-widths, time scale or seed invalid");
+      if (nparams != 4 + (2 * (int64_t)nyh + 1) + (2 * (int64_t)nzh + 1) + 11LL * D.ny)
+        return fail(c, CDNS_EINVAL, "digital-filter parameter count does not match the layout");
+    }
     if (kind == cdns::BC_DIRICHLET && nparams != 5LL * D.ny)
       return fail(c, CDNS_EINVAL, "Dirichlet profile needs 5*ny values");
     if (kind == cdns::BC_WALL_ISO && (nparams != 1 || !(params[0] > 0.0)))
@@ -340,6 +361,12 @@ cdns_status cdns_set_bc(cdns_ctx* c, int32_t face, int32_t kind, const double* p
   D.wall_lo = D.bc[2] == cdns::BC_WALL_ISO || D.bc[2] == cdns::BC_WALL_ADIA;
   D.wall_hi = D.bc[3] == cdns::BC_WALL_ISO || D.bc[3] == cdns::BC_WALL_ADIA;
   invalidate_graph(c);
+  if (kind == cdns::BC_DF_INFLOW) {
+    // the initial inflow plane (generator key 0)
+    hipError_t e = cdns::launch_df(D, true, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "inflow generator");
+  }
   return CDNS_OK;
 }
 
@@ -533,6 +560,8 @@ cdns_status cdns_time_phases(cdns_ctx* c, int32_t nsteps, double cfl, double dt_
   if (D.sensor_mode > 0) e = cdns::launch_count_iface(D, true, st);
   for (int step = 0; step < nsteps && e == hipSuccess; ++step) {
     timed(CDNS_PH_DT, [&] { return cdns::launch_dt(D, st); });
+    if (D.bc[0] == cdns::BC_DF_INFLOW)
+      timed(CDNS_PH_GHOSTS, [&] { return cdns::launch_df(D, false, st); });
     for (int stage = 0; stage < 3; ++stage) {
       if (D.sensor_mode == 2 && e == hipSuccess) e = cdns::launch_stage_begin(D, st);
       if (cdns::ghosts_needed(D))

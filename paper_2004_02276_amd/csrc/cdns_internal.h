@@ -13,7 +13,7 @@ constexpr int kRedBlocks = 1024;  // partial-sum slots of the generic reductions
 
 // Boundary kinds (same values as the C ABI).
 enum { BC_PERIODIC = 0, BC_WALL_ISO = 1, BC_WALL_ADIA = 2, BC_DIRICHLET = 3,
-       BC_OUTFLOW = 4, BC_SHOCK_TOP = 5 };
+       BC_OUTFLOW = 4, BC_SHOCK_TOP = 5, BC_DF_INFLOW = 6 };
 
 // Device status bits.
 enum { ST_BAD_STATE = 1u, ST_BAD_GHOST = 2u };
@@ -61,6 +61,8 @@ struct Desc {
   int* list[3];                   // [N] compacted interface lists per direction
   unsigned* count;                // [4] list lengths
   double* gx[2];                  // [5][3][nz][ny] x-face ghost planes
+  double* dfpsi;                  // [3][nz][ny] filtered inflow field (digital filter)
+  double* dffy;                   // [3][nz][ny] inflow deviates filtered along y
   double* gy[2];                  // [5][3][nz][nxg] y-face ghost planes
   double* part;                   // [npart] right-hand-side block partial sums (forcing)
   int npart;
@@ -90,6 +92,9 @@ hipError_t launch_dt(const Desc& D, hipStream_t st);
 hipError_t launch_diag(const Desc& D, hipStream_t st);
 hipError_t launch_export_iflags(const Desc& D, uint8_t* out, hipStream_t st);
 hipError_t launch_count_iface(const Desc& D, bool reset, hipStream_t st);  // scal[SC_WACC]
+// digital-filter inflow: the initial plane (key 0), or the update at the
+// start of the current step (key = scal[SC_STEP], dt = scal[SC_DT])
+hipError_t launch_df(const Desc& D, bool initial, hipStream_t st);
 hipError_t launch_export_iface(const Desc& D, int dir, double* out, hipStream_t st);
 bool rhs_tile_supported(int tx, int ty);
 int rhs_blocks(const Desc& D);

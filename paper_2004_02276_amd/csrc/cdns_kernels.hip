@@ -439,6 +439,46 @@ __global__ void k_stage_begin(Desc D) {
 
 // ------------------------------------------------------------------ ghost planes
 
+// Characteristic extrapolation through a face with normal DIR (Sec. 3.2,
+// non-reflecting boundaries): the amplitudes of (q_b - q_i) on the waves
+// leaving the domain are extrapolated linearly, incoming ones are held.
+// qb is the boundary node, qi its interior neighbour, hi the upper face;
+// gq[s] receives ghost layer s+1.
+template <int DIR>
+__device__ __forceinline__ void char_ghosts(const Desc& D, const double qb[5], const double qi[5],
+                                            bool hi, double gq[kHalo][5]) {
+  constexpr int PN = 1 + DIR, P1 = 1 + (DIR + 1) % 3, P2 = 1 + (DIR + 2) % 3;
+  const double r = qb[0], ir = 1.0 / r;
+  const double u = qb[PN] * ir, v = qb[P1] * ir, ww = qb[P2] * ir;  // normal, tangential
+  const double p = D.gm1 * (qb[4] - 0.5 * r * (u * u + v * v + ww * ww));
+  const double c = sqrt(D.gamma * p * ir);
+  const double H = (qb[4] + p) * ir;
+  const double q2 = u * u + v * v + ww * ww;
+  const double ic = 1.0 / c, b1 = D.gm1 * ic * ic, b2 = 0.5 * q2 * b1;
+  // differences in the permuted order (rho, m_n, m_t1, m_t2, E)
+  const double d0 = qb[0] - qi[0], d1 = qb[PN] - qi[PN], d2 = qb[P1] - qi[P1];
+  const double d3 = qb[P2] - qi[P2], d4 = qb[4] - qi[4];
+  double a0 = 0.5 * (b2 + u * ic) * d0 - 0.5 * (b1 * u + ic) * d1 - 0.5 * b1 * v * d2 -
+              0.5 * b1 * ww * d3 + 0.5 * b1 * d4;
+  double a1 = (1.0 - b2) * d0 + b1 * u * d1 + b1 * v * d2 + b1 * ww * d3 - b1 * d4;
+  double a2 = -v * d0 + d2;
+  double a3 = -ww * d0 + d3;
+  double a4 = 0.5 * (b2 - u * ic) * d0 - 0.5 * (b1 * u - ic) * d1 - 0.5 * b1 * v * d2 -
+              0.5 * b1 * ww * d3 + 0.5 * b1 * d4;
+  const double lam0 = u - c, lam1 = u, lam4 = u + c;
+  if (!(hi ? lam0 > 0.0 : lam0 < 0.0)) a0 = 0.0;
+  if (!(hi ? lam1 > 0.0 : lam1 < 0.0)) { a1 = 0.0; a2 = 0.0; a3 = 0.0; }
+  if (!(hi ? lam4 > 0.0 : lam4 < 0.0)) a4 = 0.0;
+  double dr[5];
+  dr[0] = a0 + a1 + a4;
+  dr[PN] = (u - c) * a0 + u * a1 + (u + c) * a4;
+  dr[P1] = v * (a0 + a1 + a4) + a2;
+  dr[P2] = ww * (a0 + a1 + a4) + a3;
+  dr[4] = (H - u * c) * a0 + 0.5 * q2 * a1 + v * a2 + ww * a3 + (H + u * c) * a4;
+  for (int s = 0; s < kHalo; ++s)
+    for (int m = 0; m < 5; ++m) gq[s][m] = qb[m] + (double)(s + 1) * dr[m];
+}
+
 __device__ __forceinline__ void ghost_x_body(const Desc& D, const double* __restrict__ w, long long t) {
   // t over 2 * ny * nz (side, k, j)
   const long long per_side = (long long)D.ny * D.nz;
@@ -446,6 +486,7 @@ __device__ __forceinline__ void ghost_x_body(const Desc& D, const double* __rest
   const long long r = t - side * per_side;
   const int k = (int)(r / D.ny), j = (int)(r - (long long)k * D.ny);
   const int kind = D.bc[side];
+  if (kind == BC_DF_INFLOW) return;  // planes written by the inflow generator once per step
   double* g = D.gx[side];
   const size_t mst = (size_t)kHalo * D.nz * D.ny;
   double gq[kHalo][5];
@@ -464,36 +505,7 @@ __device__ __forceinline__ void ghost_x_body(const Desc& D, const double* __rest
       qb[m] = w[(size_t)m * D.N + nb];
       qi[m] = w[(size_t)m * D.N + ni];
     }
-    const double r = qb[0], ir = 1.0 / r;
-    const double u = qb[1] * ir, v = qb[2] * ir, ww = qb[3] * ir;
-    const double p = D.gm1 * (qb[4] - 0.5 * r * (u * u + v * v + ww * ww));
-    const double c = sqrt(D.gamma * p * ir);
-    const double H = (qb[4] + p) * ir;
-    const double q2 = u * u + v * v + ww * ww;
-    const double ic = 1.0 / c, b1 = D.gm1 * ic * ic, b2 = 0.5 * q2 * b1;
-    double dq[5];
-    for (int m = 0; m < 5; ++m) dq[m] = qb[m] - qi[m];
-    // characteristic amplitudes (x direction, natural component order)
-    double a0 = 0.5 * (b2 + u * ic) * dq[0] - 0.5 * (b1 * u + ic) * dq[1] - 0.5 * b1 * v * dq[2] -
-                0.5 * b1 * ww * dq[3] + 0.5 * b1 * dq[4];
-    double a1 = (1.0 - b2) * dq[0] + b1 * u * dq[1] + b1 * v * dq[2] + b1 * ww * dq[3] - b1 * dq[4];
-    double a2 = -v * dq[0] + dq[2];
-    double a3 = -ww * dq[0] + dq[3];
-    double a4 = 0.5 * (b2 - u * ic) * dq[0] - 0.5 * (b1 * u - ic) * dq[1] - 0.5 * b1 * v * dq[2] -
-                0.5 * b1 * ww * dq[3] + 0.5 * b1 * dq[4];
-    const double lam0 = u - c, lam1 = u, lam4 = u + c;
-    const bool hi = side == 1;
-    if (!(hi ? lam0 > 0.0 : lam0 < 0.0)) a0 = 0.0;
-    if (!(hi ? lam1 > 0.0 : lam1 < 0.0)) { a1 = 0.0; a2 = 0.0; a3 = 0.0; }
-    if (!(hi ? lam4 > 0.0 : lam4 < 0.0)) a4 = 0.0;
-    double dr[5];
-    dr[0] = a0 + a1 + a4;
-    dr[1] = (u - c) * a0 + u * a1 + (u + c) * a4;
-    dr[2] = v * (a0 + a1 + a4) + a2;
-    dr[3] = ww * (a0 + a1 + a4) + a3;
-    dr[4] = (H - u * c) * a0 + 0.5 * q2 * a1 + v * a2 + ww * a3 + (H + u * c) * a4;
-    for (int s = 0; s < kHalo; ++s)
-      for (int m = 0; m < 5; ++m) gq[s][m] = qb[m] + (double)(s + 1) * dr[m];
+    char_ghosts<0>(D, qb, qi, side == 1, gq);
   }
   for (int s = 0; s < kHalo; ++s)
     for (int m = 0; m < 5; ++m)
@@ -510,12 +522,21 @@ __device__ __forceinline__ void ghost_y_body(const Desc& D, const double* __rest
   const int kind = D.bc[2 + side];
   double* g = D.gy[side];
   const size_t mst = (size_t)kHalo * D.nz * D.nxg;
+  double gq[kHalo][5];
+  if (kind == BC_OUTFLOW) {
+    double qb[5], qi[5];
+    load_node(D, w, i, side == 0 ? 0 : D.ny - 1, k, qb);
+    load_node(D, w, i, side == 0 ? 1 : D.ny - 2, k, qi);
+    char_ghosts<1>(D, qb, qi, side == 1, gq);
+  }
   for (int s = 1; s <= kHalo; ++s) {
     double q[5];
     if (is_wall(kind)) {
       double qm[5];
       load_node(D, w, i, side == 0 ? s - 1 : D.ny - s, k, qm);
       wall_ghost(D, kind, side, qm, q);
+    } else if (kind == BC_OUTFLOW) {
+      for (int m = 0; m < 5; ++m) q[m] = gq[s - 1][m];
     } else {  // imposed shock state
       const double* pr = D.bcp[2 + side];
       const int ish = (int)pr[0];
@@ -525,6 +546,95 @@ __device__ __forceinline__ void ghost_y_body(const Desc& D, const double* __rest
     for (int m = 0; m < 5; ++m)
       g[m * mst + ((size_t)(s - 1) * D.nz + k) * D.nxg + (size_t)(i + kHalo)] = q[m];
   }
+}
+
+// ------------------------------------------------------------------ inflow turbulence
+// Synthetic inflow turbulence by digital filtering (Sec. 3.2), parameters
+// D.bcp[0] = {Ny, Nz, T, seed, b_y[2Ny+1], b_z[2Nz+1], mean (rho,u,v,w,p)
+// [5][ny], Cholesky (a11,a21,a22,a31,a32,a33)[6][ny]}.  Deviates are
+// uniform on [-sqrt 3, sqrt 3) from SplitMix64 (output n of the generator
+// seeded with `seed`), filtered along y and then z (periodic), correlated
+// in time, mapped by the Cholesky factor and completed by the strong
+// Reynolds analogy; one plane per RK step on the three x- ghost layers.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t n) {
+  uint64_t z = seed + n * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t df_key(const Desc& D, int initial) {
+  return initial ? 0ULL : (uint64_t)llround(D.scal[SC_STEP]);  // step s (0-based): s + 1
+}
+
+// fy[c][k][j] = sum_l b_y[l] r(c, k, j + l), the deviates made on the fly
+__global__ void k_df_filter_y(Desc D, int initial) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int ny = D.ny, nz = D.nz;
+  if (t >= 3LL * nz * ny) return;
+  const int c = (int)(t / ((long long)nz * ny));
+  const int rem = (int)(t - (long long)c * nz * ny);
+  const int k = rem / ny, j = rem - k * ny;
+  const double* pr = D.bcp[0];
+  const int Ny = (int)pr[0];
+  const uint64_t seed = (uint64_t)pr[3];
+  const double* by = pr + 4;
+  const uint64_t key = df_key(D, initial);
+  const uint64_t nyr = (uint64_t)(ny + 2 * Ny);
+  const uint64_t row = 1 + ((key * 3 + (uint64_t)c) * (uint64_t)nz + (uint64_t)k) * nyr;
+  double acc = 0.0;
+  for (int l = -Ny; l <= Ny; ++l) {
+    const uint64_t z = splitmix64_at(seed, row + (uint64_t)(j + l + Ny));
+    const double u = (double)(z >> 11) * 0x1.0p-53;
+    acc += by[l + Ny] * ((2.0 * u - 1.0) * 1.7320508075688772);
+  }
+  D.dffy[t] = acc;
+}
+
+// psi_hat = sum_m b_z[m] fy(k + m); psi update; fluctuations; ghost planes
+__global__ void k_df_plane(Desc D, int initial) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int ny = D.ny, nz = D.nz;
+  if (t >= (long long)nz * ny) return;
+  const int k = (int)(t / ny), j = (int)(t - (long long)k * ny);
+  const double* pr = D.bcp[0];
+  const int Ny = (int)pr[0], Nz = (int)pr[1];
+  const double TL = pr[2];
+  const double* bz = pr + 4 + 2 * Ny + 1;
+  const double* mean = bz + 2 * Nz + 1;
+  const double* chol = mean + 5 * ny;
+  const double dt = D.scal[SC_DT];
+  const double E = exp(-3.141592653589793 * dt / (2.0 * TL));
+  const double F = sqrt(1.0 - E * E);
+  const size_t plane = (size_t)nz * ny;
+  double ps[3];
+  for (int c = 0; c < 3; ++c) {
+    double acc = 0.0;
+    for (int m = -Nz; m <= Nz; ++m) {
+      int kk = (k + m) % nz;
+      kk = kk < 0 ? kk + nz : kk;
+      acc += bz[m + Nz] * D.dffy[(size_t)c * plane + (size_t)kk * ny + j];
+    }
+    const size_t q = (size_t)c * plane + (size_t)t;
+    const double v = initial ? acc : D.dfpsi[q] * E + acc * F;
+    D.dfpsi[q] = v;
+    ps[c] = v;
+  }
+  const double a11 = chol[j], a21 = chol[ny + j], a22 = chol[2 * ny + j];
+  const double a31 = chol[3 * ny + j], a32 = chol[4 * ny + j], a33 = chol[5 * ny + j];
+  const double du = a11 * ps[0];
+  const double dv = a21 * ps[0] + a22 * ps[1];
+  const double dw = a31 * ps[0] + a32 * ps[1] + a33 * ps[2];
+  const double rm = mean[j], um = mean[ny + j], vm = mean[2 * ny + j], wm = mean[3 * ny + j];
+  const double pm = mean[4 * ny + j];
+  const double Tm = pm / (rm * D.R);
+  const double T = Tm - um * du / D.cp;
+  double q[5];
+  from_prim(D, pm / (D.R * T), um + du, vm + dv, wm + dw, pm, q);
+  double* g = D.gx[0];
+  const size_t mst = (size_t)kHalo * nz * ny;
+  for (int s = 0; s < kHalo; ++s)
+    for (int m = 0; m < 5; ++m) g[m * mst + ((size_t)s * nz + k) * ny + j] = q[m];
 }
 
 __global__ void k_ghost_x(Desc D, int stage) {
@@ -1555,6 +1665,12 @@ hipError_t launch_stage_begin(const Desc& D, hipStream_t st) {
 }
 
 bool ghosts_needed(const Desc& D) { return !D.per_x || !D.per_y; }
+
+hipError_t launch_df(const Desc& D, bool initial, hipStream_t st) {
+  k_df_filter_y<<<nblk(3LL * D.nz * D.ny, 256), 256, 0, st>>>(D, initial ? 1 : 0);
+  k_df_plane<<<nblk((long long)D.nz * D.ny, 256), 256, 0, st>>>(D, initial ? 1 : 0);
+  return hipGetLastError();
+}
 
 hipError_t launch_ghosts(const Desc& D, int stage, hipStream_t st) {
   if (!D.per_x) k_ghost_x<<<nblk(2LL * D.ny * D.nz, 128), 128, 0, st>>>(D, stage);

@@ -37,6 +37,7 @@ BC_WALL_ADIABATIC = 2    # params: []
 BC_DIRICHLET = 3         # params: primitives (rho,u,v,w,p) per transverse j, shape (5, ny)
 BC_OUTFLOW_CHAR = 4      # params: []
 BC_SHOCK_TOP = 5         # params: [i_shock, rho1,u1,v1,w1,p1, rho2,u2,v2,w2,p2]
+BC_DF_INFLOW = 6         # params: see df_inflow_params (x- face only)
 
 FACE_XM, FACE_XP, FACE_YM, FACE_YP, FACE_ZM, FACE_ZP = range(6)
 
@@ -332,6 +333,134 @@ def sbli(nx: int = 1024, ny: int = 256, nz: int = 128, mach: float = 2.0,
                    theta_star=SBLI_THETA_STAR if theta_star is None else theta_star,
                    sensor_eps=(1.0 / delta) ** 2, forcing=False, bcs=bcs, w0=w0,
                    cfl=0.8, nsteps=nsteps)
+
+
+# ----------------------------------------------- spatially developing boundary layer
+def musker_uplus(yp):
+    """Musker's (1979) explicit inner profile u+(y+) (zero at the wall)."""
+    yp = np.asarray(yp, dtype=np.float64)
+    return (5.424 * np.arctan((2.0 * yp - 8.15) / 16.7)
+            + np.log10((yp + 10.6) ** 9.6 / (yp * yp - 8.15 * yp + 86.0) ** 2)
+            - 3.51132976630723)
+
+
+def bl_vd_uplus(yp, eta, pi_wake: float = 0.45, kappa: float = 0.41):
+    """Incompressible (van Driest) profile: Musker inner law plus Coles' wake
+    2 Pi/kappa sin^2(pi eta/2), eta = y/delta capped at 1."""
+    e = np.minimum(np.asarray(eta, dtype=np.float64), 1.0)
+    return musker_uplus(yp) + 2.0 * pi_wake / kappa * np.sin(0.5 * math.pi * e) ** 2
+
+
+def gaussian_filter_coeffs(n: float) -> np.ndarray:
+    """Digital-filter coefficients for a length of n grid spacings:
+    b_k proportional to exp(-pi k^2 / (2 n^2)), k = -2n..2n (at least one
+    neighbour), normalised to unit sum of squares."""
+    half = max(1, int(math.ceil(2.0 * n)))
+    k = np.arange(-half, half + 1, dtype=np.float64)
+    b = np.exp(-math.pi * k * k / (2.0 * max(n, 1e-12) ** 2))
+    return b / math.sqrt(float(np.sum(b * b)))
+
+
+def df_inflow_params(mean_prim: np.ndarray, rstress: np.ndarray, by: np.ndarray, bz: np.ndarray,
+                     t_lag: float, seed: int) -> np.ndarray:
+    """Parameter vector of the digital-filter inflow face: [Ny, Nz, T, seed,
+    b_y, b_z, mean (rho,u,v,w,p)[5][ny], lower Cholesky factor of the
+    Reynolds stresses (a11, a21, a22, a31, a32, a33)[6][ny]].  rstress is
+    (R11, R22, R33, R12, R13, R23)[6][ny]."""
+    R11, R22, R33, R12, R13, R23 = rstress
+    a11 = np.sqrt(np.maximum(R11, 0.0))
+    safe = np.where(a11 > 0.0, a11, 1.0)
+    a21 = np.where(a11 > 0.0, R12 / safe, 0.0)
+    a31 = np.where(a11 > 0.0, R13 / safe, 0.0)
+    a22 = np.sqrt(np.maximum(R22 - a21 * a21, 0.0))
+    safe22 = np.where(a22 > 0.0, a22, 1.0)
+    a32 = np.where(a22 > 0.0, (R23 - a21 * a31) / safe22, 0.0)
+    a33 = np.sqrt(np.maximum(R33 - a31 * a31 - a32 * a32, 0.0))
+    ny_half, nz_half = (len(by) - 1) // 2, (len(bz) - 1) // 2
+    head = np.array([float(ny_half), float(nz_half), float(t_lag), float(seed)])
+    return np.concatenate([head, by, bz, np.asarray(mean_prim, np.float64).ravel(),
+                           np.stack([a11, a21, a22, a31, a32, a33]).ravel()])
+
+
+def boundary_layer(nx: int = 1024, ny: int = 128, nz: int = 128, lx: float = 30.0,
+                   ly: float = 12.0, lz: float = 6.0, mach: float = 2.0, re_tau: float = 250.0,
+                   beta: float = 3.0, len_y: float = 0.25, len_z: float = 0.25,
+                   t_lag: float = 0.5, seed_index: int = 5, theta_star: float = 0.1,
+                   nsteps: int = 200) -> Problem:
+    """Spatially developing supersonic turbulent boundary layer over an
+    isothermal wall at the recovery temperature, lengths in units of the
+    inflow thickness delta_in = 1 (free stream: rho = u = T = 1).
+
+    Mean field (Sec. 3.2 recipe): Musker's inner profile with Coles' wake
+    as the van Driest velocity, transformed to the compressible profile with
+    the Crocco-Busemann temperature for a recovery-temperature wall,
+    T(u) = T_r (1 - a^2 u^2), a^2 = (T_r - 1)/T_r, for which the van
+    Driest integral inverts in closed form: u = sin(a u_vd)/a.  The friction
+    velocity makes u(delta_in) = 0.99; the wall viscosity follows from
+    Re_tau.  Inflow: digital filtering with synthetic Reynolds-stress
+    profiles (the paper interpolates a DNS database that is not available):
+    (R11, R22, R33, R12) = (2.2^2, 1.0^2, 1.4^2, -0.9) u_tau^2 (1 - eta^2)
+    (1 - exp(-y+/8))^2 inside the layer, zero outside; filter lengths len_y,
+    len_z (in delta_in) and Lagrangian time t_lag.  Outflow and top faces:
+    characteristic non-reflecting; spanwise periodic.  The interior starts
+    from the mean profile (uniform in x)."""
+    g, Pr = 1.4, 0.72
+    R = 1.0 / (g * mach * mach)
+    Tr = 1.0 + 0.5 * (g - 1.0) * Pr ** (1.0 / 3.0) * mach * mach
+    a = math.sqrt((Tr - 1.0) / Tr)
+    y, ye, yee = sinh_wall_y(ny, ly, beta)
+    eta = y  # delta_in = 1
+    uvd_edge = math.asin(0.99 * a) / a
+    u_tau = uvd_edge / float(bl_vd_uplus(re_tau, 1.0))
+    rho_w = 1.0 / Tr
+    mu_w = rho_w * u_tau * 1.0 / re_tau
+    yp = y * re_tau
+    uvd = u_tau * bl_vd_uplus(yp, eta)
+    u = np.where(eta < 1.0, np.sin(np.minimum(a * uvd, 0.5 * math.pi)) / a, 1.0)
+    u = np.minimum(u, 1.0)
+    T = Tr * (1.0 - a * a * u * u)
+    pinf = R  # rho = T = 1 in the free stream
+    rho = pinf / (R * T)
+    S = sutherland_S(220.0)
+    mu_ref = mu_w / (Tr ** 1.5 * (1.0 + S) / (Tr + S))
+    # synthetic Reynolds stresses
+    damp = (1.0 - np.exp(-yp / 8.0)) ** 2
+    h = np.clip(1.0 - eta * eta, 0.0, None) * damp * u_tau * u_tau
+    rs = np.stack([2.2 ** 2 * h, 1.0 ** 2 * h, 1.4 ** 2 * h, -0.9 * h, 0.0 * h, 0.0 * h])
+    # filter widths in grid spacings (mean spacing inside the layer for y)
+    dz = lz / nz
+    inside = eta < 1.0
+    dy_bl = float(np.mean(np.diff(y[inside]))) if inside.sum() > 1 else float(y[1] - y[0])
+    by = gaussian_filter_coeffs(len_y / dy_bl)
+    bz = gaussian_filter_coeffs(len_z / dz)
+    mean = np.stack([rho, u, np.zeros(ny), np.zeros(ny), np.full(ny, pinf)])
+    seed = BASE_SEED + seed_index
+    params = df_inflow_params(mean, rs, by, bz, t_lag, seed)
+    shape = (nz, ny, nx)
+    U = np.broadcast_to(u[None, :, None], shape)
+    Rh = np.broadcast_to(rho[None, :, None], shape)
+    zeros = np.zeros(shape)
+    w0 = conserved_from_primitive(Rh, U, zeros, zeros, np.full(shape, pinf), g)
+    bcs = _periodic_bcs()
+    bcs[FACE_XM] = (BC_DF_INFLOW, params)
+    bcs[FACE_XP] = (BC_OUTFLOW_CHAR, np.zeros(0))
+    bcs[FACE_YM] = (BC_WALL_ISOTHERMAL, np.array([Tr]))
+    bcs[FACE_YP] = (BC_OUTFLOW_CHAR, np.zeros(0))
+    return Problem(name=f"bl{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, lx=lx, lz=lz,
+                   y=y, y_eta=ye, y_etaeta=yee, gamma=g, Pr=Pr, R_gas=R, mu_ref=mu_ref,
+                   T_ref=1.0, S_suth=S, viscous=True, sensor_mode=SENSOR_HYBRID,
+                   theta_star=theta_star, sensor_eps=1.0, forcing=False, bcs=bcs, w0=w0,
+                   cfl=0.8, nsteps=nsteps)
+
+
+def small_boundary_layer(nx: int = 48, ny: int = 32, nz: int = 16, **kw) -> Problem:
+    """Parity-sized boundary layer (same recipe, shorter box)."""
+    kw.setdefault("lx", 4.0)
+    kw.setdefault("ly", 3.0)
+    kw.setdefault("lz", 1.5)
+    kw.setdefault("beta", 2.0)
+    kw.setdefault("re_tau", 120.0)
+    return boundary_layer(nx, ny, nz, **kw)
 
 
 # ----------------------------------------------- decaying isotropic turbulence

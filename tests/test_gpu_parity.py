@@ -75,6 +75,8 @@ RHS_CASES = {
     # inviscid instance of the fused kernel (viscous terms compiled out)
     "dit24_inviscid_hybrid": lambda: dataclasses.replace(
         P.decaying_turbulence(24, mach=1.5, re=800.0, seed=13), viscous=False),
+    # boundary layer: digital-filter inflow (initial plane), top outflow
+    "bl_48x32x16": lambda: P.small_boundary_layer(),
 }
 
 
@@ -157,6 +159,8 @@ STEP_CASES = {
                              False),
     "dit24_inviscid_30steps": (lambda: dataclasses.replace(
         P.decaying_turbulence(24, mach=0.5, re=800.0, seed=14), viscous=False), 30, False),
+    # inflow generator advanced once per step on both sides (keys 1..n)
+    "bl_48x32x16_40steps": (lambda: P.small_boundary_layer(), 40, False),
 }
 
 
@@ -297,3 +301,17 @@ def test_full_size_channel_steps_conserve(torch_cuda):
     assert abs(d1["mass"] - d0["mass"]) <= 1e-12 * abs(d0["mass"])
     assert abs(d1["mom"][0] - d0["mom"][0]) <= 1e-11 * abs(d0["mom"][0])
     assert d1["rho_min"] > 0 and d1["p_min"] > 0 and d1["step"] == 20
+
+
+def test_batch_rejects_digital_filter_inflow(torch_cuda):
+    from paper_2004_02276_amd import Solver
+    from paper_2004_02276_amd.serve import Batch
+    say("[batch] inflow generator rejected")
+    s = Solver(P.small_boundary_layer(32, 16, 8))
+    from paper_2004_02276_amd import _binding as B
+    b = Batch(4)
+    with pytest.raises(B.CdnsError) as err:
+        b.attach(s)
+    assert err.value.status == B.CDNS_EUNSUP
+    b.close()
+    s.close()
