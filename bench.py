@@ -6,8 +6,9 @@ Workload (default): the compressible channel 256x128x128 (4.19 M points,
 FP64 state, isothermal staggered walls on a tanh-stretched grid, bulk Mach
 1.5, Re_b = 3000, hybrid central/WENO with the Ducros sensor, bulk
 forcing), synthetic seeded initial field.  --workload sbli (shock on a
-boundary layer, 1024x256x128) and --workload tgv (32^3) give reference
-figures on the other two configurations.  A step is one full RK3 step (three
+boundary layer, 1024x256x128), tgv (32^3) and bl (spatially developing
+boundary layer with digital-filter inflow, 1024x128x128) give reference
+figures on the other configurations.  A step is one full RK3 step (three
 stages of ghost planes, sensor, flag compaction, WENO on lists, fused
 right-hand side, forcing reduction and update), replayed from a HIP graph.
 
@@ -53,6 +54,10 @@ WORKLOADS = {
                      "central/WENO, Dirichlet inflow, characteristic outflow, adiabatic wall, "
                      "imposed shock, CFL 0.8"),
     "tgv": ("taylor_green", "Taylor-Green vortex 32^3, FP64 state, central only, CFL 0.8"),
+    "bl": ("boundary_layer", "spatially developing Mach 2 boundary layer 1024x128x128 "
+                             "(30 x 12 x 6 inflow thicknesses), FP64 state, hybrid central/WENO, "
+                             "digital-filter inflow turbulence, recovery-temperature wall, "
+                             "characteristic outflow and top, CFL 0.8"),
 }
 
 
@@ -106,7 +111,7 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32flux"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=list(WORKLOADS), default="channel",
-                    help="channel (the headline workload), sbli or tgv (reference figures)")
+                    help="channel (the headline workload); sbli, tgv, bl (reference figures)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path (one simulation "
