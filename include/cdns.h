@@ -32,8 +32,9 @@
  *    the nodes sit at eta_j = (j+1/2)/ny so the walls fall half-way
  *    between the last node and the first ghost (staggered wall, Sec. 3.1).
  *  - All work is enqueued on the hip stream given at creation and is
- *    asynchronous, except cdns_diagnostics() and cdns_get_theta(), which
- *    synchronise that stream.
+ *    asynchronous, except cdns_diagnostics(), the export hooks,
+ *    cdns_time_phases() and cdns_stats_export(), which synchronise that
+ *    stream.
  */
 #ifndef CDNS_H
 #define CDNS_H
@@ -195,6 +196,23 @@ cdns_status cdns_advance_n(cdns_ctx* ctx, int32_t n, double cfl, double dt_fixed
 /* Volume integrals, extrema and status of the current state; synchronises
  * the stream.  Returns CDNS_ESTATE if the device flagged a bad state. */
 cdns_status cdns_diagnostics(cdns_ctx* ctx, cdns_diag* out);
+
+/* Running statistics for mean profiles and turbulent stresses (the
+ * quantities of Sec. 4's validation figures; the paper does not describe
+ * how they are gathered).  cdns_stats_accumulate adds, for every (i, j)
+ * column, the spanwise sums (k ascending) over the current state of
+ * CDNS_NSTAT products to a per-context accumulator [CDNS_NSTAT][ny][nx]
+ * and counts one sample (asynchronous, no host synchronisation);
+ * cdns_stats_export copies the accumulator to host memory (caller-owned,
+ * CDNS_NSTAT*ny*nx doubles) and the sample count to *samples
+ * (synchronises); cdns_stats_reset zeroes both.  Quantities, with
+ * u = (rho u)/rho, T = (E/rho - |u|^2/2)/c_v, p = rho R T: */
+enum { CDNS_ST_RHO = 0, CDNS_ST_RHOU, CDNS_ST_RHOV, CDNS_ST_RHOW, CDNS_ST_RHOUU,
+       CDNS_ST_RHOVV, CDNS_ST_RHOWW, CDNS_ST_RHOUV, CDNS_ST_U, CDNS_ST_UU, CDNS_ST_T,
+       CDNS_ST_RHOT, CDNS_ST_TT, CDNS_ST_P, CDNS_ST_PP, CDNS_ST_RHORHO, CDNS_NSTAT };
+cdns_status cdns_stats_accumulate(cdns_ctx* ctx);
+cdns_status cdns_stats_export(cdns_ctx* ctx, double* host_out, int64_t* samples);
+cdns_status cdns_stats_reset(cdns_ctx* ctx);
 
 /* Test hooks: node sensor value theta, node flags and interface flags
  * (bit d: interface i+1/2 in direction d is shock-capturing) of the last

@@ -97,6 +97,8 @@ def _load():
         lib.ora_iface_flux.restype = ctypes.c_int
         lib.ora_num_threads.argtypes = []
         lib.ora_num_threads.restype = ctypes.c_int
+        lib.ora_stats.argtypes = [pp, dp, dp]
+        lib.ora_stats.restype = ctypes.c_int
         lib.ora_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         lib.ora_splitmix64.restype = ctypes.c_uint64
         lib.ora_df_update.argtypes = [pp, ctypes.c_uint64, ctypes.c_double, ctypes.c_int, dp, dp,
@@ -263,3 +265,18 @@ def df_update(pr, key: int, dt: float, first: bool, psi: Optional[np.ndarray] = 
     _check(lib.ora_df_update(ctypes.byref(m.s), ctypes.c_uint64(key), float(dt), int(bool(first)),
                              _dptr(psi), _dptr(plane), _dptr(fl)), "ora_df_update")
     return psi, plane, fl
+
+
+STAT_NAMES = ["rho", "rho_u", "rho_v", "rho_w", "rho_uu", "rho_vv", "rho_ww", "rho_uv", "u", "uu",
+              "T", "rho_T", "TT", "p", "pp", "rho_rho"]
+
+
+def stats(pr, w: np.ndarray, acc: Optional[np.ndarray] = None) -> np.ndarray:
+    """Spanwise sums of the statistics products of state w added to acc
+    (shape (16, ny, nx)); returns acc."""
+    lib = _load()
+    acc = np.zeros((16, pr.ny, pr.nx)) if acc is None else acc
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    m = _Marshalled(pr)
+    _check(lib.ora_stats(ctypes.byref(m.s), _dptr(w), _dptr(acc)), "ora_stats")
+    return acc

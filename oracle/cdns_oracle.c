@@ -1066,6 +1066,34 @@ int ora_totals(const ora_problem* P, const double* w, double* out6) {
   return ORA_OK;
 }
 
+/* Running statistics (the quantities behind the mean profiles and stresses
+ * of Sec. 4): for every (i, j) column, the spanwise sums (k ascending) of
+ * rho, rho u, rho v, rho w, rho u u, rho v v, rho w w, rho u v, u, u u, T,
+ * rho T, T T, p, p p, rho rho are added to acc[16][ny][nx], with
+ * u = (rho u)/rho, T = (E/rho - |u|^2/2)/c_v, p = rho R T. */
+int ora_stats(const ora_problem* P, const double* w, double* acc) {
+  const int nx = P->nx, ny = P->ny, nz = P->nz;
+  const size_t N = (size_t)nx * ny * nz, plane = (size_t)nx * ny;
+  const double icv = (P->gamma - 1.0) / P->R_gas;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      double a[16] = {0};
+      for (int k = 0; k < nz; ++k) {
+        size_t n = (size_t)k * plane + (size_t)j * nx + i;
+        double r = w[n], ir = 1.0 / r;
+        double u = w[N + n] * ir, v = w[2 * N + n] * ir, ww = w[3 * N + n] * ir;
+        double T = (w[4 * N + n] * ir - 0.5 * (u * u + v * v + ww * ww)) * icv;
+        double p = r * P->R_gas * T;
+        double ru = w[N + n], rv = w[2 * N + n], rw = w[3 * N + n];
+        double q[16] = {r, ru, rv, rw, ru * u, rv * v, rw * ww, ru * v, u, u * u, T, r * T,
+                        T * T, p, p * p, r * r};
+        for (int m = 0; m < 16; ++m) a[m] += q[m];
+      }
+      for (int m = 0; m < 16; ++m) acc[(size_t)m * plane + (size_t)j * nx + i] += a[m];
+    }
+  return ORA_OK;
+}
+
 int ora_num_threads(void) {
   int n = 1;
 #ifdef _OPENMP

@@ -18,11 +18,13 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -
                 -6: "EBUSY"}
 CDNS_FP64, CDNS_FP32_FLUX = 0, 1
 PHASES = ["dt", "ghosts", "sensor", "iflags", "weno", "rhs", "force", "rk"]
+NSTAT = 16  # running-statistics products (CDNS_NSTAT)
 
 EXPORTED = [
     "cdns_version", "cdns_workspace_bytes", "cdns_create", "cdns_set_bc", "cdns_set_tiling",
     "cdns_rhs", "cdns_rk_step", "cdns_advance_n", "cdns_diagnostics", "cdns_export_sensor",
-    "cdns_export_iface_flux", "cdns_time_phases",
+    "cdns_export_iface_flux", "cdns_time_phases", "cdns_stats_accumulate", "cdns_stats_export",
+    "cdns_stats_reset",
     "cdns_last_error", "cdns_destroy", "cdns_batch_create", "cdns_batch_workspace_bytes",
     "cdns_batch_attach", "cdns_batch_detach", "cdns_batch_set_step", "cdns_batch_step",
     "cdns_batch_destroy",
@@ -100,6 +102,12 @@ def load() -> ctypes.CDLL:
     lib.cdns_time_phases.argtypes = [vp, i32, f64, f64, ctypes.POINTER(f64), ctypes.POINTER(i32),
                                      ctypes.POINTER(ctypes.c_int64)]
     lib.cdns_time_phases.restype = i32
+    lib.cdns_stats_accumulate.argtypes = [vp]
+    lib.cdns_stats_accumulate.restype = i32
+    lib.cdns_stats_export.argtypes = [vp, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)]
+    lib.cdns_stats_export.restype = i32
+    lib.cdns_stats_reset.argtypes = [vp]
+    lib.cdns_stats_reset.restype = i32
     lib.cdns_last_error.argtypes = [vp]
     lib.cdns_last_error.restype = ctypes.c_char_p
     lib.cdns_destroy.argtypes = [vp]

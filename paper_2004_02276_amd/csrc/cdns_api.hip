@@ -31,6 +31,7 @@ struct cdns_ctx {
   double g_cfl = -1.0, g_dt = -1.0;
   bool last_rhs_valid = false;
   int batch_refs = 0;
+  int64_t stat_samples = 0;           // samples in the statistics accumulator
 };
 
 namespace {
@@ -40,7 +41,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t metric, bcp, w1, w2, ra, rb, nflag, slot, theta, fw, list, count, gx, gy, df, part, red,
+  size_t metric, bcp, w1, w2, ra, rb, nflag, slot, theta, fw, list, count, gx, gy, df, stats, part, red,
       redd, scal, status, diag, total;
   size_t bcp_cap, part_cap;
 };
@@ -82,6 +83,7 @@ Layout layout_of(const cdns_grid* g) {
   L.gx = take(2 * 5 * cdns::kHalo * nz * ny * sizeof(double));
   L.gy = take(2 * 5 * cdns::kHalo * nz * nxg * sizeof(double));
   L.df = take(2 * 3 * nz * ny * sizeof(double));
+  L.stats = take((size_t)cdns::kNStat * ny * nx * sizeof(double));
   L.part = take(L.part_cap * sizeof(double));
   L.red = take(2 * cdns::kRedBlocks * sizeof(double));
   L.redd = take((size_t)cdns::DG_COUNT * cdns::kRedBlocks * sizeof(double));
@@ -272,6 +274,7 @@ cdns_status cdns_create(const cdns_grid* grid, const cdns_phys* phys, int32_t pr
   const size_t gys = (size_t)5 * cdns::kHalo * nz * D.nxg;
   D.gx[0] = (double*)(ws + L.gx);
   D.gx[1] = D.gx[0] + gxs;
+  D.stats = (double*)(ws + L.stats);
   D.dfpsi = (double*)(ws + L.df);
   D.dffy = D.dfpsi + (size_t)3 * nz * ny;
   D.gy[0] = (double*)(ws + L.gy);
@@ -300,6 +303,8 @@ cdns_status cdns_create(const cdns_grid* grid, const cdns_phys* phys, int32_t pr
       (e = hipMemsetAsync(ws + L.status, 0, 4 * sizeof(unsigned), c->stream)) != hipSuccess ||
       (e = hipMemsetAsync(ws + L.slot, 0xFF, 3 * D.N * sizeof(int), c->stream)) != hipSuccess ||
       (e = hipMemsetAsync(ws + L.nflag, 0, D.N, c->stream)) != hipSuccess ||
+      (e = hipMemsetAsync(ws + L.stats, 0, (size_t)cdns::kNStat * ny * nx * sizeof(double),
+                          c->stream)) != hipSuccess ||
       (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
     delete c;
     return CDNS_EHIP;
@@ -603,6 +608,35 @@ cdns_status cdns_time_phases(cdns_ctx* c, int32_t nsteps, double cfl, double dt_
       return hip_fail(c, e, "interface count");
     *weno_ifaces_out = (int64_t)acc;
   }
+  return CDNS_OK;
+}
+
+cdns_status cdns_stats_accumulate(cdns_ctx* c) {
+  if (!c) return CDNS_EINVAL;
+  hipError_t e = cdns::launch_stats(c->D, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "statistics launch");
+  c->stat_samples += 1;
+  return CDNS_OK;
+}
+
+cdns_status cdns_stats_export(cdns_ctx* c, double* host_out, int64_t* samples) {
+  if (!c || !host_out || !samples) return c ? fail(c, CDNS_EINVAL, "null output") : CDNS_EINVAL;
+  const Desc& D = c->D;
+  const size_t bytes = (size_t)cdns::kNStat * D.ny * D.nx * sizeof(double);
+  hipError_t e = hipMemcpyAsync(host_out, D.stats, bytes, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "statistics export");
+  *samples = c->stat_samples;
+  return CDNS_OK;
+}
+
+cdns_status cdns_stats_reset(cdns_ctx* c) {
+  if (!c) return CDNS_EINVAL;
+  const Desc& D = c->D;
+  hipError_t e = hipMemsetAsync(D.stats, 0, (size_t)cdns::kNStat * D.ny * D.nx * sizeof(double),
+                                c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "statistics reset");
+  c->stat_samples = 0;
   return CDNS_OK;
 }
 

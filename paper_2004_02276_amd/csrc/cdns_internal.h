@@ -61,6 +61,7 @@ struct Desc {
   int* list[3];                   // [N] compacted interface lists per direction
   unsigned* count;                // [4] list lengths
   double* gx[2];                  // [5][3][nz][ny] x-face ghost planes
+  double* stats;                  // [NSTAT][ny][nx] spanwise sums of the running statistics
   double* dfpsi;                  // [3][nz][ny] filtered inflow field (digital filter)
   double* dffy;                   // [3][nz][ny] inflow deviates filtered along y
   double* gy[2];                  // [5][3][nz][nxg] y-face ghost planes
@@ -95,6 +96,8 @@ hipError_t launch_count_iface(const Desc& D, bool reset, hipStream_t st);  // sc
 // digital-filter inflow: the initial plane (key 0), or the update at the
 // start of the current step (key = scal[SC_STEP], dt = scal[SC_DT])
 hipError_t launch_df(const Desc& D, bool initial, hipStream_t st);
+constexpr int kNStat = 16;  // running-statistics products (CDNS_NSTAT)
+hipError_t launch_stats(const Desc& D, hipStream_t st);
 hipError_t launch_export_iface(const Desc& D, int dir, double* out, hipStream_t st);
 bool rhs_tile_supported(int tx, int ty);
 int rhs_blocks(const Desc& D);

@@ -1666,6 +1666,51 @@ hipError_t launch_stage_begin(const Desc& D, hipStream_t st) {
 
 bool ghosts_needed(const Desc& D) { return !D.per_x || !D.per_y; }
 
+// ------------------------------------------------------------------ running statistics
+// One thread per (i, j) column: spanwise sums (k ascending) of the
+// statistics products of the current state, added to the accumulator.
+__global__ void k_stats(Desc D) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)D.nx * D.ny) return;
+  const double* w = D.win[0];
+  const size_t N = (size_t)D.N, plane = (size_t)D.nx * D.ny;
+  double acc[kNStat];
+#pragma unroll
+  for (int q = 0; q < kNStat; ++q) acc[q] = 0.0;
+  for (int k = 0; k < D.nz; ++k) {
+#pragma clang fp contract(off)
+    const size_t n = (size_t)k * plane + (size_t)t;
+    const double r = w[n], ir = 1.0 / r;
+    const double u = w[N + n] * ir, v = w[2 * N + n] * ir, ww = w[3 * N + n] * ir;
+    const double T = (w[4 * N + n] * ir - 0.5 * (u * u + v * v + ww * ww)) * D.icv;
+    const double p = r * D.R * T;
+    const double ru = w[N + n], rv = w[2 * N + n], rw = w[3 * N + n];
+    acc[0] += r;
+    acc[1] += ru;
+    acc[2] += rv;
+    acc[3] += rw;
+    acc[4] += ru * u;
+    acc[5] += rv * v;
+    acc[6] += rw * ww;
+    acc[7] += ru * v;
+    acc[8] += u;
+    acc[9] += u * u;
+    acc[10] += T;
+    acc[11] += r * T;
+    acc[12] += T * T;
+    acc[13] += p;
+    acc[14] += p * p;
+    acc[15] += r * r;
+  }
+#pragma unroll
+  for (int q = 0; q < kNStat; ++q) D.stats[(size_t)q * plane + (size_t)t] += acc[q];
+}
+
+hipError_t launch_stats(const Desc& D, hipStream_t st) {
+  k_stats<<<nblk((long long)D.nx * D.ny, 256), 256, 0, st>>>(D);
+  return hipGetLastError();
+}
+
 hipError_t launch_df(const Desc& D, bool initial, hipStream_t st) {
   k_df_filter_y<<<nblk(3LL * D.nz * D.ny, 256), 256, 0, st>>>(D, initial ? 1 : 0);
   k_df_plane<<<nblk((long long)D.nz * D.ny, 256), 256, 0, st>>>(D, initial ? 1 : 0);

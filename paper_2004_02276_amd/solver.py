@@ -126,6 +126,48 @@ class Solver:
                                             ifl.data_ptr()), "cdns_export_sensor")
         return theta, nfl, ifl
 
+    # ------------------------------------------------------------ statistics
+    def stats_accumulate(self) -> None:
+        """Add the spanwise sums of the current state's statistics products
+        to the running accumulator (asynchronous)."""
+        B.check(self.lib, self.ctx, self.lib.cdns_stats_accumulate(self.ctx),
+                "cdns_stats_accumulate")
+
+    def stats_reset(self) -> None:
+        B.check(self.lib, self.ctx, self.lib.cdns_stats_reset(self.ctx), "cdns_stats_reset")
+
+    def stats_raw(self):
+        """(sums [16][ny][nx] over z and samples, number of samples)."""
+        out = np.zeros((B.NSTAT, self.pr.ny, self.pr.nx))
+        n = ctypes.c_int64(0)
+        B.check(self.lib, self.ctx,
+                self.lib.cdns_stats_export(self.ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           ctypes.byref(n)), "cdns_stats_export")
+        return out, int(n.value)
+
+    def stats(self, average_x: bool = False) -> Dict:
+        """Mean fields from the running statistics: spanwise (and, with
+        average_x, streamwise) Reynolds means, Favre means rho u_i/rho,
+        Favre stresses R_ij = rho u_i u_j/rho - u~_i u~_j (ij = 11, 22, 33,
+        12), rms of u, T, p and rho; arrays over (y, x) or over y."""
+        S, n = self.stats_raw()
+        if n == 0:
+            raise ValueError("no statistics accumulated")
+        cnt = n * self.pr.nz
+        if average_x:
+            S = S.sum(axis=2)
+            cnt *= self.pr.nx
+        m = S / cnt
+        rho = m[0]
+        uf, vf, wf = m[1] / rho, m[2] / rho, m[3] / rho
+        var = lambda sq, mean: np.maximum(sq - mean * mean, 0.0)
+        return {"samples": n, "rho": rho, "u_favre": uf, "v_favre": vf, "w_favre": wf,
+                "R11": m[4] / rho - uf * uf, "R22": m[5] / rho - vf * vf,
+                "R33": m[6] / rho - wf * wf, "R12": m[7] / rho - uf * vf,
+                "u": m[8], "u_rms": np.sqrt(var(m[9], m[8])), "T": m[10], "T_favre": m[11] / rho,
+                "T_rms": np.sqrt(var(m[12], m[10])), "p": m[13], "p_rms": np.sqrt(var(m[14], m[13])),
+                "rho_rms": np.sqrt(var(m[15], rho))}
+
     def export_iface_flux(self, d: int):
         t = self.torch
         out = t.empty((5, self.pr.nz, self.pr.ny, self.pr.nx), dtype=t.float64, device=self.device)
