@@ -13,7 +13,12 @@ characteristic outflow boundary is pinned only by a behaviour check
 the digital-filter inflow generator is pinned by the published SplitMix64
 reference outputs and by its statistics (unit variance of the filtered
 field, prescribed Reynolds stresses, filter and time correlations), its
-constants are readings (the paper gives the method only).
+constants are readings (the paper gives the method only).  The scheme-order
+variants (central order 2L for L = 1, 2, 3; WENO order 2r - 1 for r = 2, 3,
+4) are pinned in tests/test_oracle_orders.py by Taylor-derived weights,
+polynomial definitions of the WENO candidates and indicators, design-order
+convergence, conservation and kinetic-energy identities and the exact Sod
+solution.
 """
 from __future__ import annotations
 
@@ -63,6 +68,7 @@ class _Problem(ctypes.Structure):
         ("bc_params", ctypes.POINTER(ctypes.c_double) * 6),
         ("bc_nparams", ctypes.c_int32 * 6),
         ("df_plane", ctypes.POINTER(ctypes.c_double)),
+        ("central_L", ctypes.c_int32), ("weno_r", ctypes.c_int32),
     ]
 
 
@@ -88,6 +94,10 @@ def _load():
         lib.ora_rk_stage.restype = None
         lib.ora_weno5.argtypes = [dp]
         lib.ora_weno5.restype = ctypes.c_double
+        lib.ora_weno.argtypes = [ctypes.c_int, dp]
+        lib.ora_weno.restype = ctypes.c_double
+        lib.ora_weno_parts.argtypes = [ctypes.c_int, dp, dp, dp]
+        lib.ora_weno_parts.restype = None
         lib.ora_eigenvectors.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp]
         lib.ora_eigenvectors.restype = None
@@ -131,6 +141,7 @@ class _Marshalled:
         s.theta_star, s.sensor_eps = pr.theta_star, pr.sensor_eps
         s.forcing = int(bool(pr.forcing))
         s.terms = int(terms)
+        s.central_L, s.weno_r = scheme_params(pr)
         for f, (kind, params) in enumerate(pr.bcs):
             arr = np.ascontiguousarray(np.asarray(params, dtype=np.float64).ravel())
             if arr.size == 0:
@@ -143,6 +154,16 @@ class _Marshalled:
             s.bc_params[f] = _dptr(arr)
             s.bc_nparams[f] = n
         self.s = s
+
+
+def scheme_params(pr):
+    """(L, r) of a problem: central order 2L, WENO order 2r - 1 (defaults
+    4 and 5 when the problem does not name them)."""
+    co = int(getattr(pr, "central_order", 4))
+    wo = int(getattr(pr, "weno_order", 5))
+    if co not in (2, 4, 6) or wo not in (3, 5, 7):
+        raise ValueError(f"unsupported scheme orders central {co}, WENO {wo}")
+    return co // 2, (wo + 1) // 2
 
 
 def _check(st: int, what: str):
@@ -212,6 +233,27 @@ def weno5(v) -> float:
     a = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
     assert a.size == 5
     return lib.ora_weno5(_dptr(a))
+
+
+def weno(r: int, v) -> float:
+    """WENO-JS reconstruction of order 2r-1 at the right face of the middle
+    cell of the 2r-1 values v."""
+    lib = _load()
+    a = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
+    assert a.size == 2 * r - 1
+    return lib.ora_weno(int(r), _dptr(a))
+
+
+def weno_parts(r: int, v):
+    """(candidate face values q_k, smoothness indicators beta_k) of the
+    reconstruction of order 2r-1."""
+    lib = _load()
+    a = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
+    assert a.size == 2 * r - 1
+    q = np.zeros(4)
+    b = np.zeros(4)
+    lib.ora_weno_parts(int(r), _dptr(a), _dptr(q), _dptr(b))
+    return q[:r], b[:r]
 
 
 def eigenvectors(gamma: float, d: int, u: float, v: float, w: float, Ht: float):

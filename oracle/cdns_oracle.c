@@ -12,16 +12,19 @@
  * (no contraction to fused multiply-add, t^{3/2} as t*sqrt(t)).
  *
  * Data layout of the caller's arrays: w[5][nz][ny][nx], x fastest.
- * Internally every field lives on a padded grid with a halo of H = 3 nodes
- * on each side; ghost nodes are filled explicitly (x faces, then y faces over
- * the x-extended range, then z faces over the x,y-extended range) and every
- * operator then reads plain neighbours.  This is deliberately the most
- * direct form of the discretisation, not a fast one.
+ * Internally every field lives on a padded grid with a halo of H = 4 nodes
+ * on each side; the hw = max(2, L, r) ghost layers that the schemes reach
+ * (L: half-width of the central stencils, r: WENO stencil size) are filled
+ * explicitly (x faces, then y faces over the x-extended range, then z faces
+ * over the x,y-extended range) and every operator then reads plain
+ * neighbours.  This is deliberately the most direct form of the
+ * discretisation, not a fast one.
  *
  * Parity status of each function is stated beside it; all are pinned by
  * the CPU tests (closed forms, invariants, exact solutions, convergence).
  */
 #include <math.h>
+#include <stddef.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -29,7 +32,7 @@
 #include <omp.h>
 #endif
 
-#define H 3
+#define H 4
 
 enum { BC_PERIODIC = 0, BC_WALL_ISO = 1, BC_WALL_ADIA = 2, BC_DIRICHLET = 3,
        BC_OUTFLOW = 4, BC_SHOCK_TOP = 5, BC_DF_INFLOW = 6 };
@@ -52,13 +55,27 @@ typedef struct {
   /* digital-filter inflow plane to use (conserved [5][nz][ny]); NULL: the
    * initial plane of the generator (see df_plane) */
   const double* df_plane;
+  /* scheme orders (Sec. 2.1): central flux and viscous derivatives of order
+   * 2L (L = 1, 2, 3; 0 selects L = 2), WENO reconstruction of order 2r - 1
+   * from r candidate stencils (r = 2, 3, 4; 0 selects r = 3) */
+  int32_t central_L, weno_r;
 } ora_problem;
 
-/* Standard 4th-order central coefficients (Sec. 2.1): first derivative
- * a_1 = 2/3, a_2 = -1/12; second derivative b_0 = -5/2, b_1 = 4/3,
- * b_2 = -1/12. */
-static const double A1 = 2.0 / 3.0, A2 = -1.0 / 12.0;
-static const double B0 = -5.0 / 2.0, B1 = 4.0 / 3.0, B2 = -1.0 / 12.0;
+/* Standard central finite-difference coefficients of order 2L (Sec. 2.1),
+ * rows L = 1, 2, 3: first derivative f'_i ~ (1/h) sum_{l=1}^{L} a_l
+ * (f_{i+l} - f_{i-l}); second derivative f''_i ~ (1/h^2) (b_0 f_i +
+ * sum_{l=1}^{L} b_l (f_{i+l} + f_{i-l})). */
+static const double ACOEF[4][3] = {{0.0, 0.0, 0.0},
+                                   {1.0 / 2.0, 0.0, 0.0},
+                                   {2.0 / 3.0, -1.0 / 12.0, 0.0},
+                                   {3.0 / 4.0, -3.0 / 20.0, 1.0 / 60.0}};
+static const double BCOEF[4][4] = {{0.0, 0.0, 0.0, 0.0},
+                                   {-2.0, 1.0, 0.0, 0.0},
+                                   {-5.0 / 2.0, 4.0 / 3.0, -1.0 / 12.0, 0.0},
+                                   {-49.0 / 18.0, 3.0 / 2.0, -3.0 / 20.0, 1.0 / 90.0}};
+/* largest magnitude of the symbol of the order-2L second derivative
+ * (reached at the grid Nyquist wavenumber): |b_0 + 2 sum_l (-1)^l b_l| */
+static const double D2RHO[4] = {0.0, 4.0, 16.0 / 3.0, 272.0 / 45.0};
 
 /* Wray's low-storage RK3 (Sec. 2.2, eq. RK).  The second alpha is printed
  * with a plus sign; only -17/60 makes the scheme consistent (weights sum to
@@ -68,6 +85,7 @@ static const double RK_BETA[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
 
 typedef struct {
   int nx, ny, nz, nxp, nyp, nzp;
+  int L, r, hw;   /* central half-width, WENO stencil size, ghost layers used */
   size_t np;
   double dx, dz, deta;
   double cv, cp, icv;
@@ -81,6 +99,11 @@ static void make_geom(const ora_problem* P, geom* g) {
   g->cv = P->R_gas / (P->gamma - 1.0);
   g->icv = 1.0 / g->cv;
   g->cp = P->gamma * P->R_gas / (P->gamma - 1.0);
+  g->L = P->central_L ? P->central_L : 2;
+  g->r = P->weno_r ? P->weno_r : 3;
+  g->hw = 2;  /* the shock sensor's fourth-order derivatives */
+  if (g->L > g->hw) g->hw = g->L;
+  if (g->r > g->hw) g->hw = g->r;
 }
 
 static inline size_t pidx(const geom* g, int i, int j, int k) {
@@ -178,30 +201,79 @@ void ora_eigenvectors(double gamma, int d, double u, double v, double w, double 
     }
 }
 
-/* ------------------------------------------------------------ WENO5-JS
- * Jiang-Shu fifth-order reconstruction at the right face of the central
- * cell of (v[-2], v[-1], v[0], v[1], v[2]) = v[0..4]; eps = 1e-6, power 2,
- * linear weights (1/10, 6/10, 3/10).  (Sec. 2.1; order not stated in the
- * paper, fifth order assumed.) */
-double ora_weno5(const double* v) {
-  double vm2 = v[0], vm1 = v[1], v0 = v[2], vp1 = v[3], vp2 = v[4];
-  double q0 = (2.0 * vm2 - 7.0 * vm1 + 11.0 * v0) / 6.0;
-  double q1 = (-vm1 + 5.0 * v0 + 2.0 * vp1) / 6.0;
-  double q2 = (2.0 * v0 + 5.0 * vp1 - vp2) / 6.0;
-  /* smoothness indicators: squared second and first differences of each candidate */
-  double c0 = vm2 - 2.0 * vm1 + v0, e0 = vm2 - 4.0 * vm1 + 3.0 * v0;
-  double c1 = vm1 - 2.0 * v0 + vp1, e1 = vm1 - vp1;
-  double c2 = v0 - 2.0 * vp1 + vp2, e2 = 3.0 * v0 - 4.0 * vp1 + vp2;
-  double s0 = 13.0 / 12.0 * (c0 * c0) + 0.25 * (e0 * e0);
-  double s1 = 13.0 / 12.0 * (c1 * c1) + 0.25 * (e1 * e1);
-  double s2 = 13.0 / 12.0 * (c2 * c2) + 0.25 * (e2 * e2);
-  const double eps = 1e-6;
-  double a0 = 0.1 / ((eps + s0) * (eps + s0));
-  double a1 = 0.6 / ((eps + s1) * (eps + s1));
-  double a2 = 0.3 / ((eps + s2) * (eps + s2));
-  double sum = a0 + a1 + a2;
-  return (a0 * q0 + a1 * q1 + a2 * q2) / sum;
+/* ------------------------------------------------------------ WENO-JS
+ * Jiang-Shu weighted reconstruction of order 2r - 1 at the right face of
+ * cell i from the r candidate stencils S_k = {i-r+1+k, ..., i+k}
+ * (k = 0..r-1).  v[0..2r-2] holds cells i-r+1..i+r-1.  ora_weno_parts gives
+ * each candidate's polynomial value at the face, q_k, and its smoothness
+ * indicator beta_k (sum over the derivatives m = 1..r-1 of the squared m-th
+ * derivative of the candidate polynomial integrated over cell i, scaled by
+ * h^(2m-1)); ora_weno combines them with the nonlinear weights
+ * d_k/(eps + beta_k)^2, eps = 1e-6, normalised.  Linear weights d_k:
+ * r = 2: (1/3, 2/3); r = 3: (1/10, 6/10, 3/10); r = 4: (1/35, 12/35, 18/35,
+ * 4/35).  (Sec. 2.1 cites the Jiang-Shu scheme without its order; the
+ * default is r = 3, fifth order.) */
+void ora_weno_parts(int r, const double* v, double* q, double* beta) {
+  const double* c = v + (r - 1);  /* c[0] = cell i */
+  if (r == 2) {
+    q[0] = (-c[-1] + 3.0 * c[0]) / 2.0;
+    q[1] = (c[0] + c[1]) / 2.0;
+    beta[0] = (c[0] - c[-1]) * (c[0] - c[-1]);
+    beta[1] = (c[1] - c[0]) * (c[1] - c[0]);
+  } else if (r == 3) {
+    double vm2 = c[-2], vm1 = c[-1], v0 = c[0], vp1 = c[1], vp2 = c[2];
+    q[0] = (2.0 * vm2 - 7.0 * vm1 + 11.0 * v0) / 6.0;
+    q[1] = (-vm1 + 5.0 * v0 + 2.0 * vp1) / 6.0;
+    q[2] = (2.0 * v0 + 5.0 * vp1 - vp2) / 6.0;
+    /* squared second and first differences of each candidate */
+    double c0 = vm2 - 2.0 * vm1 + v0, e0 = vm2 - 4.0 * vm1 + 3.0 * v0;
+    double c1 = vm1 - 2.0 * v0 + vp1, e1 = vm1 - vp1;
+    double c2 = v0 - 2.0 * vp1 + vp2, e2 = 3.0 * v0 - 4.0 * vp1 + vp2;
+    beta[0] = 13.0 / 12.0 * (c0 * c0) + 0.25 * (e0 * e0);
+    beta[1] = 13.0 / 12.0 * (c1 * c1) + 0.25 * (e1 * e1);
+    beta[2] = 13.0 / 12.0 * (c2 * c2) + 0.25 * (e2 * e2);
+  } else {
+    double a = c[-3], b = c[-2], d = c[-1], e = c[0], f = c[1], g = c[2], h = c[3];
+    q[0] = (-3.0 * a + 13.0 * b - 23.0 * d + 25.0 * e) / 12.0;
+    q[1] = (b - 5.0 * d + 13.0 * e + 3.0 * f) / 12.0;
+    q[2] = (-d + 7.0 * e + 7.0 * f - g) / 12.0;
+    q[3] = (3.0 * e + 13.0 * f - 5.0 * g + h) / 12.0;
+    /* the indicators as quadratic forms of the four stencil values
+     * (Balsara and Shu's seventh-order scheme), divided by 240 */
+    beta[0] = (a * (547.0 * a - 3882.0 * b + 4642.0 * d - 1854.0 * e) +
+               b * (7043.0 * b - 17246.0 * d + 7042.0 * e) + d * (11003.0 * d - 9402.0 * e) +
+               2107.0 * e * e) / 240.0;
+    beta[1] = (b * (267.0 * b - 1642.0 * d + 1602.0 * e - 494.0 * f) +
+               d * (2843.0 * d - 5966.0 * e + 1922.0 * f) + e * (3443.0 * e - 2522.0 * f) +
+               547.0 * f * f) / 240.0;
+    beta[2] = (d * (547.0 * d - 2522.0 * e + 1922.0 * f - 494.0 * g) +
+               e * (3443.0 * e - 5966.0 * f + 1602.0 * g) + f * (2843.0 * f - 1642.0 * g) +
+               267.0 * g * g) / 240.0;
+    beta[3] = (e * (2107.0 * e - 9402.0 * f + 7042.0 * g - 1854.0 * h) +
+               f * (11003.0 * f - 17246.0 * g + 4642.0 * h) + g * (7043.0 * g - 3882.0 * h) +
+               547.0 * h * h) / 240.0;
+  }
 }
+
+double ora_weno(int r, const double* v) {
+  static const double DLIN[5][4] = {{0, 0, 0, 0}, {0, 0, 0, 0},
+                                    {1.0 / 3.0, 2.0 / 3.0, 0, 0},
+                                    {0.1, 0.6, 0.3, 0},
+                                    {1.0 / 35.0, 12.0 / 35.0, 18.0 / 35.0, 4.0 / 35.0}};
+  double q[4], beta[4];
+  ora_weno_parts(r, v, q, beta);
+  const double eps = 1e-6;
+  double num = 0.0, sum = 0.0;
+  for (int k = 0; k < r; ++k) {
+    double ak = DLIN[r][k] / ((eps + beta[k]) * (eps + beta[k]));
+    num += ak * q[k];
+    sum += ak;
+  }
+  return num / sum;
+}
+
+/* fifth-order case, kept as its own entry point for the tests */
+double ora_weno5(const double* v) { return ora_weno(3, v); }
 
 /* ------------------------------------------------------------ inflow turbulence
  * Synthetic inflow turbulence by digital filtering (Sec. 3.2: the DF method
@@ -320,6 +392,7 @@ int ora_df_update(const ora_problem* P, uint64_t key, double dt, int first, doub
  * qb the boundary node, qi its interior neighbour, out[s-1] ghost s. */
 static void char_ghosts(const ora_problem* P, const geom* g, int d, int hi, const double qb[5],
                         const double qi[5], double out[H][5]) {
+  const int hw = g->hw;
   double dq[5];
   for (int m = 0; m < 5; ++m) dq[m] = qb[m] - qi[m];
   prim_t s0 = to_prim(P, g, qb);
@@ -335,7 +408,7 @@ static void char_ghosts(const ora_problem* P, const geom* g, int d, int hi, cons
     int outgoing = hi ? (lam[a] > 0.0) : (lam[a] < 0.0);
     dv[a] = outgoing ? acc : 0.0;
   }
-  for (int s = 1; s <= H; ++s)
+  for (int s = 1; s <= hw; ++s)
     for (int m = 0; m < 5; ++m) {
       double acc = 0.0;
       for (int a = 0; a < 5; ++a) acc += Rn[m * 5 + a] * dv[a];
@@ -345,7 +418,7 @@ static void char_ghosts(const ora_problem* P, const geom* g, int d, int hi, cons
 
 /* ------------------------------------------------------------ ghost nodes */
 static int fill_ghosts(const ora_problem* P, const geom* g, double* W[5]) {
-  const int nx = g->nx, ny = g->ny, nz = g->nz;
+  const int nx = g->nx, ny = g->ny, nz = g->nz, hw = g->hw;
   int bad = 0;
   /* x faces (interior j, k) */
   for (int side = 0; side < 2; ++side) {
@@ -353,7 +426,7 @@ static int fill_ghosts(const ora_problem* P, const geom* g, double* W[5]) {
     for (int k = 0; k < nz; ++k)
       for (int j = 0; j < ny; ++j) {
         if (kind == BC_PERIODIC) {
-          for (int s = 1; s <= H; ++s) {
+          for (int s = 1; s <= hw; ++s) {
             int gi = side == 0 ? -s : nx - 1 + s;
             int si = side == 0 ? nx - s : s - 1;
             for (int m = 0; m < 5; ++m) W[m][pidx(g, gi, j, k)] = W[m][pidx(g, si, j, k)];
@@ -363,7 +436,7 @@ static int fill_ghosts(const ora_problem* P, const geom* g, double* W[5]) {
           double q[5];
           from_prim(P, pr[0 * ny + j], pr[1 * ny + j], pr[2 * ny + j], pr[3 * ny + j],
                     pr[4 * ny + j], q);
-          for (int s = 1; s <= H; ++s) {
+          for (int s = 1; s <= hw; ++s) {
             int gi = side == 0 ? -s : nx - 1 + s;
             for (int m = 0; m < 5; ++m) W[m][pidx(g, gi, j, k)] = q[m];
           }
@@ -376,13 +449,13 @@ static int fill_ghosts(const ora_problem* P, const geom* g, double* W[5]) {
             qi[m] = W[m][pidx(g, ii, j, k)];
           }
           char_ghosts(P, g, 0, side, qb, qi, gq);
-          for (int s = 1; s <= H; ++s) {
+          for (int s = 1; s <= hw; ++s) {
             int gi = side == 0 ? -s : nx - 1 + s;
             for (int m = 0; m < 5; ++m) W[m][pidx(g, gi, j, k)] = gq[s - 1][m];
           }
         } else if (kind == BC_DF_INFLOW && side == 0) {
           /* the inflow plane of the current step, the same on every layer */
-          for (int s = 1; s <= H; ++s)
+          for (int s = 1; s <= hw; ++s)
             for (int m = 0; m < 5; ++m)
               W[m][pidx(g, -s, j, k)] = P->df_plane[((size_t)m * nz + k) * ny + j];
         } else {
@@ -394,8 +467,8 @@ static int fill_ghosts(const ora_problem* P, const geom* g, double* W[5]) {
   for (int side = 0; side < 2; ++side) {
     int kind = P->bc_kind[2 + side];
     for (int k = 0; k < nz; ++k)
-      for (int i = -H; i < nx + H; ++i) {
-        for (int s = 1; s <= H; ++s) {
+      for (int i = -hw; i < nx + hw; ++i) {
+        for (int s = 1; s <= hw; ++s) {
           int gj = side == 0 ? -s : ny - 1 + s;
           double q[5];
           if (kind == BC_PERIODIC) {
@@ -436,9 +509,9 @@ static int fill_ghosts(const ora_problem* P, const geom* g, double* W[5]) {
   }
   /* z faces over the x,y-extended range: only periodic is accepted */
   if (P->bc_kind[4] != BC_PERIODIC || P->bc_kind[5] != BC_PERIODIC) return ORA_EUNSUP;
-  for (int j = -H; j < ny + H; ++j)
-    for (int i = -H; i < nx + H; ++i)
-      for (int s = 1; s <= H; ++s)
+  for (int j = -hw; j < ny + hw; ++j)
+    for (int i = -hw; i < nx + hw; ++i)
+      for (int s = 1; s <= hw; ++s)
         for (int m = 0; m < 5; ++m) {
           W[m][pidx(g, i, j, -s)] = W[m][pidx(g, i, j, nz - s)];
           W[m][pidx(g, i, j, nz - 1 + s)] = W[m][pidx(g, i, j, s - 1)];
@@ -470,6 +543,8 @@ static int validate(const ora_problem* P) {
     if (k == BC_SHOCK_TOP && P->bc_nparams[f] != 11) return ORA_EINVAL;
   }
   if (P->sensor_mode < 0 || P->sensor_mode > 2) return ORA_EINVAL;
+  if (P->central_L < 0 || P->central_L > 3) return ORA_EINVAL;
+  if (P->weno_r != 0 && (P->weno_r < 2 || P->weno_r > 4)) return ORA_EINVAL;
   return ORA_OK;
 }
 
@@ -520,10 +595,11 @@ static int prepare(const ora_problem* P, const double* w, work_t* a) {
   int st = fill_ghosts(P, g, a->W);
   if (st == ORA_EUNSUP) return st;
   int bad = st == ORA_ESTATE;
+  const int hw = g->hw;  /* layers beyond hw stay unset and unused */
 #pragma omp parallel for reduction(| : bad)
-  for (int k = -H; k < g->nz + H; ++k)
-    for (int j = -H; j < g->ny + H; ++j)
-      for (int i = -H; i < g->nx + H; ++i) {
+  for (int k = -hw; k < g->nz + hw; ++k)
+    for (int j = -hw; j < g->ny + hw; ++j)
+      for (int i = -hw; i < g->nx + hw; ++i) {
         size_t q = pidx(g, i, j, k);
         double s5[5] = {a->W[0][q], a->W[1][q], a->W[2][q], a->W[3][q], a->W[4][q]};
         prim_t s = to_prim(P, g, s5);
@@ -535,21 +611,27 @@ static int prepare(const ora_problem* P, const double* w, work_t* a) {
 }
 
 /* ------------------------------------------------------------ derivatives
- * First and second derivatives, 4th order (Sec. 2.1).  The y direction uses
- * the computational coordinate eta with the analytic metric:
+ * First and second derivatives of order 2L (Sec. 2.1).  The y direction
+ * uses the computational coordinate eta with the analytic metric:
  * d/dy = (1/y_eta) d/deta,  d2/dy2 = (d2/deta2 - y_etaeta d/dy)/y_eta^2. */
-static inline double d1(const double* f, size_t q, size_t s, double inv) {
-  return inv * (A1 * (f[q + s] - f[q - s]) + A2 * (f[q + 2 * s] - f[q - 2 * s]));
+static inline double d1(const double* f, size_t q, size_t s, double inv, int L) {
+  double acc = 0.0;
+  for (int l = 1; l <= L; ++l) acc += ACOEF[L][l - 1] * (f[q + l * s] - f[q - l * s]);
+  return inv * acc;
 }
-static inline double d2(const double* f, size_t q, size_t s, double inv2) {
-  return inv2 * (B0 * f[q] + B1 * (f[q + s] + f[q - s]) + B2 * (f[q + 2 * s] + f[q - 2 * s]));
+static inline double d2(const double* f, size_t q, size_t s, double inv2, int L) {
+  double acc = BCOEF[L][0] * f[q];
+  for (int l = 1; l <= L; ++l) acc += BCOEF[L][l] * (f[q + l * s] + f[q - l * s]);
+  return inv2 * acc;
 }
 
 /* ------------------------------------------------------------ shock sensor
  * Ducros sensor (Sec. 2.1, eq. sensor):
  * theta = max(-div u / sqrt(div^2 + |curl u|^2 + eps_s), 0), with the
  * regulariser eps_s = (u0/L0)^2 given per case (the printed form is read as
- * a squared inverse time scale). */
+ * a squared inverse time scale).  Its velocity derivatives are of fourth
+ * order whatever the order of the fluxes (the paper ties the sensor to no
+ * scheme order). */
 static void sensor_theta(const ora_problem* P, work_t* a, double* theta /* [N] or NULL */) {
   const geom* g = &a->g;
   size_t sx = 1, sy = (size_t)g->nxp, sz = (size_t)g->nxp * g->nyp;
@@ -559,9 +641,12 @@ static void sensor_theta(const ora_problem* P, work_t* a, double* theta /* [N] o
       double iy = 1.0 / (g->deta * P->y_eta[j]);
       for (int i = 0; i < g->nx; ++i) {
         size_t q = pidx(g, i, j, k);
-        double ux = d1(a->u, q, sx, 1.0 / g->dx), uy = d1(a->u, q, sy, iy), uz = d1(a->u, q, sz, 1.0 / g->dz);
-        double vx = d1(a->v, q, sx, 1.0 / g->dx), vy = d1(a->v, q, sy, iy), vz = d1(a->v, q, sz, 1.0 / g->dz);
-        double wx = d1(a->w, q, sx, 1.0 / g->dx), wy = d1(a->w, q, sy, iy), wz = d1(a->w, q, sz, 1.0 / g->dz);
+        double ux = d1(a->u, q, sx, 1.0 / g->dx, 2), uy = d1(a->u, q, sy, iy, 2);
+        double uz = d1(a->u, q, sz, 1.0 / g->dz, 2);
+        double vx = d1(a->v, q, sx, 1.0 / g->dx, 2), vy = d1(a->v, q, sy, iy, 2);
+        double vz = d1(a->v, q, sz, 1.0 / g->dz, 2);
+        double wx = d1(a->w, q, sx, 1.0 / g->dx, 2), wy = d1(a->w, q, sy, iy, 2);
+        double wz = d1(a->w, q, sz, 1.0 / g->dz, 2);
         double div = ux + vy + wz;
         double ox = wy - vz, oy = uz - wx, oz = vx - uy;
         double den = sqrt(div * div + (ox * ox + oy * oy + oz * oz) + P->sensor_eps);
@@ -592,7 +677,7 @@ static void wrap_flags(const ora_problem* P, work_t* a) {
 
 /* Interface flags: interface i+1/2 in direction d uses the shock-capturing
  * flux when the sensor mode forces it everywhere, or when any of the nodes
- * i-1, i, i+1, i+2 (the central stencil) is flagged.  The two boundary
+ * i-L+1..i+L (the stencil of the central flux of order 2L) is flagged.  The two boundary
  * interfaces of a non-periodic direction (walls and open boundaries) always
  * use the central flux. */
 static void interface_flags(const ora_problem* P, work_t* a) {
@@ -610,7 +695,8 @@ static void interface_flags(const ora_problem* P, work_t* a) {
           if (!per && id[d] == n[d] - 1) f = 0;
           else if (P->sensor_mode == 2) f = 1;
           else if (P->sensor_mode == 1)
-            f = a->nflag[q - st[d]] | a->nflag[q] | a->nflag[q + st[d]] | a->nflag[q + 2 * st[d]];
+            for (int o = 1 - g->L; o <= g->L; ++o)
+              f |= a->nflag[(size_t)((ptrdiff_t)q + (ptrdiff_t)o * (ptrdiff_t)st[d])];
           a->iflag[d][q] = f;
         }
   }
@@ -621,9 +707,9 @@ static void interface_flags(const ora_problem* P, work_t* a) {
  * (1/8)(F_a + F_b)(G_a + G_b)(H_a + H_b), appears below with F = rho,
  * G = u_n and H = phi. */
 
-/* Energy-preserving central flux of order 4 (L = 2) at interface i+1/2,
- * node i at padded index q, stride s along the direction d (eq. encflux):
- * f = 2 sum_{l=1}^{2} a_l sum_{m=0}^{l-1} avg(rho, u_n, phi)_{i-m,l}, with
+/* Energy-preserving central flux of order 2L at interface i+1/2, node i at
+ * padded index q, stride s along the direction d (eq. encflux):
+ * f = 2 sum_{l=1}^{L} a_l sum_{m=0}^{l-1} avg(rho, u_n, phi)_{i-m,l}, with
  * phi = 1, u, v, w, H.  The pressure term of the momentum equation is put
  * in the same conservative form with two-point averages,
  * 2 sum_l a_l sum_m (p_{i-m} + p_{i-m+l})/2.  Output in natural order;
@@ -631,44 +717,53 @@ static void interface_flags(const ora_problem* P, work_t* a) {
  *
  * Evaluation order (fixed, so that results can be compared bit for bit at
  * low Mach number, where the residual is a small difference of large
- * fluxes): per pair t the mass-flux factor M_t = (2 a_t) (1/8)(rho_a +
- * rho_b)(u_a + u_b); per component f = M_0 (phi_a + phi_b)_0, then
- * f = fma(M_t, (phi_a + phi_b)_t, f) for t = 1, 2; the pressure part
- * a_0 (p_a + p_b)_0 accumulated the same way. */
+ * fluxes): the pairs (i-m, i-m+l) are taken with l ascending and m
+ * ascending within l; per pair t the mass-flux factor M_t = (2 a_l)
+ * (1/8)(rho_a + rho_b)(u_a + u_b); per component f = M_0 (phi_a + phi_b)_0,
+ * then f = fma(M_t, (phi_a + phi_b)_t, f) for the following pairs; the
+ * pressure part a_l (p_a + p_b) accumulated the same way. */
 static void central_flux(const work_t* a, size_t q, size_t s, int d, int conv, int pres,
                          double f[5]) {
   const double* un = d == 0 ? a->u : (d == 1 ? a->v : a->w);
   const double* r = a->rho;
   const double* phis[5] = {NULL, a->u, a->v, a->w, a->Ht};
-  /* pairs (i-m, i-m+l): (i,i+1) l=1 m=0; (i,i+2) l=2 m=0; (i-1,i+1) l=2 m=1 */
-  size_t pa[3] = {q, q, q - s};
-  size_t pb[3] = {q + s, q + 2 * s, q + s};
-  double al[3] = {A1, A2, A2};
-  double M[3];
-  for (int t = 0; t < 3; ++t)
+  const int L = a->g.L;
+  /* pairs (i-m, i-m+l), l = 1..L, m = 0..l-1 */
+  size_t pa[6], pb[6];
+  double al[6];
+  int np = 0;
+  for (int l = 1; l <= L; ++l)
+    for (int m = 0; m < l; ++m) {
+      pa[np] = q - (size_t)m * s;
+      pb[np] = q + (size_t)(l - m) * s;
+      al[np] = ACOEF[L][l - 1];
+      ++np;
+    }
+  double M[6];
+  for (int t = 0; t < np; ++t)
     M[t] = (2.0 * al[t]) * (0.125 * (r[pa[t]] + r[pb[t]]) * (un[pa[t]] + un[pb[t]]));
   for (int c = 0; c < 5; ++c) {
-    double sum[3];
-    for (int t = 0; t < 3; ++t)
+    double sum[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < np; ++t)
       sum[t] = c == 0 ? 2.0 : phis[c][pa[t]] + phis[c][pb[t]];
     double acc = M[0] * sum[0];
-    acc = fma(M[1], sum[1], acc);
-    acc = fma(M[2], sum[2], acc);
+    for (int t = 1; t < np; ++t) acc = fma(M[t], sum[t], acc);
     f[c] = conv ? acc : 0.0;
   }
   if (pres) {
     double acc = al[0] * (a->p[pa[0]] + a->p[pb[0]]);
-    acc = fma(al[1], a->p[pa[1]] + a->p[pb[1]], acc);
-    acc = fma(al[2], a->p[pa[2]] + a->p[pb[2]], acc);
+    for (int t = 1; t < np; ++t) acc = fma(al[t], a->p[pa[t]] + a->p[pb[t]], acc);
     f[1 + d] += acc;
   }
 }
 
 /* Shock-capturing flux at interface i+1/2 (Sec. 2.1): Lax-Friedrichs flux
  * vector splitting of the characteristic fields, each split flux
- * reconstructed with WENO5.  Eigenvectors at the Roe average of nodes i and
- * i+1; splitting constant per field = max |eigenvalue| over the six stencil
- * nodes i-2..i+3 (local Lax-Friedrichs). */
+ * reconstructed with the WENO scheme of order 2r - 1 (the positive part
+ * from cells i-r+1..i+r-1, the negative part mirrored about the interface
+ * from cells i+r..i-r+2).  Eigenvectors at the Roe average of nodes i and
+ * i+1; splitting constant per field = max |eigenvalue| over the 2r stencil
+ * nodes i-r+1..i+r (local Lax-Friedrichs). */
 static void weno_flux(const ora_problem* P, const work_t* a, size_t q, size_t s, int d,
                       double f[5]) {
   int pm[5];
@@ -684,11 +779,12 @@ static void weno_flux(const ora_problem* P, const work_t* a, size_t q, size_t s,
   double croe = sqrt((P->gamma - 1.0) * (Hroe - 0.5 * q2));
   double Rm[5][5], Lm[5][5];
   eigvecs_perm(P->gamma - 1.0, uroe[d], uroe[(d + 1) % 3], uroe[(d + 2) % 3], Hroe, croe, Rm, Lm);
-  /* stencil values */
-  double gp[6][5], gmn[6][5], alpha[5] = {0, 0, 0, 0, 0};
-  double vch[6][5], gch[6][5];
-  for (int t = 0; t < 6; ++t) {
-    size_t qs = q + (size_t)((long)(t - 2) * (long)s);
+  /* stencil values, node i-r+1+t */
+  const int rw = a->g.r, ns = 2 * rw;
+  double gp[8][5], gmn[8][5], alpha[5] = {0, 0, 0, 0, 0};
+  double vch[8][5], gch[8][5];
+  for (int t = 0; t < ns; ++t) {
+    size_t qs = q + (size_t)((long)(t - rw + 1) * (long)s);
     double wn[5], fn[5];
     for (int c = 0; c < 5; ++c) wn[c] = a->W[pm[c]][qs];
     double un = vel[d][qs];
@@ -709,13 +805,16 @@ static void weno_flux(const ora_problem* P, const work_t* a, size_t q, size_t s,
   }
   double ghat[5];
   for (int k = 0; k < 5; ++k) {
-    for (int t = 0; t < 6; ++t) {
+    for (int t = 0; t < ns; ++t) {
       gp[t][k] = 0.5 * (gch[t][k] + alpha[k] * vch[t][k]);
       gmn[t][k] = 0.5 * (gch[t][k] - alpha[k] * vch[t][k]);
     }
-    double sp[5] = {gp[0][k], gp[1][k], gp[2][k], gp[3][k], gp[4][k]};       /* i-2..i+2 */
-    double sm[5] = {gmn[5][k], gmn[4][k], gmn[3][k], gmn[2][k], gmn[1][k]};  /* i+3..i-1 */
-    ghat[k] = ora_weno5(sp) + ora_weno5(sm);
+    double sp[7], sm[7];
+    for (int t = 0; t < ns - 1; ++t) {
+      sp[t] = gp[t][k];            /* i-r+1..i+r-1 */
+      sm[t] = gmn[ns - 1 - t][k];  /* i+r..i-r+2 */
+    }
+    ghat[k] = ora_weno(rw, sp) + ora_weno(rw, sm);
   }
   for (int c = 0; c < 5; ++c) {
     double acc = 0.0;
@@ -779,7 +878,7 @@ static void euler_terms(const ora_problem* P, work_t* a, double* r) {
 
 /* ------------------------------------------------------------ viscous terms
  * Laplacian form (Sec. 2.1): d/dx_j (mu du/dx_j) = dmu/dx_j du/dx_j +
- * mu d2u/dx_j2 with 4th-order first and second derivatives; the stress
+ * mu d2u/dx_j2 with first and second derivatives of order 2L; the stress
  * divergence expands to
  *   F_i = mu (lap u_i + (1/3) d_i div) + d_j mu (d_j u_i + d_i u_j) - (2/3) d_i mu div,
  * the energy equation receives u_i F_i + sigma_ij d_j u_i (the work of the
@@ -793,6 +892,7 @@ static void viscous_terms(const ora_problem* P, work_t* a, double* r) {
   double ix = 1.0 / g->dx, iz = 1.0 / g->dz;
   double ix2 = ix * ix, iz2 = iz * iz, ie2 = 1.0 / (g->deta * g->deta);
   double kfac = g->cp / P->Pr;
+  const int L = g->L;
 #pragma omp parallel for
   for (int k = 0; k < g->nz; ++k)
     for (int j = 0; j < g->ny; ++j) {
@@ -803,35 +903,35 @@ static void viscous_terms(const ora_problem* P, work_t* a, double* r) {
         const double* fld[4] = {a->u, a->v, a->w, a->T};
         double gx[4], gy[4], gz[4], lap[4];
         for (int f = 0; f < 4; ++f) {
-          gx[f] = d1(fld[f], q, sx, ix);
-          gy[f] = d1(fld[f], q, sy, iy);
-          gz[f] = d1(fld[f], q, sz, iz);
-          double fxx = d2(fld[f], q, sx, ix2);
-          double fyy = (d2(fld[f], q, sy, ie2) - yee * gy[f]) / (ye * ye);
-          double fzz = d2(fld[f], q, sz, iz2);
+          gx[f] = d1(fld[f], q, sx, ix, L);
+          gy[f] = d1(fld[f], q, sy, iy, L);
+          gz[f] = d1(fld[f], q, sz, iz, L);
+          double fxx = d2(fld[f], q, sx, ix2, L);
+          double fyy = (d2(fld[f], q, sy, ie2, L) - yee * gy[f]) / (ye * ye);
+          double fzz = d2(fld[f], q, sz, iz2, L);
           lap[f] = fxx + fyy + fzz;
         }
-        double uxx = d2(a->u, q, sx, ix2);
-        double vyy = (d2(a->v, q, sy, ie2) - yee * gy[1]) / (ye * ye);
-        double wzz = d2(a->w, q, sz, iz2);
-        /* mixed derivatives as compositions of first derivatives */
-        double ux_at[5], vx_at[5], ux_z[5], wx_z[5], vy_z[5], wy_z[5];
-        for (int l = -2; l <= 2; ++l) {
+        double uxx = d2(a->u, q, sx, ix2, L);
+        double vyy = (d2(a->v, q, sy, ie2, L) - yee * gy[1]) / (ye * ye);
+        double wzz = d2(a->w, q, sz, iz2, L);
+        /* mixed derivatives as compositions of first derivatives; the
+         * windows hold the inner derivative at offsets -L..L */
+        double ux_at[7], vx_at[7], ux_z[7], wx_z[7], vy_z[7], wy_z[7];
+        for (int l = -L; l <= L; ++l) {
           size_t qy = q + (size_t)((long)l * (long)sy);
-          ux_at[l + 2] = d1(a->u, qy, sx, ix);
-          vx_at[l + 2] = d1(a->v, qy, sx, ix);
+          ux_at[l + L] = d1(a->u, qy, sx, ix, L);
+          vx_at[l + L] = d1(a->v, qy, sx, ix, L);
           size_t qz = q + (size_t)((long)l * (long)sz);
-          ux_z[l + 2] = d1(a->u, qz, sx, ix);
-          wx_z[l + 2] = d1(a->w, qz, sx, ix);
-          vy_z[l + 2] = d1(a->v, qz, sy, iy);
-          wy_z[l + 2] = d1(a->w, qz, sy, iy);
+          ux_z[l + L] = d1(a->u, qz, sx, ix, L);
+          wx_z[l + L] = d1(a->w, qz, sx, ix, L);
+          vy_z[l + L] = d1(a->v, qz, sy, iy, L);
+          wy_z[l + L] = d1(a->w, qz, sy, iy, L);
         }
-#define D1ARR(arr, inv) ((inv) * (A1 * ((arr)[3] - (arr)[1]) + A2 * ((arr)[4] - (arr)[0])))
-        double uxy = D1ARR(ux_at, iy), vxy = D1ARR(vx_at, iy);
-        double uxz = D1ARR(ux_z, iz), wxz = D1ARR(wx_z, iz);
-        double vyz = D1ARR(vy_z, iz), wyz = D1ARR(wy_z, iz);
-#undef D1ARR
-        double mux = d1(a->mu, q, sx, ix), muy = d1(a->mu, q, sy, iy), muz = d1(a->mu, q, sz, iz);
+        double uxy = d1(ux_at, L, 1, iy, L), vxy = d1(vx_at, L, 1, iy, L);
+        double uxz = d1(ux_z, L, 1, iz, L), wxz = d1(wx_z, L, 1, iz, L);
+        double vyz = d1(vy_z, L, 1, iz, L), wyz = d1(wy_z, L, 1, iz, L);
+        double mux = d1(a->mu, q, sx, ix, L), muy = d1(a->mu, q, sy, iy, L);
+        double muz = d1(a->mu, q, sz, iz, L);
         double mu = a->mu[q];
         double ux = gx[0], uy = gy[0], uz = gz[0];
         double vx = gx[1], vy = gy[1], vz = gz[1];
@@ -952,9 +1052,10 @@ int ora_rhs(const ora_problem* P, const double* w, double* r, double* theta,
 }
 
 /* Time step (the paper gives no rule): dt = CFL * min(1/max_i sum_d (|u_d|+c)/dx_d,
- * 2.5/max_i [max(4/3, gamma/Pr) (mu/rho) (16/3) sum_d dx_d^-2]); 2.5 is about
- * the real-axis stability bound of the RK3 scheme and 16/3 the largest
- * magnitude of the 4th-order second-derivative symbol. */
+ * 2.5/max_i [max(4/3, gamma/Pr) (mu/rho) rho_2 sum_d dx_d^-2]); 2.5 is about
+ * the real-axis stability bound of the RK3 scheme and rho_2 the largest
+ * magnitude of the symbol of the second derivative in use (4, 16/3 and
+ * 272/45 for orders 2, 4 and 6). */
 int ora_dt(const ora_problem* P, const double* w, double cfl, double* dt_out) {
   int st = validate(P);
   if (st) return st;
@@ -981,7 +1082,7 @@ int ora_dt(const ora_problem* P, const double* w, double cfl, double* dt_out) {
     }
   double dt = 1.0 / cmax;
   if (P->viscous && vmax > 0.0) {
-    double dv = 2.5 / (16.0 / 3.0 * vmax);
+    double dv = 2.5 / (D2RHO[g.L] * vmax);
     if (dv < dt) dt = dv;
   }
   *dt_out = cfl * dt;

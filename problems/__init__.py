@@ -74,6 +74,8 @@ class Problem:
     w0: Optional[np.ndarray] = None   # (5, nz, ny, nx)
     cfl: float = 0.8
     nsteps: int = 10
+    central_order: int = 4   # order 2L of the central flux and viscous terms: 2, 4 or 6
+    weno_order: int = 5      # order 2r-1 of the WENO reconstruction: 3, 5 or 7
 
     @property
     def npts(self) -> int:
