@@ -19,6 +19,7 @@ state) and the FP64 oracle timed on the host cores on a bounded sample of
 the same workload.
 """
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -39,11 +40,14 @@ STEP_BYTES_PER_PT_FORCED = 448.0
 # The fused right-hand-side kernel must read w (40 B) and write R (40 B).
 RHS_BYTES_PER_PT = 80.0
 # FP64 operations of one shock-capturing interface flux, counted from the
-# formula (a fused multiply-add counts two, a division or square root one):
-# Roe average and eigenvalue constants 64, six nodes x (primitives, flux,
-# two characteristic projections, eigenvalue bounds) 444, Lax-Friedrichs
-# splitting 100, ten WENO5 reconstructions 690, back-projection 26.
-WENO_FLOPS_PER_IFACE = 1324.0
+# formula (a fused multiply-add counts two, a division or square root one),
+# by WENO order 2r-1: Roe average and eigenvalue constants 64; 2r nodes x
+# (primitives, flux, two characteristic projections, eigenvalue bounds) 74
+# each; Lax-Friedrichs splitting 20 per reconstruction node (2r-1 per side);
+# ten reconstructions of 20 (WENO3), 69 (WENO5) or 149 (WENO7) each;
+# back-projection 26.  WENO5: 64 + 444 + 100 + 690 + 26 = 1324.
+WENO_FLOPS_BY_ORDER = {3: 646.0, 5: 1324.0, 7: 2312.0}
+WENO_FLOPS_PER_IFACE = WENO_FLOPS_BY_ORDER[5]
 
 
 # name -> (problem constructor name, description)
@@ -112,6 +116,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=list(WORKLOADS), default="channel",
                     help="channel (the headline workload); sbli, tgv, bl (reference figures)")
+    ap.add_argument("--central-order", type=int, choices=[2, 4, 6], default=4,
+                    help="order of the central flux and viscous terms")
+    ap.add_argument("--weno-order", type=int, choices=[3, 5, 7], default=5,
+                    help="order of the WENO reconstruction")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path (one simulation "
@@ -133,6 +141,9 @@ def main():
     torch.cuda.synchronize()
     del src, dst
     pr = getattr(P, WORKLOADS[args.workload][0])()
+    pr = dataclasses.replace(pr, central_order=args.central_order, weno_order=args.weno_order)
+    # counter-based traffic figures were taken with the default scheme
+    default_scheme = (args.central_order, args.weno_order) == (4, 5)
     precision = 0 if args.precision == "fp64" else 1
     s = Solver(pr, precision=precision)
     cfl = pr.cfl
@@ -165,20 +176,23 @@ def main():
     mean_ms = ph[dom][0]
     if dom == "weno":
         n_iface = n_iface_total / max(ph["weno"][1], 1)
-        flops = WENO_FLOPS_PER_IFACE * n_iface
+        fl_if = WENO_FLOPS_BY_ORDER[args.weno_order]
+        flops = fl_if * n_iface
         achieved = flops / (mean_ms * 1e-3) / 1e12
         roof = {"kernel": "k_weno", "bound": "alu", "achieved": achieved,
                 "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_TFLOPS,
-                "traffic": load_traffic("k_weno"),
-                "algorithmic_per_launch": f"{WENO_FLOPS_PER_IFACE:.0f} flop x {n_iface:.0f} "
+                "traffic": load_traffic("k_weno") if default_scheme else None,
+                "algorithmic_per_launch": f"{fl_if:.0f} flop x {n_iface:.0f} "
                                           f"interfaces (mean over the timed launches)"}
     else:
         nbytes = RHS_BYTES_PER_PT * pr.npts
         achieved = nbytes / (ph["rhs"][0] * 1e-3) / 1e9
         roof = {"kernel": "k_rhs", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic("k_rhs"),
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic("k_rhs") if default_scheme else None,
                 "algorithmic_per_launch": f"{RHS_BYTES_PER_PT:.0f} B x {pr.npts} points"}
     roof["mean_launch_ms"] = mean_ms
+    scheme = ("" if (args.central_order, args.weno_order) == (4, 5) else
+              f"; central order {args.central_order}, WENO order {args.weno_order}")
     hbm_frac_step = value * 1e6 * STEP_BYTES_PER_PT_FORCED / (HBM_PEAK_GBS * 1e9)
 
     out = {
@@ -194,7 +208,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if precision == 0 else "f32-flux/f64-state",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload][1],
+        "config": {"workload": WORKLOADS[args.workload][1] + scheme,
                    "points": pr.npts, "parallelism": "single GPU"},
         "hbm_frac_step_algorithmic": hbm_frac_step,
         "phase_ms_per_step": per_step,

@@ -8,12 +8,14 @@
  * momentum and total energy of a perfect heat-conducting gas with Newtonian
  * stresses, Fourier heat flux, Sutherland viscosity, k = c_p mu / Pr, and an
  * optional streamwise body force f with power f u (constant mass flow).
- * Convective terms (Sec. 2.1, eqs. num_flux, avg_operator, encflux): fourth
- * order kinetic-energy-preserving central flux in split form, replaced at
- * interfaces flagged by the Ducros sensor (eq. sensor) with WENO
- * reconstruction of Lax-Friedrichs-split characteristic fluxes.  Viscous
- * terms in Laplacian form with fourth-order formulas.  Time integration
- * (Sec. 2.2, eq. RK): Wray's three-stage low-storage scheme.
+ * Convective terms (Sec. 2.1, eqs. num_flux, avg_operator, encflux):
+ * kinetic-energy-preserving central flux in split form of order 2L (fourth
+ * order by default, L = 1..3 selectable), replaced at interfaces flagged by
+ * the Ducros sensor (eq. sensor) with WENO reconstruction (fifth order by
+ * default, third and seventh selectable) of Lax-Friedrichs-split
+ * characteristic fluxes.  Viscous terms in Laplacian form with formulas of
+ * the same order 2L.  Time integration (Sec. 2.2, eq. RK): Wray's
+ * three-stage low-storage scheme.
  *
  * Conventions
  *  - Every function returns a cdns_status; nothing aborts or throws across
@@ -104,7 +106,7 @@ enum { CDNS_SENSOR_OFF = 0, CDNS_SENSOR_HYBRID = 1, CDNS_SENSOR_WENO_ALL = 2 };
  *                  E = exp(-pi dt/(2T)); fluctuations u'_i = a_ij psi_j;
  *                  T' = -u_mean u'/c_p at constant pressure (strong
  *                  Reynolds analogy).  The plane is refreshed once per RK
- *                  step and imposed on the three ghost layers.  Not
+ *                  step and imposed on the ghost layers.  Not
  *                  accepted by batches. */
 enum {
   CDNS_BC_PERIODIC = 0,
@@ -177,8 +179,28 @@ cdns_status cdns_set_bc(cdns_ctx* ctx, int32_t face, int32_t kind, const double*
  * one of the compiled variants (64x4, 32x8, 64x2, 128x2, 64x8), kz >= 1
  * planes per block.  Results are bitwise independent of the choice except
  * for the rounding of the bulk-force sum, whose per-tile partial sums follow
- * the tiling.  Returns CDNS_EINVAL for other shapes. */
+ * the tiling.  Returns CDNS_EINVAL for other shapes, CDNS_EUNSUP for a
+ * shape other than 64x4 when the central order is not 4. */
 cdns_status cdns_set_tiling(cdns_ctx* ctx, int32_t tile_x, int32_t tile_y, int32_t kz);
+
+/* Scheme orders (Sec. 2.1; eq. encflux gives the central flux of order 2L
+ * for any L, the viscous formulas use first and second derivatives of the
+ * same order; the WENO scheme is cited without its order).  central_order
+ * in {2, 4, 6} (L = 1, 2, 3): the split-form flux over the pairs
+ * (i-m, i-m+l), l = 1..L, m < l, and the Laplacian-form viscous terms;
+ * interface i+1/2 switches to the shock-capturing flux when a node of
+ * i-L+1..i+L is flagged.  weno_order in {3, 5, 7}: Jiang-Shu reconstruction
+ * from r = 2, 3, 4 candidate stencils (smoothness indicators are the
+ * integrals of the squared candidate derivatives, eps = 1e-6), the
+ * Lax-Friedrichs constant taken over the 2r stencil nodes.  The shock
+ * sensor keeps fourth-order derivatives, and the viscous time-step bound
+ * uses the largest magnitude of the order-2L second-derivative symbol (4,
+ * 16/3, 272/45).  Defaults: 4 and 5.  Orders other than 4 run the fused
+ * kernel in the 64x4 tile only (the tiling is reset to the default if it
+ * differs) and need nz >= central_order.  With a digital-filter inflow the
+ * initial inflow plane is regenerated.  Call before stepping.  Returns
+ * CDNS_EINVAL for other orders or too small a grid. */
+cdns_status cdns_set_scheme(cdns_ctx* ctx, int32_t central_order, int32_t weno_order);
 
 /* Full right-hand side R(w) of dw/dt = R(w) (Sec. 2.2) for the device
  * array w_dev [5][nz][ny][nx], written to r_dev (same layout), including
@@ -256,7 +278,8 @@ cdns_status cdns_batch_create(int32_t max_slots, void* workspace_dev, size_t wor
 size_t cdns_batch_workspace_bytes(int32_t max_slots);
 /* Attach a context (its tile shape and precision must match the batch's);
  * *slot receives its slot.  CDNS_EBUSY: already attached or no free slot;
- * CDNS_EUNSUP: the context uses digital-filter inflow. */
+ * CDNS_EUNSUP: the context uses digital-filter inflow or scheme orders
+ * other than the defaults. */
 cdns_status cdns_batch_attach(cdns_batch* b, cdns_ctx* ctx, int32_t* slot);
 cdns_status cdns_batch_detach(cdns_batch* b, int32_t slot);
 /* nsteps RK3 steps of every attached instance; each uses its own cfl /

@@ -22,6 +22,7 @@ NSTAT = 16  # running-statistics products (CDNS_NSTAT)
 
 EXPORTED = [
     "cdns_version", "cdns_workspace_bytes", "cdns_create", "cdns_set_bc", "cdns_set_tiling",
+    "cdns_set_scheme",
     "cdns_rhs", "cdns_rk_step", "cdns_advance_n", "cdns_diagnostics", "cdns_export_sensor",
     "cdns_export_iface_flux", "cdns_time_phases", "cdns_stats_accumulate", "cdns_stats_export",
     "cdns_stats_reset",
@@ -87,6 +88,8 @@ def load() -> ctypes.CDLL:
     lib.cdns_set_bc.restype = i32
     lib.cdns_set_tiling.argtypes = [vp, i32, i32, i32]
     lib.cdns_set_tiling.restype = i32
+    lib.cdns_set_scheme.argtypes = [vp, i32, i32]
+    lib.cdns_set_scheme.restype = i32
     lib.cdns_rhs.argtypes = [vp, dp, dp]
     lib.cdns_rhs.restype = i32
     lib.cdns_rk_step.argtypes = [vp, f64, f64]

@@ -120,6 +120,16 @@ void set_tiling_desc(Desc& D, int tx, int ty, int kz) {
   D.npart = D.tiles_x * D.tiles_y * D.zchunks;
 }
 
+// Scheme orders: central half-width L (order 2L), WENO stencils r (order
+// 2r-1); ghost layers in use max(2, L, r) (the sensor reaches two); the
+// largest |symbol| of the order-2L second derivative for the time step.
+void set_orders(Desc& D, int L, int r) {
+  D.cl = L;
+  D.wr = r;
+  D.hw = std::max(2, std::max(L, r));
+  D.rho2 = L == 1 ? 4.0 : (L == 2 ? 16.0 / 3.0 : 272.0 / 45.0);
+}
+
 // Default tiling: enough blocks to give each of the 256 CUs two.
 void default_tiling(Desc& D) {
   int tx = 64, ty = 4;
@@ -234,6 +244,7 @@ cdns_status cdns_create(const cdns_grid* grid, const cdns_phys* phys, int32_t pr
   D.muc = phys->mu_ref * (1.0 + phys->S_suth);
   D.kfac = D.cp / phys->Pr;
   D.vfac = std::max(4.0 / 3.0, phys->gamma / phys->Pr);
+  set_orders(D, 2, 3);
   D.theta_star = phys->theta_star;
   D.eps_s = phys->sensor_eps;
   D.viscous = phys->viscous ? 1 : 0;
@@ -388,11 +399,35 @@ cdns_status cdns_set_tiling(cdns_ctx* c, int32_t tx, int32_t ty, int32_t kz) {
   if (!c) return CDNS_EINVAL;
   if (!cdns::rhs_tile_supported(tx, ty) || kz < 1)
     return fail(c, CDNS_EINVAL, "unsupported tile shape");
+  if (c->D.cl != 2 && (tx != 64 || ty != 4))
+    return fail(c, CDNS_EUNSUP, "central orders other than 4 use the 64x4 tile only");
   Desc t = c->D;
   set_tiling_desc(t, tx, ty, kz);
   if ((size_t)t.npart > c->part_cap) return fail(c, CDNS_EINVAL, "too many tiles");
   c->D = t;
   invalidate_graph(c);
+  return CDNS_OK;
+}
+
+cdns_status cdns_set_scheme(cdns_ctx* c, int32_t central_order, int32_t weno_order) {
+  if (!c) return CDNS_EINVAL;
+  if (central_order != 2 && central_order != 4 && central_order != 6)
+    return fail(c, CDNS_EINVAL, "central order must be 2, 4 or 6");
+  if (weno_order != 3 && weno_order != 5 && weno_order != 7)
+    return fail(c, CDNS_EINVAL, "WENO order must be 3, 5 or 7");
+  const int L = central_order / 2, r = (weno_order + 1) / 2;
+  if (c->D.nz < 2 * L) return fail(c, CDNS_EINVAL, "nz is below the central stencil width");
+  Desc t = c->D;
+  set_orders(t, L, r);
+  if (L != 2 && (t.tile_x != 64 || t.tile_y != 4)) default_tiling(t);
+  c->D = t;
+  invalidate_graph(c);
+  if (t.bc[0] == cdns::BC_DF_INFLOW) {
+    // the ghost layers in use may have changed: the initial plane again
+    hipError_t e = cdns::launch_df(t, true, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "inflow generator");
+  }
   return CDNS_OK;
 }
 

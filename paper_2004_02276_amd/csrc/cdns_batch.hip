@@ -141,6 +141,7 @@ cdns_status cdns_batch_attach(cdns_batch* b, cdns_ctx* ctx, int32_t* slot) {
   if (!b || !ctx || !slot) return CDNS_EINVAL;
   const Desc& D = cdns::ctx_desc(ctx);
   if (D.bc[0] == cdns::BC_DF_INFLOW) return CDNS_EUNSUP;  // per-step inflow state not batched
+  if (D.cl != 2 || D.wr != 3) return CDNS_EUNSUP;           // batched kernels: default orders
   for (int s = 0; s < b->max_slots; ++s)
     if (b->slot[s] == ctx) return CDNS_EBUSY;
   bool any = false;

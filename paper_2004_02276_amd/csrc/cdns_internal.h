@@ -8,7 +8,8 @@
 
 namespace cdns {
 
-constexpr int kHalo = 3;          // ghost depth (WENO5 stencil i-2..i+3)
+constexpr int kHalo = 4;          // ghost planes stored (WENO7 stencil i-3..i+4); Desc::hw
+                                  // of them are filled, as many as the stencils reach
 constexpr int kRedBlocks = 1024;  // partial-sum slots of the generic reductions
 
 // Boundary kinds (same values as the C ABI).
@@ -41,6 +42,9 @@ struct Desc {
   double gamma, gm1, R, cv, icv, cp, Pr, mu_ref, iTref, S, muc, kfac;
   double theta_star, eps_s, vol_den;
   double vfac;                    // max(4/3, gamma/Pr) for the viscous time-step bound
+  double rho2;                    // largest |symbol| of the second derivative in use
+  int cl, wr, hw;                 // central half-width L (order 2L), WENO stencils r
+                                  // (order 2r-1), ghost layers filled max(2, L, r)
   int viscous, sensor_mode, forcing, precision;
   int per_x, per_y;
   int bc[6];
@@ -60,11 +64,11 @@ struct Desc {
                                   // compacted: entry e belongs to node list[d][e]
   int* list[3];                   // [N] compacted interface lists per direction
   unsigned* count;                // [4] list lengths
-  double* gx[2];                  // [5][3][nz][ny] x-face ghost planes
+  double* gx[2];                  // [5][kHalo][nz][ny] x-face ghost planes
   double* stats;                  // [NSTAT][ny][nx] spanwise sums of the running statistics
   double* dfpsi;                  // [3][nz][ny] filtered inflow field (digital filter)
   double* dffy;                   // [3][nz][ny] inflow deviates filtered along y
-  double* gy[2];                  // [5][3][nz][nxg] y-face ghost planes
+  double* gy[2];                  // [5][kHalo][nz][nxg] y-face ghost planes
   double* part;                   // [npart] right-hand-side block partial sums (forcing)
   int npart;
   double* red;                    // [2*kRedBlocks] generic reduction partials

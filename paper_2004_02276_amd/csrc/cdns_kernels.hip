@@ -22,16 +22,29 @@
 // x-contiguous rows, so a wavefront touches 512 contiguous bytes per field.
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "cdns_internal.h"
 
 namespace cdns {
 
-// Fourth-order central coefficients (Sec. 2.1).
+// Central finite-difference coefficients of order 2L (Sec. 2.1), L = 1..3:
+// first derivative a_l (l = 1..L), second derivative b_l (l = 0..L).
+__host__ __device__ constexpr double coef_a(int L, int l) {
+  return L == 1 ? 0.5
+       : L == 2 ? (l == 1 ? 2.0 / 3.0 : -1.0 / 12.0)
+                : (l == 1 ? 3.0 / 4.0 : (l == 2 ? -3.0 / 20.0 : 1.0 / 60.0));
+}
+// Fourth-order first-derivative weights of the shock sensor (its order does
+// not follow the flux order).
 #define CA1 (2.0 / 3.0)
 #define CA2 (-1.0 / 12.0)
-#define CB0 (-5.0 / 2.0)
-#define CB1 (4.0 / 3.0)
-#define CB2 (-1.0 / 12.0)
+
+__host__ __device__ constexpr double coef_b(int L, int l) {
+  return L == 1 ? (l == 0 ? -2.0 : 1.0)
+       : L == 2 ? (l == 0 ? -5.0 / 2.0 : (l == 1 ? 4.0 / 3.0 : -1.0 / 12.0))
+                : (l == 0 ? -49.0 / 18.0 : (l == 1 ? 3.0 / 2.0 : (l == 2 ? -3.0 / 20.0 : 1.0 / 90.0)));
+}
 
 // consecutive logical tiles land on the same XCD (blocks are dealt
 // round-robin over the 8 XCDs), so neighbouring tiles share an L2
@@ -229,82 +242,147 @@ __device__ __forceinline__ void to_prim<double>(const Desc& D, const double q[5]
   s.mu = D.mu_ref * tt * wsqrt<double>(tt) * (1.0 + D.S) * wrcp<double>(tt + D.S);
 }
 
-// Energy-preserving central flux (eq. encflux with L = 2) at the interface
-// between nodes b and c of the four consecutive nodes a, b, c, d along
-// direction DIR; pressure in the same conservative form.
-template <typename F, int DIR>
-__device__ __forceinline__ void central_flux(const PV<F>& a, const PV<F>& b, const PV<F>& c,
-                                             const PV<F>& d, F f[5]) {
-  const F na = DIR == 0 ? a.u : (DIR == 1 ? a.v : a.w);
-  const F nb = DIR == 0 ? b.u : (DIR == 1 ? b.v : b.w);
-  const F nc = DIR == 0 ? c.u : (DIR == 1 ? c.v : c.w);
-  const F nd = DIR == 0 ? d.u : (DIR == 1 ? d.v : d.w);
-  const F c1 = F(0.25 * CA1) * ((b.r + c.r) * (nb + nc));
-  const F c2 = F(0.25 * CA2) * ((b.r + d.r) * (nb + nd));
-  const F c3 = F(0.25 * CA2) * ((a.r + c.r) * (na + nc));
-  f[0] = F(2) * (c1 + c2 + c3);
-  f[1] = c1 * (b.u + c.u) + c2 * (b.u + d.u) + c3 * (a.u + c.u);
-  f[2] = c1 * (b.v + c.v) + c2 * (b.v + d.v) + c3 * (a.v + c.v);
-  f[3] = c1 * (b.w + c.w) + c2 * (b.w + d.w) + c3 * (a.w + c.w);
-  f[4] = c1 * (b.h + c.h) + c2 * (b.h + d.h) + c3 * (a.h + c.h);
-  f[1 + DIR] += F(CA1) * (b.p + c.p) + F(CA2) * ((b.p + d.p) + (a.p + c.p));
+// Energy-preserving central flux of order 2L (eq. encflux) at the interface
+// between nodes nd[L-1] and nd[L] of the 2L consecutive nodes nd[0..2L-1]
+// along direction DIR.  The pairs (i-m, i-m+l) are taken with l ascending
+// and m ascending within l; the pressure is put in the same conservative
+// form with two-point averages.
+template <int DIR, typename F>
+__device__ __forceinline__ F normal_vel(const PV<F>& s) {
+  return DIR == 0 ? s.u : (DIR == 1 ? s.v : s.w);
+}
+
+template <typename F, int DIR, int L>
+__device__ __forceinline__ void central_flux(const PV<F>* nd, F f[5]) {
+  constexpr int NP = L * (L + 1) / 2;
+  F c[NP];
+  F pf = F(0);
+  {
+    int t = 0;
+#pragma unroll
+    for (int l = 1; l <= L; ++l) {
+      F ps = F(0);
+#pragma unroll
+      for (int m = 0; m < l; ++m, ++t) {
+        const PV<F>& A = nd[L - 1 - m];
+        const PV<F>& B = nd[L - 1 - m + l];
+        c[t] = F(0.25 * coef_a(L, l)) * ((A.r + B.r) * (normal_vel<DIR>(A) + normal_vel<DIR>(B)));
+        ps = m == 0 ? (A.p + B.p) : ps + (A.p + B.p);
+      }
+      pf = l == 1 ? F(coef_a(L, 1)) * ps : pf + F(coef_a(L, l)) * ps;
+    }
+  }
+  F s0 = c[0], s1 = F(0), s2 = F(0), s3 = F(0), s4 = F(0);
+  {
+    int t = 0;
+#pragma unroll
+    for (int l = 1; l <= L; ++l)
+#pragma unroll
+      for (int m = 0; m < l; ++m, ++t) {
+        const PV<F>& A = nd[L - 1 - m];
+        const PV<F>& B = nd[L - 1 - m + l];
+        if (t > 0) s0 = s0 + c[t];
+        const F a1 = c[t] * (A.u + B.u), a2 = c[t] * (A.v + B.v);
+        const F a3 = c[t] * (A.w + B.w), a4 = c[t] * (A.h + B.h);
+        s1 = t == 0 ? a1 : s1 + a1;
+        s2 = t == 0 ? a2 : s2 + a2;
+        s3 = t == 0 ? a3 : s3 + a3;
+        s4 = t == 0 ? a4 : s4 + a4;
+      }
+  }
+  f[0] = F(2) * s0;
+  f[1] = s1;
+  f[2] = s2;
+  f[3] = s3;
+  f[4] = s4;
+  f[1 + DIR] += pf;
 }
 
 // FP64 version in a fixed evaluation order without contraction: per pair
-// (i,i+1), (i,i+2), (i-1,i+1) the mass-flux factor M = (2 a_l)(1/8)(rho_a +
-// rho_b)(u_a + u_b) (a_l = a_1, a_2, a_2), each component the sum of
-// M (phi_a + phi_b) over the pairs in that order with fused multiply-adds,
-// the pressure part sum a_l (p_a + p_b) the same way.
-template <int DIR>
-__device__ __forceinline__ void central_flux_f64(const PV<double>& a, const PV<double>& b,
-                                                 const PV<double>& c, const PV<double>& d,
-                                                 double f[5]) {
+// the mass-flux factor M = (2 a_l)(1/8)(rho_a + rho_b)(u_a + u_b), each
+// component M_0 (phi_a + phi_b)_0 followed by fused multiply-adds of the
+// later pairs, the pressure part sum a_l (p_a + p_b) the same way.
+template <int DIR, int L>
+__device__ __forceinline__ void central_flux_f64(const PV<double>* nd, double f[5]) {
 #pragma clang fp contract(off)
-  const double na = DIR == 0 ? a.u : (DIR == 1 ? a.v : a.w);
-  const double nb = DIR == 0 ? b.u : (DIR == 1 ? b.v : b.w);
-  const double nc = DIR == 0 ? c.u : (DIR == 1 ? c.v : c.w);
-  const double nd = DIR == 0 ? d.u : (DIR == 1 ? d.v : d.w);
-  const double m1 = (2.0 * CA1) * (0.125 * (b.r + c.r) * (nb + nc));
-  const double m2 = (2.0 * CA2) * (0.125 * (b.r + d.r) * (nb + nd));
-  const double m3 = (2.0 * CA2) * (0.125 * (a.r + c.r) * (na + nc));
-  f[0] = fma(m3, 2.0, fma(m2, 2.0, m1 * 2.0));
-  f[1] = fma(m3, a.u + c.u, fma(m2, b.u + d.u, m1 * (b.u + c.u)));
-  f[2] = fma(m3, a.v + c.v, fma(m2, b.v + d.v, m1 * (b.v + c.v)));
-  f[3] = fma(m3, a.w + c.w, fma(m2, b.w + d.w, m1 * (b.w + c.w)));
-  f[4] = fma(m3, a.h + c.h, fma(m2, b.h + d.h, m1 * (b.h + c.h)));
-  const double pf = fma(CA2, a.p + c.p, fma(CA2, b.p + d.p, CA1 * (b.p + c.p)));
+  constexpr int NP = L * (L + 1) / 2;
+  double M[NP];
+  int ia[NP], ib[NP];
+  double al[NP];
+  {
+    int t = 0;
+#pragma unroll
+    for (int l = 1; l <= L; ++l)
+#pragma unroll
+      for (int m = 0; m < l; ++m, ++t) {
+        ia[t] = L - 1 - m;
+        ib[t] = L - 1 - m + l;
+        al[t] = coef_a(L, l);
+      }
+  }
+#pragma unroll
+  for (int t = 0; t < NP; ++t) {
+    const PV<double>& A = nd[ia[t]];
+    const PV<double>& B = nd[ib[t]];
+    M[t] = (2.0 * al[t]) * (0.125 * (A.r + B.r) * (normal_vel<DIR>(A) + normal_vel<DIR>(B)));
+  }
+  // one component at a time, pairs in order
+  auto comp = [&](auto phi) {
+    double acc = M[0] * phi(nd[ia[0]], nd[ib[0]]);
+#pragma unroll
+    for (int t = 1; t < NP; ++t) acc = fma(M[t], phi(nd[ia[t]], nd[ib[t]]), acc);
+    return acc;
+  };
+  f[0] = comp([](const PV<double>&, const PV<double>&) { return 2.0; });
+  f[1] = comp([](const PV<double>& A, const PV<double>& B) { return A.u + B.u; });
+  f[2] = comp([](const PV<double>& A, const PV<double>& B) { return A.v + B.v; });
+  f[3] = comp([](const PV<double>& A, const PV<double>& B) { return A.w + B.w; });
+  f[4] = comp([](const PV<double>& A, const PV<double>& B) { return A.h + B.h; });
+  double pf = al[0] * (nd[ia[0]].p + nd[ib[0]].p);
+#pragma unroll
+  for (int t = 1; t < NP; ++t) pf = fma(al[t], nd[ia[t]].p + nd[ib[t]].p, pf);
   f[1 + DIR] = f[1 + DIR] + pf;
 }
 
 // Pressure-only flux at a staggered wall (convective fluxes vanish there).
-template <typename F, int DIR>
-__device__ __forceinline__ void wall_flux(const PV<F>& a, const PV<F>& b, const PV<F>& c,
-                                          const PV<F>& d, F f[5]) {
+template <typename F, int DIR, int L>
+__device__ __forceinline__ void wall_flux(const PV<F>* nd, F f[5]) {
   f[0] = f[1] = f[2] = f[3] = f[4] = F(0);
-  f[1 + DIR] = F(CA1) * (b.p + c.p) + F(CA2) * ((b.p + d.p) + (a.p + c.p));
+  F pf = F(0);
+#pragma unroll
+  for (int l = 1; l <= L; ++l) {
+    F ps = F(0);
+#pragma unroll
+    for (int m = 0; m < l; ++m) ps = m == 0 ? (nd[L - 1 - m].p + nd[L - 1 - m + l].p)
+                                            : ps + (nd[L - 1 - m].p + nd[L - 1 - m + l].p);
+    pf = l == 1 ? F(coef_a(L, 1)) * ps : pf + F(coef_a(L, l)) * ps;
+  }
+  f[1 + DIR] = pf;
 }
 
-template <int DIR>
-__device__ __forceinline__ void wall_flux_f64(const PV<double>& a, const PV<double>& b,
-                                              const PV<double>& c, const PV<double>& d,
-                                              double f[5]) {
+template <int DIR, int L>
+__device__ __forceinline__ void wall_flux_f64(const PV<double>* nd, double f[5]) {
 #pragma clang fp contract(off)
   f[0] = f[1] = f[2] = f[3] = f[4] = 0.0;
-  f[1 + DIR] = fma(CA2, a.p + c.p, fma(CA2, b.p + d.p, CA1 * (b.p + c.p)));
+  double pf = coef_a(L, 1) * (nd[L - 1].p + nd[L].p);
+#pragma unroll
+  for (int l = 1; l <= L; ++l)
+#pragma unroll
+    for (int m = 0; m < l; ++m)
+      if (l > 1 || m > 0) pf = fma(coef_a(L, l), nd[L - 1 - m].p + nd[L - 1 - m + l].p, pf);
+  f[1 + DIR] = pf;
 }
 
-// Dispatch: FP64 uses the fixed-order forms above.
-template <typename F, int DIR>
-__device__ __forceinline__ void cflux(const PV<F>& a, const PV<F>& b, const PV<F>& c,
-                                      const PV<F>& d, F f[5]) {
-  if constexpr (sizeof(F) == 8) central_flux_f64<DIR>(a, b, c, d, f);
-  else central_flux<F, DIR>(a, b, c, d, f);
+// Dispatch: FP64 uses the fixed-order forms above.  nd points at node i-L+1.
+template <typename F, int DIR, int L>
+__device__ __forceinline__ void cflux(const PV<F>* nd, F f[5]) {
+  if constexpr (sizeof(F) == 8) central_flux_f64<DIR, L>(nd, f);
+  else central_flux<F, DIR, L>(nd, f);
 }
-template <typename F, int DIR>
-__device__ __forceinline__ void wflux(const PV<F>& a, const PV<F>& b, const PV<F>& c,
-                                      const PV<F>& d, F f[5]) {
-  if constexpr (sizeof(F) == 8) wall_flux_f64<DIR>(a, b, c, d, f);
-  else wall_flux<F, DIR>(a, b, c, d, f);
+template <typename F, int DIR, int L>
+__device__ __forceinline__ void wflux(const PV<F>* nd, F f[5]) {
+  if constexpr (sizeof(F) == 8) wall_flux_f64<DIR, L>(nd, f);
+  else wall_flux<F, DIR, L>(nd, f);
 }
 
 // WENO5-JS reconstruction at i+1/2 from v_{i-2..i+2}.  The argument `eps4`
@@ -334,20 +412,80 @@ __device__ __forceinline__ F weno5(F vm2, F vm1, F v0, F vp1, F vp2, F eps4) {
   return num * wrcp<F>(F(6) * den);
 }
 
-// Lax-Friedrichs split characteristic WENO5 flux at interface i+1/2 along
-// DIR from the conserved states of nodes i-2..i+3 (Sec. 2.1).  Eigenvectors
-// at the Roe average of nodes i, i+1; splitting constant per field from the
-// largest |eigenvalue| over the six nodes.
-template <typename F, int DIR, typename Loader>
+// WENO3-JS (two candidate stencils, linear weights 1/3, 2/3) at i+1/2 from
+// v_{i-1..i+1}, same input scaling as weno5; numerator and denominator are
+// multiplied by 3 t0 t1 (a = (t1, 2 t0)) and the candidates by 2.
+template <typename F>
+__device__ __forceinline__ F weno3(F vm1, F v0, F vp1, F eps4) {
+  const F q0 = F(3) * v0 - vm1;
+  const F q1 = v0 + vp1;
+  const F d0 = v0 - vm1, d1 = vp1 - v0;
+  const F s0 = eps4 + d0 * d0, s1 = eps4 + d1 * d1;
+  const F t0 = s0 * s0, t1 = s1 * s1;
+  const F num = t1 * q0 + F(2) * t0 * q1;
+  const F den = t1 + F(2) * t0;
+  return num * wrcp<F>(F(2) * den);
+}
+
+// WENO7-JS (four candidate stencils, linear weights (1, 12, 18, 4)/35) at
+// i+1/2 from v[0..6] = v_{i-3..i+3}, same input scaling as weno5.  The
+// smoothness indicators are Balsara and Shu's quadratic forms divided by
+// 240 (which makes them the integrals of the squared derivatives of the
+// candidate polynomials over the cell, as for the other orders); the
+// candidates are multiplied by 12 and the weights formed with one
+// reciprocal each (a product form would overflow in FP32).
+template <typename F>
+__device__ __forceinline__ F weno7(const F* v, F eps4) {
+  const F a = v[0], b = v[1], d = v[2], e = v[3], f = v[4], g = v[5], h = v[6];
+  const F q0 = F(-3) * a + F(13) * b - F(23) * d + F(25) * e;
+  const F q1 = b - F(5) * d + F(13) * e + F(3) * f;
+  const F q2 = -d + F(7) * e + F(7) * f - g;
+  const F q3 = F(3) * e + F(13) * f - F(5) * g + h;
+  const F c240 = F(1.0 / 240.0);
+  const F b0 = c240 * (a * (F(547) * a - F(3882) * b + F(4642) * d - F(1854) * e) +
+                       b * (F(7043) * b - F(17246) * d + F(7042) * e) +
+                       d * (F(11003) * d - F(9402) * e) + F(2107) * e * e);
+  const F b1 = c240 * (b * (F(267) * b - F(1642) * d + F(1602) * e - F(494) * f) +
+                       d * (F(2843) * d - F(5966) * e + F(1922) * f) +
+                       e * (F(3443) * e - F(2522) * f) + F(547) * f * f);
+  const F b2 = c240 * (d * (F(547) * d - F(2522) * e + F(1922) * f - F(494) * g) +
+                       e * (F(3443) * e - F(5966) * f + F(1602) * g) +
+                       f * (F(2843) * f - F(1642) * g) + F(267) * g * g);
+  const F b3 = c240 * (e * (F(2107) * e - F(9402) * f + F(7042) * g - F(1854) * h) +
+                       f * (F(11003) * f - F(17246) * g + F(4642) * h) +
+                       g * (F(7043) * g - F(3882) * h) + F(547) * h * h);
+  const F s0 = eps4 + b0, s1 = eps4 + b1, s2 = eps4 + b2, s3 = eps4 + b3;
+  const F w0 = wrcp<F>(s0 * s0), w1 = F(12) * wrcp<F>(s1 * s1);
+  const F w2 = F(18) * wrcp<F>(s2 * s2), w3 = F(4) * wrcp<F>(s3 * s3);
+  const F num = w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3;
+  const F den = w0 + w1 + w2 + w3;
+  return num * wrcp<F>(F(12) * den);
+}
+
+// Reconstruction of order 2R-1 at i+1/2 from v[0..2R-2] = v_{i-R+1..i+R-1}.
+template <typename F, int R>
+__device__ __forceinline__ F wrec(const F* v, F eps4) {
+  if constexpr (R == 2) return weno3<F>(v[0], v[1], v[2], eps4);
+  else if constexpr (R == 3) return weno5<F>(v[0], v[1], v[2], v[3], v[4], eps4);
+  else return weno7<F>(v, eps4);
+}
+
+// Lax-Friedrichs split characteristic WENO flux of order 2R-1 at interface
+// i+1/2 along DIR from the conserved states of the 2R nodes i-R+1..i+R
+// (stencil index s = 0..2R-1, Sec. 2.1).  Eigenvectors at the Roe average
+// of nodes i, i+1; splitting constant per field from the largest
+// |eigenvalue| over the stencil.
+template <typename F, int DIR, int R, typename Loader>
 __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5]) {
+  constexpr int NS = 2 * R;
   constexpr int PN = 1 + DIR, P1 = 1 + (DIR + 1) % 3, P2 = 1 + (DIR + 2) % 3;
   const F gm1 = (F)D.gm1, gam = (F)D.gamma;
-  // Roe average of nodes i (s=2) and i+1 (s=3)
+  // Roe average of nodes i (s=R-1) and i+1 (s=R)
   F ur, vr, wr, Hr;
   {
     double qa[5], qb[5];
-    get(2, qa);
-    get(3, qb);
+    get(R - 1, qa);
+    get(R, qb);
     const F ra = (F)qa[0], rb = (F)qb[0];
     const F ira = wrcp<F>(ra), irb = wrcp<F>(rb);
     const F una = (F)qa[PN] * ira, t1a = (F)qa[P1] * ira, t2a = (F)qa[P2] * ira;
@@ -384,10 +522,10 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
     out[4] = Xh - Yh;
   };
   // stencil nodes: physical flux, eigenvalue bounds, characteristic projections
-  F v[6][5], g[6][5];
+  F v[NS][5], g[NS][5];
   F am0 = F(0), am1 = F(0), am4 = F(0);
 #pragma unroll
-  for (int s = 0; s < 6; ++s) {
+  for (int s = 0; s < NS; ++s) {
     double qd[5];
     get(s, qd);
     const F r = (F)qd[0];
@@ -411,12 +549,13 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
   for (int k = 0; k < 5; ++k) {
     const F a = alpha[k];
     // twice the Lax-Friedrichs split characteristic fluxes g+- = (g +- a v)/2
-#define GP(s) (g[s][k] + a * v[s][k])
-#define GM(s) (g[s][k] - a * v[s][k])
-    gh[k] = F(0.5) * (weno5<F>(GP(0), GP(1), GP(2), GP(3), GP(4), eps4) +
-                      weno5<F>(GM(5), GM(4), GM(3), GM(2), GM(1), eps4));
-#undef GP
-#undef GM
+    F vp[NS - 1], vm[NS - 1];
+#pragma unroll
+    for (int t = 0; t < NS - 1; ++t) {
+      vp[t] = g[t][k] + a * v[t][k];                    // i-R+1..i+R-1
+      vm[t] = g[NS - 1 - t][k] - a * v[NS - 1 - t][k];  // i+R..i-R+2 (mirrored)
+    }
+    gh[k] = F(0.5) * (wrec<F, R>(vp, eps4) + wrec<F, R>(vm, eps4));
   }
   // right eigenvectors applied to the reconstructed characteristic flux
   const F f0 = gh[0] + gh[1] + gh[4];
@@ -475,6 +614,7 @@ __device__ __forceinline__ void char_ghosts(const Desc& D, const double qb[5], c
   dr[P1] = v * (a0 + a1 + a4) + a2;
   dr[P2] = ww * (a0 + a1 + a4) + a3;
   dr[4] = (H - u * c) * a0 + 0.5 * q2 * a1 + v * a2 + ww * a3 + (H + u * c) * a4;
+#pragma unroll
   for (int s = 0; s < kHalo; ++s)
     for (int m = 0; m < 5; ++m) gq[s][m] = qb[m] + (double)(s + 1) * dr[m];
 }
@@ -494,6 +634,7 @@ __device__ __forceinline__ void ghost_x_body(const Desc& D, const double* __rest
     const double* pr = D.bcp[side];
     double q[5];
     from_prim(D, pr[j], pr[D.ny + j], pr[2 * D.ny + j], pr[3 * D.ny + j], pr[4 * D.ny + j], q);
+#pragma unroll
     for (int s = 0; s < kHalo; ++s)
       for (int m = 0; m < 5; ++m) gq[s][m] = q[m];
   } else {  // characteristic outflow
@@ -507,9 +648,11 @@ __device__ __forceinline__ void ghost_x_body(const Desc& D, const double* __rest
     }
     char_ghosts<0>(D, qb, qi, side == 1, gq);
   }
+  // only the D.hw layers the stencils reach are written
+#pragma unroll
   for (int s = 0; s < kHalo; ++s)
-    for (int m = 0; m < 5; ++m)
-      g[m * mst + ((size_t)s * D.nz + k) * D.ny + j] = gq[s][m];
+    if (s < D.hw)
+      for (int m = 0; m < 5; ++m) g[m * mst + ((size_t)s * D.nz + k) * D.ny + j] = gq[s][m];
 }
 
 __device__ __forceinline__ void ghost_y_body(const Desc& D, const double* __restrict__ w, long long t) {
@@ -519,6 +662,7 @@ __device__ __forceinline__ void ghost_y_body(const Desc& D, const double* __rest
   const long long r = t - side * per_side;
   const int k = (int)(r / D.nxg);
   const int i = (int)(r - (long long)k * D.nxg) - kHalo;
+  if (i < -D.hw || i >= D.nx + D.hw) return;  // x range of the layers in use
   const int kind = D.bc[2 + side];
   double* g = D.gy[side];
   const size_t mst = (size_t)kHalo * D.nz * D.nxg;
@@ -529,7 +673,9 @@ __device__ __forceinline__ void ghost_y_body(const Desc& D, const double* __rest
     load_node(D, w, i, side == 0 ? 1 : D.ny - 2, k, qi);
     char_ghosts<1>(D, qb, qi, side == 1, gq);
   }
+#pragma unroll
   for (int s = 1; s <= kHalo; ++s) {
+    if (s > D.hw) break;  // only the layers the stencils reach
     double q[5];
     if (is_wall(kind)) {
       double qm[5];
@@ -633,7 +779,7 @@ __global__ void k_df_plane(Desc D, int initial) {
   from_prim(D, pm / (D.R * T), um + du, vm + dv, wm + dw, pm, q);
   double* g = D.gx[0];
   const size_t mst = (size_t)kHalo * nz * ny;
-  for (int s = 0; s < kHalo; ++s)
+  for (int s = 0; s < D.hw; ++s)
     for (int m = 0; m < 5; ++m) g[m * mst + ((size_t)s * nz + k) * ny + j] = q[m];
 }
 
@@ -842,24 +988,31 @@ __device__ __forceinline__ unsigned flag_mask16(uint4 v) {
 
 // Interface-flag masks (bit r = node n0+r) of 16 consecutive nodes that lie
 // in one x-row starting at i0 (row (j, k)); the node flags are read as
-// 128-bit words.
+// 128-bit words.  Interface i+1/2 is flagged when a node of the central
+// stencil i-L+1..i+L is.
+template <int L>
 __device__ __forceinline__ void iface_masks_row(const Desc& D, int n0, int i0, int j, int k,
                                                 unsigned& mx, unsigned& my, unsigned& mz) {
   const uint4* nf = reinterpret_cast<const uint4*>(D.nflag);
   const unsigned mc = flag_mask16(nf[n0 >> 4]);
   const int rowstep = D.nx, plane = D.nx * D.ny;
-  // x: neighbours i0-1, i0+16, i0+17 beyond the word
-  const unsigned e = (unsigned)node_flag(D, i0 - 1, j, k) | (mc << 1) |
-                     ((unsigned)node_flag(D, i0 + 16, j, k) << 17) |
-                     ((unsigned)node_flag(D, i0 + 17, j, k) << 18);
-  mx = (e | (e >> 1) | (e >> 2) | (e >> 3)) & 0xFFFFu;
-  if (!D.per_x && i0 + 16 == D.nx) mx &= 0x7FFFu;  // last x interface is a boundary
-  // y: rows j-1, j+1, j+2 (non-periodic rows beyond the walls are unflagged)
-  unsigned oy = mc;
-  const int jj[3] = {j - 1, j + 1, j + 2};
+  // x: bit t of e is node i0-L+1+t; neighbours beyond the word singly
+  unsigned e = mc << (L - 1);
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    int t = jj[q];
+  for (int t = 0; t < L - 1; ++t) e |= (unsigned)node_flag(D, i0 - L + 1 + t, j, k) << t;
+#pragma unroll
+  for (int t = 0; t < L; ++t) e |= (unsigned)node_flag(D, i0 + 16 + t, j, k) << (L + 15 + t);
+  unsigned ox = e;
+#pragma unroll
+  for (int t = 1; t < 2 * L; ++t) ox |= e >> t;
+  mx = ox & 0xFFFFu;
+  if (!D.per_x && i0 + 16 == D.nx) mx &= 0x7FFFu;  // last x interface is a boundary
+  // y: rows j-L+1..j+L (non-periodic rows beyond the walls are unflagged)
+  unsigned oy = mc;
+#pragma unroll
+  for (int o = 1 - L; o <= L; ++o) {
+    if (o == 0) continue;
+    int t = j + o;
     if (t < 0 || t >= D.ny) {
       if (!D.per_y) continue;
       t = wrapi(t, D.ny);
@@ -867,12 +1020,12 @@ __device__ __forceinline__ void iface_masks_row(const Desc& D, int n0, int i0, i
     oy |= flag_mask16(nf[(n0 + (t - j) * rowstep) >> 4]);
   }
   my = (!D.per_y && j == D.ny - 1) ? 0u : oy;
-  // z: planes k-1, k+1, k+2 (periodic)
+  // z: planes k-L+1..k+L (periodic)
   unsigned oz = mc;
-  const int kk[3] = {k - 1, k + 1, k + 2};
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const int t = wrapi(kk[q], D.nz);
+  for (int o = 1 - L; o <= L; ++o) {
+    if (o == 0) continue;
+    const int t = wrapi(k + o, D.nz);
     oz |= flag_mask16(nf[(n0 + (t - k) * plane) >> 4]);
   }
   mz = oz;
@@ -886,6 +1039,7 @@ __device__ __forceinline__ void iface_masks_row(const Desc& D, int n0, int i0, i
 // reading the list touches consecutive nodes in consecutive lanes.
 constexpr int kIflagsPer = 16;
 
+template <int L>
 __device__ __forceinline__ void iflags_body(const Desc& D, long long blk) {
   __shared__ unsigned sm[4];
   __shared__ unsigned base[3];
@@ -899,7 +1053,7 @@ __device__ __forceinline__ void iflags_body(const Desc& D, long long blk) {
     const int rr = n0 / D.nx;
     int j = rr % D.ny, k = rr / D.ny;
     if (D.sensor_mode == 1 && D.nx % kIflagsPer == 0 && n0 + kIflagsPer <= N) {
-      iface_masks_row(D, n0, i0, j, k, mx, my, mz);
+      iface_masks_row<L>(D, n0, i0, j, k, mx, my, mz);
     } else {
       // general shape: walk the nodes with incremental indices.  An
       // interface is shock-capturing when a node of its central stencil is
@@ -911,16 +1065,14 @@ __device__ __forceinline__ void iflags_body(const Desc& D, long long blk) {
         if (D.sensor_mode == 2) {
           f = (uint8_t)((bx ? 0 : 1) | (by ? 0 : 2) | 4);
         } else {
-          f = 0;
-          const uint8_t c0 = node_flag(D, i, j, k);
-          if (!bx && (c0 | node_flag(D, i - 1, j, k) | node_flag(D, i + 1, j, k) |
-                      node_flag(D, i + 2, j, k)))
-            f |= 1;
-          if (!by && (c0 | node_flag(D, i, j - 1, k) | node_flag(D, i, j + 1, k) |
-                      node_flag(D, i, j + 2, k)))
-            f |= 2;
-          if (c0 | node_flag(D, i, j, k - 1) | node_flag(D, i, j, k + 1) | node_flag(D, i, j, k + 2))
-            f |= 4;
+          uint8_t ox = 0, oy = 0, oz = 0;
+#pragma unroll
+          for (int o = 1 - L; o <= L; ++o) {
+            ox |= node_flag(D, i + o, j, k);
+            oy |= node_flag(D, i, j + o, k);
+            oz |= node_flag(D, i, j, k + o);
+          }
+          f = (uint8_t)((!bx && ox ? 1 : 0) | (!by && oy ? 2 : 0) | (oz ? 4 : 0));
         }
         mx |= (unsigned)(f & 1) << r;
         my |= (unsigned)((f >> 1) & 1) << r;
@@ -974,28 +1126,30 @@ __device__ __forceinline__ void iflags_body(const Desc& D, long long blk) {
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(256) k_iflags(Desc D) { iflags_body(D, blockIdx.x); }
+template <int L>
+__global__ void __launch_bounds__(256) k_iflags(Desc D) { iflags_body<L>(D, blockIdx.x); }
 
 // ------------------------------------------------------------------ WENO on lists
-template <typename F, int DIR>
+template <typename F, int DIR, int R>
 __device__ __forceinline__ void weno_entry(const Desc& D, const double* __restrict__ w, int n, unsigned e) {
+  constexpr int NS = 2 * R;
   int i, j;
   const int k = qdiv(qdiv(n, D.nx, D.rnx, i), D.ny, D.rny, j);
-  // all 30 loads are issued before any arithmetic (latency-bound kernel)
-  double qn[6][5];
+  // all 10 R loads are issued before any arithmetic (latency-bound kernel)
+  double qn[NS][5];
   const int c = DIR == 0 ? i : (DIR == 1 ? j : k);
   const int nd = DIR == 0 ? D.nx : (DIR == 1 ? D.ny : D.nz);
-  if (c >= 2 && c + 3 < nd) {  // stencil inside the interior: direct addressing
+  if (c >= R - 1 && c + R < nd) {  // stencil inside the interior: direct addressing
     const long long st = DIR == 0 ? 1LL : (DIR == 1 ? (long long)D.nx : (long long)D.nx * D.ny);
-    const double* __restrict__ b = w + (n - 2 * st);
+    const double* __restrict__ b = w + (n - (R - 1) * st);
 #pragma unroll
-    for (int s = 0; s < 6; ++s)
+    for (int s = 0; s < NS; ++s)
 #pragma unroll
       for (int m = 0; m < 5; ++m) qn[s][m] = b[m * D.N + s * st];
   } else {
 #pragma unroll
-    for (int s = 0; s < 6; ++s) {
-      const int o = s - 2;
+    for (int s = 0; s < NS; ++s) {
+      const int o = s - (R - 1);
       load_node(D, w, i + (DIR == 0 ? o : 0), j + (DIR == 1 ? o : 0), k + (DIR == 2 ? o : 0),
                 qn[s]);
     }
@@ -1005,13 +1159,13 @@ __device__ __forceinline__ void weno_entry(const Desc& D, const double* __restri
     for (int m = 0; m < 5; ++m) q[m] = qn[s][m];
   };
   F f[5];
-  weno_flux<F, DIR>(D, get, f);
+  weno_flux<F, DIR, R>(D, get, f);
   double* out = D.Fw[DIR];
 #pragma unroll
   for (int m = 0; m < 5; ++m) out[(size_t)m * D.N + e] = (double)f[m];
 }
 
-template <typename F>
+template <typename F, int R>
 __global__ void __launch_bounds__(256) k_weno(Desc D, const double* __restrict__ w) {
   const int dir = blockIdx.y;
   const unsigned cnt = D.count[dir];
@@ -1024,9 +1178,9 @@ __global__ void __launch_bounds__(256) k_weno(Desc D, const double* __restrict__
   const unsigned e1 = min(cnt, (lb + 1) * per);
   for (unsigned e = lb * per + threadIdx.x; e < e1; e += 256u) {
     const int n = D.list[dir][e];
-    if (dir == 0) weno_entry<F, 0>(D, w, n, e);
-    else if (dir == 1) weno_entry<F, 1>(D, w, n, e);
-    else weno_entry<F, 2>(D, w, n, e);
+    if (dir == 0) weno_entry<F, 0, R>(D, w, n, e);
+    else if (dir == 1) weno_entry<F, 1, R>(D, w, n, e);
+    else weno_entry<F, 2, R>(D, w, n, e);
   }
 }
 
@@ -1034,44 +1188,72 @@ __global__ void __launch_bounds__(256) k_weno(Desc D, const double* __restrict__
 // Quantity slots in the LDS plane.
 enum { QR = 0, QU, QV, QW, QP, QH, QT, QM, NQ };
 
-template <typename F, int TX, int TY>
+// Shared memory of one block of the fused kernel for central half-width L.
+template <typename F, int TX, int TY, int L>
 struct RhsSmem {
-  F q[NQ][TY + 4][TX + 4];             // current plane with a 2-node halo
-  F zr[4][3][TX * TY];                 // per-thread ring of (rho, p, H) of planes c-1..c+2
-  double pend[2][5][TX * TY];          // per-thread residuals awaiting their z-mixed terms
+  F q[NQ][TY + 2 * L][TX + 2 * L];    // current plane with an L-node halo
+  F zr[2 * L][3][TX * TY];            // per-thread ring of (rho, p, H) of planes c-L+1..c+L
+  double pend[L][5][TX * TY];         // per-thread residuals awaiting their z-mixed terms
   double red[TX * TY / 64];
 };
 
-template <typename F>
-__device__ __forceinline__ F d1c(F m2, F m1, F p1, F p2, F inv) {
-  return inv * (F(CA1) * (p1 - m1) + F(CA2) * (p2 - m2));
+// First and second central derivatives of order 2L from an accessor
+// at(o) = f_{i+o}: inv * sum_l a_l (f_{+l} - f_{-l}) and
+// inv2 * (b_0 f_0 + sum_l b_l (f_{+l} + f_{-l})), each written as one
+// expression summed left to right (l ascending).
+template <typename F, int L, typename At, int... I>
+__device__ __forceinline__ F d1_sum(At& at, std::integer_sequence<int, I...>) {
+  return (... + (F(coef_a(L, I + 1)) * (at(I + 1) - at(-(I + 1)))));
 }
-template <typename F>
-__device__ __forceinline__ F d2c(F m2, F m1, F c, F p1, F p2, F inv2) {
-  return inv2 * (F(CB0) * c + F(CB1) * (p1 + m1) + F(CB2) * (p2 + m2));
+template <typename F, int L, typename At, int... I>
+__device__ __forceinline__ F d2_sum(At& at, F ctr, std::integer_sequence<int, I...>) {
+  return ((F(coef_b(L, 0)) * ctr) + ... + (F(coef_b(L, I + 1)) * (at(I + 1) + at(-(I + 1)))));
+}
+template <typename F, int L, typename At>
+__device__ __forceinline__ F d1g(At&& at, F inv) {
+  return inv * d1_sum<F, L>(at, std::make_integer_sequence<int, L>{});
+}
+template <typename F, int L, typename At>
+__device__ __forceinline__ F d2g(At&& at, F ctr, F inv2) {
+  return inv2 * d2_sum<F, L>(at, ctr, std::make_integer_sequence<int, L>{});
 }
 
-template <typename F, int TX, int TY>
-__device__ __forceinline__ void lds_prim(const RhsSmem<F, TX, TY>& S, int ly, int lx, PV<F>& s) {
+template <typename F, int TX, int TY, int L>
+__device__ __forceinline__ void lds_prim(const RhsSmem<F, TX, TY, L>& S, int ly, int lx, PV<F>& s) {
   s.r = S.q[QR][ly][lx]; s.u = S.q[QU][ly][lx]; s.v = S.q[QV][ly][lx]; s.w = S.q[QW][ly][lx];
   s.p = S.q[QP][ly][lx]; s.h = S.q[QH][ly][lx]; s.t = S.q[QT][ly][lx]; s.mu = S.q[QM][ly][lx];
 }
 
-template <typename F, int TX, int TY>
-__device__ __forceinline__ void lds_store(RhsSmem<F, TX, TY>& S, int ly, int lx, const PV<F>& s) {
+template <typename F, int TX, int TY, int L>
+__device__ __forceinline__ void lds_store(RhsSmem<F, TX, TY, L>& S, int ly, int lx, const PV<F>& s) {
   S.q[QR][ly][lx] = s.r; S.q[QU][ly][lx] = s.u; S.q[QV][ly][lx] = s.v; S.q[QW][ly][lx] = s.w;
   S.q[QP][ly][lx] = s.p; S.q[QH][ly][lx] = s.h; S.q[QT][ly][lx] = s.t; S.q[QM][ly][lx] = s.mu;
 }
 
-// One block of the fused kernel: tile (tile index lb) of the instance D.
-// VISC_ON false compiles the viscous terms out (inviscid problems: fewer
-// registers); true evaluates them when the instance is viscous.
-template <typename F, int TX, int TY, bool VISC_ON = true>
+// x mod P in [0, P) for x >= -P and a compile-time period P (a mask for
+// powers of two, which is exact for any x)
+template <int P>
+__device__ __forceinline__ int modp(int x) {
+  if constexpr ((P & (P - 1)) == 0) return x & (P - 1);
+  else return (int)((unsigned)(x + P) % (unsigned)P);
+}
+
+// One block of the fused kernel: tile (tile index lb) of the instance D,
+// central stencils of half-width L (order 2L).  Each thread owns one (i, j)
+// column of the tile and walks its z chunk; plane c is staged in LDS with an
+// L-node halo for the in-plane derivatives and fluxes, the column's own
+// planes c-L..c+L stay in a register window for the z terms, and the
+// z-mixed viscous terms of plane c-L are completed once the in-plane
+// derivatives of plane c are known.  VISC_ON false compiles the viscous
+// terms out (inviscid problems: fewer registers); true evaluates them when
+// the instance is viscous.
+template <typename F, int TX, int TY, bool VISC_ON, int L>
 __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict__ w, double* __restrict__ R,
-                         int lb, RhsSmem<F, TX, TY>& S) {
-  constexpr int LX = TX + 4, LY = TY + 4;
+                         int lb, RhsSmem<F, TX, TY, L>& S) {
+  constexpr int LX = TX + 2 * L, LY = TY + 2 * L;
   constexpr int NT = TX * TY;
   constexpr int NH = LX * LY - TX * TY;
+  constexpr int NW = 2 * L + 1;  // window planes c-L..c+L
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
   const int txi = lb % D.tiles_x;
@@ -1084,7 +1266,7 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
   const int i = i0 + tx, j = j0 + ty;
   const bool valid = i < D.nx && j < D.ny;
   const bool col_in = valid;
-  const bool tile_in = i0 >= 2 && i0 + TX + 2 <= D.nx && j0 >= 2 && j0 + TY + 2 <= D.ny;
+  const bool tile_in = i0 >= L && i0 + TX + L <= D.nx && j0 >= L && j0 + TY + L <= D.ny;
   const size_t N = (size_t)D.N;
   const int jc = j < D.ny ? j : D.ny - 1;
   const F idx = (F)D.idx, idz = (F)D.idz, idx2 = (F)D.idx2, idz2 = (F)D.idz2;
@@ -1096,34 +1278,37 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
   const bool wall_lo = D.wall_lo && j == 0;
   const bool wall_hi = D.wall_hi && j == D.ny - 1;
 
-  // own-column register window, slots 0..4 = planes c-2..c+2
-  PV<F> win[5];
+  // own-column register window, slots 0..2L = planes c-L..c+L
+  PV<F> win[NW];
   // (rho, p, H) of the column live in the LDS ring S.zr; the other fields
   // of the window stay in registers.
-  // deferred mixed-derivative windows (planes c-4..c)
-  F Sw[5], Tw[5], Qw[5];
+  // deferred mixed-derivative windows (planes c-2L..c)
+  F Sw[NW], Tw[NW], Qw[NW];
   double Ra0[5];
   F Fzm[5];
 #pragma unroll
-  for (int s = 0; s < 5; ++s) {
+  for (int s = 0; s < NW; ++s) {
     win[s] = PV<F>{F(0), F(0), F(0), F(0), F(0), F(0), F(0), F(0)};
     Sw[s] = Tw[s] = Qw[s] = F(0);
-    Ra0[s] = 0.0;
-    Fzm[s] = F(0);
+  }
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    Ra0[m] = 0.0;
+    Fzm[m] = F(0);
   }
   double fsum = 0.0;
 
   auto load_col = [&](int plane, PV<F>& s) {
     double q[5];
     if (col_in) {
-      const int b = nidx32(D, i, j, wrap1(plane, D.nz));  // plane in [-2, nz+3], nz >= 4
+      const int b = nidx32(D, i, j, wrap1(plane, D.nz));  // plane in [-L, nz+2L-1], nz >= 2L
 #pragma unroll
       for (int m = 0; m < 5; ++m) q[m] = w[(size_t)m * N + b];
     } else {
       load_node(D, w, i, j, plane, q);
     }
     to_prim<F>(D, q, s);
-    const int slot = plane & 3;
+    const int slot = modp<2 * L>(plane);
     S.zr[slot][0][tid] = s.r;
     S.zr[slot][1][tid] = s.p;
     S.zr[slot][2][tid] = s.h;
@@ -1131,38 +1316,38 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
   // window slot with (rho, p, H) restored from the ring
   auto full = [&](int ws, int plane) {
     PV<F> s = win[ws];
-    const int slot = plane & 3;
+    const int slot = modp<2 * L>(plane);
     s.r = S.zr[slot][0][tid];
     s.p = S.zr[slot][1][tid];
     s.h = S.zr[slot][2][tid];
     return s;
   };
 
-  load_col(kb - 2, win[3]);
-  load_col(kb - 1, win[4]);
-
-  for (int c = kb - 2; c <= ke + 1; ++c) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) win[s] = win[s + 1];
-    load_col(c + 2, win[4]);
+  for (int s = 0; s < L; ++s) load_col(kb - L + s, win[L + 1 + s]);
+
+  for (int c = kb - L; c <= ke + L - 1; ++c) {
+#pragma unroll
+    for (int s = 0; s < 2 * L; ++s) win[s] = win[s + 1];
+    load_col(c + L, win[2 * L]);
     // stage plane c into LDS: interior from the window, halo cooperatively
-    lds_store<F, TX, TY>(S, ty + 2, tx + 2, full(2, c));
+    lds_store<F, TX, TY, L>(S, ty + L, tx + L, full(L, c));
     {
       const int kk = wrap1(c, D.nz);
       for (int h = tid; h < NH; h += NT) {
         int lx, ly;
-        if (h < 2 * LX) {
+        if (h < L * LX) {
           ly = h / LX; lx = h - ly * LX;
-        } else if (h < 4 * LX) {
-          const int hh = h - 2 * LX;
-          ly = TY + 2 + hh / LX; lx = hh - (hh / LX) * LX;
+        } else if (h < 2 * L * LX) {
+          const int hh = h - L * LX;
+          ly = TY + L + hh / LX; lx = hh - (hh / LX) * LX;
         } else {
-          const int hh = h - 4 * LX;
-          ly = 2 + hh / 4;
-          const int cc = hh & 3;
-          lx = cc < 2 ? cc : TX + cc;
+          const int hh = h - 2 * L * LX;
+          ly = L + hh / (2 * L);
+          const int cc = modp<2 * L>(hh);
+          lx = cc < L ? cc : TX + cc;
         }
-        const int gi = i0 - 2 + lx, gj = j0 - 2 + ly;
+        const int gi = i0 - L + lx, gj = j0 - L + ly;
         double q[5];
         if (tile_in) {
           const int b = nidx32(D, gi, gj, kk);
@@ -1173,20 +1358,20 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
         }
         PV<F> s;
         to_prim<F>(D, q, s);
-        lds_store<F, TX, TY>(S, ly, lx, s);
+        lds_store<F, TX, TY, L>(S, ly, lx, s);
       }
     }
     __syncthreads();
-    const int ly = ty + 2, lx = tx + 2;
+    const int ly = ty + L, lx = tx + L;
     // in-plane first derivatives feeding the z-mixed terms
 #pragma unroll
-    for (int s = 0; s < 4; ++s) { Sw[s] = Sw[s + 1]; Tw[s] = Tw[s + 1]; Qw[s] = Qw[s + 1]; }
+    for (int s = 0; s < 2 * L; ++s) { Sw[s] = Sw[s + 1]; Tw[s] = Tw[s + 1]; Qw[s] = Qw[s + 1]; }
     if (visc) {
-      const F wx = d1c<F>(S.q[QW][ly][lx - 2], S.q[QW][ly][lx - 1], S.q[QW][ly][lx + 1], S.q[QW][ly][lx + 2], idx);
-      const F wy = d1c<F>(S.q[QW][ly - 2][lx], S.q[QW][ly - 1][lx], S.q[QW][ly + 1][lx], S.q[QW][ly + 2][lx], iy);
-      const F ux = d1c<F>(S.q[QU][ly][lx - 2], S.q[QU][ly][lx - 1], S.q[QU][ly][lx + 1], S.q[QU][ly][lx + 2], idx);
-      const F vy = d1c<F>(S.q[QV][ly - 2][lx], S.q[QV][ly - 1][lx], S.q[QV][ly + 1][lx], S.q[QV][ly + 2][lx], iy);
-      Sw[4] = wx; Tw[4] = wy; Qw[4] = ux + vy;
+      const F wx = d1g<F, L>([&](int o) { return S.q[QW][ly][lx + o]; }, idx);
+      const F wy = d1g<F, L>([&](int o) { return S.q[QW][ly + o][lx]; }, iy);
+      const F ux = d1g<F, L>([&](int o) { return S.q[QU][ly][lx + o]; }, idx);
+      const F vy = d1g<F, L>([&](int o) { return S.q[QV][ly + o][lx]; }, iy);
+      Sw[2 * L] = wx; Tw[2 * L] = wy; Qw[2 * L] = ux + vy;
     }
     // z-direction interface flux at c+1/2 (own column)
     F Fzp[5] = {F(0), F(0), F(0), F(0), F(0)};
@@ -1197,7 +1382,10 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
 #pragma unroll
         for (int m = 0; m < 5; ++m) Fzp[m] = (F)D.Fw[2][(size_t)m * N + ez];
       } else {
-        cflux<F, 2>(full(1, c - 1), full(2, c), full(3, c + 1), full(4, c + 2), Fzp);
+        PV<F> zn[2 * L];
+#pragma unroll
+        for (int s = 0; s < 2 * L; ++s) zn[s] = full(s + 1, c - L + 1 + s);
+        cflux<F, 2, L>(zn, Fzp);
       }
     }
     if (c >= kb && c < ke && valid) {
@@ -1207,14 +1395,11 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
       // x direction: interfaces i-1/2, i+1/2 from the LDS row
       {
         F fr[5], fl[5];
-        PV<F> a, b, cc, d, e;
-        lds_prim<F, TX, TY>(S, ly, lx - 2, a);
-        lds_prim<F, TX, TY>(S, ly, lx - 1, b);
-        lds_prim<F, TX, TY>(S, ly, lx, cc);
-        lds_prim<F, TX, TY>(S, ly, lx + 1, d);
-        lds_prim<F, TX, TY>(S, ly, lx + 2, e);
-        cflux<F, 0>(b, cc, d, e, fr);
-        cflux<F, 0>(a, b, cc, d, fl);
+        PV<F> nd[2 * L + 1];
+#pragma unroll
+        for (int s = 0; s <= 2 * L; ++s) lds_prim<F, TX, TY, L>(S, ly, lx - L + s, nd[s]);
+        cflux<F, 0, L>(nd + 1, fr);
+        cflux<F, 0, L>(nd, fl);
         if (hybrid) {
           const int er = D.slot[0][n0];
           if (er >= 0) {
@@ -1238,16 +1423,13 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
       // y direction (stretched): interfaces j-1/2, j+1/2 from the LDS column
       {
         F fr[5], fl[5];
-        PV<F> a, b, cc, d, e;
-        lds_prim<F, TX, TY>(S, ly - 2, lx, a);
-        lds_prim<F, TX, TY>(S, ly - 1, lx, b);
-        lds_prim<F, TX, TY>(S, ly, lx, cc);
-        lds_prim<F, TX, TY>(S, ly + 1, lx, d);
-        lds_prim<F, TX, TY>(S, ly + 2, lx, e);
-        if (wall_hi) wflux<F, 1>(b, cc, d, e, fr);
-        else cflux<F, 1>(b, cc, d, e, fr);
-        if (wall_lo) wflux<F, 1>(a, b, cc, d, fl);
-        else cflux<F, 1>(a, b, cc, d, fl);
+        PV<F> nd[2 * L + 1];
+#pragma unroll
+        for (int s = 0; s <= 2 * L; ++s) lds_prim<F, TX, TY, L>(S, ly - L + s, lx, nd[s]);
+        if (wall_hi) wflux<F, 1, L>(nd + 1, fr);
+        else cflux<F, 1, L>(nd + 1, fr);
+        if (wall_lo) wflux<F, 1, L>(nd, fl);
+        else cflux<F, 1, L>(nd, fl);
         if (hybrid) {
           const int er = D.slot[1][n0];
           if (er >= 0) {
@@ -1275,15 +1457,15 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
         Ra0[m] = acc[m] - (double)(Fzp[m] - Fzm[m]) * didz;
       }
       if (visc) {
-        const PV<F>& o = win[2];
+        const PV<F>& o = win[L];
 #define SQ(qq, dy, dx) S.q[qq][ly + (dy)][lx + (dx)]
-#define DX1(q) d1c<F>(SQ(q, 0, -2), SQ(q, 0, -1), SQ(q, 0, 1), SQ(q, 0, 2), idx)
-#define DY1(q) d1c<F>(SQ(q, -2, 0), SQ(q, -1, 0), SQ(q, 1, 0), SQ(q, 2, 0), iy)
-#define DX2(q, ctr) d2c<F>(SQ(q, 0, -2), SQ(q, 0, -1), ctr, SQ(q, 0, 1), SQ(q, 0, 2), idx2)
+#define DX1(q) d1g<F, L>([&](int t_) { return SQ(q, 0, t_); }, idx)
+#define DY1(q) d1g<F, L>([&](int t_) { return SQ(q, t_, 0); }, iy)
+#define DX2(q, ctr) d2g<F, L>([&](int t_) { return SQ(q, 0, t_); }, ctr, idx2)
 #define DY2(q, ctr, dy1) \
-  ((d2c<F>(SQ(q, -2, 0), SQ(q, -1, 0), ctr, SQ(q, 1, 0), SQ(q, 2, 0), ideta2) - yee * (dy1)) * iye2)
-#define DZ1(fld) d1c<F>(win[0].fld, win[1].fld, win[3].fld, win[4].fld, idz)
-#define DZ2(fld) d2c<F>(win[0].fld, win[1].fld, o.fld, win[3].fld, win[4].fld, idz2)
+  ((d2g<F, L>([&](int t_) { return SQ(q, t_, 0); }, ctr, ideta2) - yee * (dy1)) * iye2)
+#define DZ1(fld) d1g<F, L>([&](int t_) { return win[L + t_].fld; }, idz)
+#define DZ2(fld) d2g<F, L>([&](int t_) { return win[L + t_].fld; }, o.fld, idz2)
         // velocity gradient
         const F ux = DX1(QU), uy = DY1(QU), uz = DZ1(u);
         const F vx = DX1(QV), vy = DY1(QV), vz = DZ1(v);
@@ -1294,11 +1476,10 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
         const F third = F(1.0 / 3.0), twoth = F(2.0 / 3.0);
         // in-plane mixed derivatives d_y(d_x f), metric of the outer (y) operator
         auto dxrow = [&](int q, int dy) {
-          return d1c<F>(S.q[q][ly + dy][lx - 2], S.q[q][ly + dy][lx - 1], S.q[q][ly + dy][lx + 1],
-                        S.q[q][ly + dy][lx + 2], idx);
+          return d1g<F, L>([&](int t_) { return S.q[q][ly + dy][lx + t_]; }, idx);
         };
-        const F uxy = d1c<F>(dxrow(QU, -2), dxrow(QU, -1), dxrow(QU, 1), dxrow(QU, 2), iy);
-        const F vxy = d1c<F>(dxrow(QV, -2), dxrow(QV, -1), dxrow(QV, 1), dxrow(QV, 2), iy);
+        const F uxy = d1g<F, L>([&](int t_) { return dxrow(QU, t_); }, iy);
+        const F vxy = d1g<F, L>([&](int t_) { return dxrow(QV, t_); }, iy);
         const F uxx = DX2(QU, o.u);
         const F vyy = DY2(QV, o.v, vy);
         const F wzz = DZ2(w);
@@ -1331,19 +1512,19 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
 #pragma unroll
       for (int m = 0; m < 5; ++m) Fzm[m] = Fzp[m];
     }
-    // finish plane c-2: z-mixed viscous parts, store, forcing partial sum
-    // (plane c-2 and plane c share the slot c & 1 of the pending ring: the
-    // older one is read before the newer one is written)
-    const int pslot = c & 1;
-    if (c >= kb + 2 && valid) {
-      const int m2 = c - 2;
+    // finish plane c-L: z-mixed viscous parts, store, forcing partial sum
+    // (plane c-L and plane c share the slot c mod L of the pending ring:
+    // the older one is read before the newer one is written)
+    const int pslot = modp<L>(c);
+    if (c >= kb + L && valid) {
+      const int m2 = c - L;
       double Ra2[5];
 #pragma unroll
       for (int m = 0; m < 5; ++m) Ra2[m] = S.pend[pslot][m][tid];
       if (visc) {
-        const F dS = d1c<F>(Sw[0], Sw[1], Sw[3], Sw[4], idz);  // d_x d_z w
-        const F dT = d1c<F>(Tw[0], Tw[1], Tw[3], Tw[4], idz);  // d_y d_z w
-        const F dQ = d1c<F>(Qw[0], Qw[1], Qw[3], Qw[4], idz);  // d_z (d_x u + d_y v)
+        const F dS = d1g<F, L>([&](int t_) { return Sw[L + t_]; }, idz);  // d_x d_z w
+        const F dT = d1g<F, L>([&](int t_) { return Tw[L + t_]; }, idz);  // d_y d_z w
+        const F dQ = d1g<F, L>([&](int t_) { return Qw[L + t_]; }, idz);  // d_z (d_x u + d_y v)
         const PV<F>& o2 = win[0];
         const F t3 = F(1.0 / 3.0) * o2.mu;
         const F ax = t3 * dS, ay = t3 * dT, az = t3 * dQ;
@@ -1385,12 +1566,14 @@ __device__ __forceinline__ int xcd_swizzle(int b, int nb) {
   return (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
 }
 
-template <typename F, int TX, int TY, bool VISC_ON>
-__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2)))
+// Sixth-order stencils need more shared memory than two blocks of a CU can
+// hold, so that variant runs one block per CU with the full register file.
+template <typename F, int TX, int TY, bool VISC_ON, int L>
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(L == 3 ? 1 : 2)))
 k_rhs(Desc D, const double* __restrict__ w, double* __restrict__ R) {
-  __shared__ RhsSmem<F, TX, TY> S;
+  __shared__ RhsSmem<F, TX, TY, L> S;
   const int lb = xcd_swizzle(blockIdx.x, gridDim.x);
-  rhs_body<F, TX, TY, VISC_ON>(D, w, R, lb, S);
+  rhs_body<F, TX, TY, VISC_ON, L>(D, w, R, lb, S);
 }
 
 // ------------------------------------------------------------------ reductions
@@ -1574,7 +1757,7 @@ __device__ __forceinline__ void dt_final_body(const Desc& D, int nb, double* sm)
     vm = block_max<256>(vm, sm);
     dt = 1.0 / cm;
     if (D.viscous && vm > 0.0) {
-      const double dv = 2.5 / (16.0 / 3.0 * vm);
+      const double dv = 2.5 / (D.rho2 * vm);
       if (dv < dt) dt = dv;
     }
     dt *= D.cfl;
@@ -1766,7 +1949,10 @@ hipError_t launch_export_iface(const Desc& D, int dir, double* out, hipStream_t 
 }
 
 hipError_t launch_iflags(const Desc& D, hipStream_t st) {
-  k_iflags<<<nblk(D.N, 256 * kIflagsPer), 256, 0, st>>>(D);
+  const unsigned nb = nblk(D.N, 256 * kIflagsPer);
+  if (D.cl == 1) k_iflags<1><<<nb, 256, 0, st>>>(D);
+  else if (D.cl == 3) k_iflags<3><<<nb, 256, 0, st>>>(D);
+  else k_iflags<2><<<nb, 256, 0, st>>>(D);
   return hipGetLastError();
 }
 
@@ -1774,8 +1960,16 @@ hipError_t launch_weno(const Desc& D, int stage, hipStream_t st) {
   long long b = nblk(D.N, 256);
   if (b > 4096) b = 4096;
   dim3 grid((unsigned)b, 3);
-  if (D.precision == 1) k_weno<float><<<grid, 256, 0, st>>>(D, D.win[stage]);
-  else k_weno<double><<<grid, 256, 0, st>>>(D, D.win[stage]);
+  const double* w = D.win[stage];
+  if (D.precision == 1) {
+    if (D.wr == 2) k_weno<float, 2><<<grid, 256, 0, st>>>(D, w);
+    else if (D.wr == 4) k_weno<float, 4><<<grid, 256, 0, st>>>(D, w);
+    else k_weno<float, 3><<<grid, 256, 0, st>>>(D, w);
+  } else {
+    if (D.wr == 2) k_weno<double, 2><<<grid, 256, 0, st>>>(D, w);
+    else if (D.wr == 4) k_weno<double, 4><<<grid, 256, 0, st>>>(D, w);
+    else k_weno<double, 3><<<grid, 256, 0, st>>>(D, w);
+  }
   return hipGetLastError();
 }
 
@@ -1786,16 +1980,22 @@ bool rhs_tile_supported(int tx, int ty) {
          (tx == 128 && ty == 2) || (tx == 64 && ty == 8);
 }
 
+// The fourth-order kernel comes in every supported tile shape; the second-
+// and sixth-order ones in the 64x4 tile only (the scheme setter enforces it).
 template <typename F, bool VISC_ON>
 static hipError_t launch_rhs_v(const Desc& D, int stage, hipStream_t st) {
   const unsigned nb = (unsigned)rhs_blocks(D);
   const double* w = D.win[stage];
   double* R = D.rcur[stage];
-  if (D.tile_x == 64 && D.tile_y == 4) k_rhs<F, 64, 4, VISC_ON><<<nb, 256, 0, st>>>(D, w, R);
-  else if (D.tile_x == 32 && D.tile_y == 8) k_rhs<F, 32, 8, VISC_ON><<<nb, 256, 0, st>>>(D, w, R);
-  else if (D.tile_x == 64 && D.tile_y == 2) k_rhs<F, 64, 2, VISC_ON><<<nb, 128, 0, st>>>(D, w, R);
-  else if (D.tile_x == 128 && D.tile_y == 2) k_rhs<F, 128, 2, VISC_ON><<<nb, 256, 0, st>>>(D, w, R);
-  else if (D.tile_x == 64 && D.tile_y == 8) k_rhs<F, 64, 8, VISC_ON><<<nb, 512, 0, st>>>(D, w, R);
+  if (D.cl != 2) {
+    if (D.tile_x != 64 || D.tile_y != 4) return hipErrorInvalidValue;
+    if (D.cl == 1) k_rhs<F, 64, 4, VISC_ON, 1><<<nb, 256, 0, st>>>(D, w, R);
+    else k_rhs<F, 64, 4, VISC_ON, 3><<<nb, 256, 0, st>>>(D, w, R);
+  } else if (D.tile_x == 64 && D.tile_y == 4) k_rhs<F, 64, 4, VISC_ON, 2><<<nb, 256, 0, st>>>(D, w, R);
+  else if (D.tile_x == 32 && D.tile_y == 8) k_rhs<F, 32, 8, VISC_ON, 2><<<nb, 256, 0, st>>>(D, w, R);
+  else if (D.tile_x == 64 && D.tile_y == 2) k_rhs<F, 64, 2, VISC_ON, 2><<<nb, 128, 0, st>>>(D, w, R);
+  else if (D.tile_x == 128 && D.tile_y == 2) k_rhs<F, 128, 2, VISC_ON, 2><<<nb, 256, 0, st>>>(D, w, R);
+  else if (D.tile_x == 64 && D.tile_y == 8) k_rhs<F, 64, 8, VISC_ON, 2><<<nb, 512, 0, st>>>(D, w, R);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -1844,7 +2044,8 @@ hipError_t launch_diag(const Desc& D, hipStream_t st) {
 // Persistent kernels over all attached instances.  Every instance is
 // processed with exactly the per-item arithmetic of its single-instance
 // kernels (same tiles, same reduction slots), so its results are the same
-// alone and in any mix.
+// alone and in any mix.  Batched instances use the default scheme orders
+// (fourth-order central, fifth-order WENO); attaching others is refused.
 int batch_items(const Desc& D, int kind) {
   switch (kind) {
     case WK_PTS: return (int)nblk(D.N, 256);
@@ -1933,7 +2134,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 __global__ void __launch_bounds__(256) k_b_iflags(const Desc* __restrict__ descs,
                                                   const BatchTable* __restrict__ T) {
   BATCH_FOR(WK_IFL)
-  if (D.sensor_mode > 0) iflags_body(D, local);
+  if (D.sensor_mode > 0) iflags_body<2>(D, local);
   BATCH_END
 }
 
@@ -1948,9 +2149,9 @@ __global__ void __launch_bounds__(256) k_b_weno(const Desc* __restrict__ descs,
       const unsigned cnt = D.count[dir];
       for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x) {
         const int n = D.list[dir][e];
-        if (dir == 0) weno_entry<F, 0>(D, w, n, e);
-        else if (dir == 1) weno_entry<F, 1>(D, w, n, e);
-        else weno_entry<F, 2>(D, w, n, e);
+        if (dir == 0) weno_entry<F, 0, 3>(D, w, n, e);
+        else if (dir == 1) weno_entry<F, 1, 3>(D, w, n, e);
+        else weno_entry<F, 2, 3>(D, w, n, e);
       }
     }
   }
@@ -1959,9 +2160,9 @@ __global__ void __launch_bounds__(256) k_b_weno(const Desc* __restrict__ descs,
 template <typename F, int TX, int TY>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) k_b_rhs(const Desc* __restrict__ descs,
                                                   const BatchTable* __restrict__ T, int stage) {
-  __shared__ RhsSmem<F, TX, TY> S;
+  __shared__ RhsSmem<F, TX, TY, 2> S;
   BATCH_FOR(WK_RHS)
-  rhs_body<F, TX, TY>(D, D.win[stage], D.rcur[stage], local, S);
+  rhs_body<F, TX, TY, true, 2>(D, D.win[stage], D.rcur[stage], local, S);
   BATCH_END
 }
 

@@ -57,6 +57,10 @@ class Solver:
             ptr = arr.ctypes.data_as(dp) if arr.size else None
             B.check(self.lib, self.ctx,
                     self.lib.cdns_set_bc(self.ctx, face, int(kind), ptr, arr.size), "cdns_set_bc")
+        co = int(getattr(problem, "central_order", 4))
+        wo = int(getattr(problem, "weno_order", 5))
+        if (co, wo) != (4, 5):
+            self.set_scheme(co, wo)
         if tiling is not None:
             self.set_tiling(*tiling)
         if problem.w0 is not None:
@@ -79,6 +83,12 @@ class Solver:
     def set_tiling(self, tile_x: int, tile_y: int, kz: int) -> None:
         B.check(self.lib, self.ctx, self.lib.cdns_set_tiling(self.ctx, tile_x, tile_y, kz),
                 "cdns_set_tiling")
+
+    def set_scheme(self, central_order: int, weno_order: int) -> None:
+        """Central/viscous order (2, 4, 6) and WENO order (3, 5, 7)."""
+        B.check(self.lib, self.ctx,
+                self.lib.cdns_set_scheme(self.ctx, int(central_order), int(weno_order)),
+                "cdns_set_scheme")
 
     def rhs(self, w=None, out=None):
         t = self.torch
