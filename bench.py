@@ -66,10 +66,15 @@ WORKLOADS = {
 
 
 def kernel_source_hash():
+    """Hash of the kernel source without line comments and blank lines, so
+    that the stored counter figures stay tied to the code they measured."""
     h = hashlib.sha256()
     for f in ("cdns_kernels.hip",):
-        with open(os.path.join(ROOT, "paper_2004_02276_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2004_02276_amd", "csrc", f), encoding="utf-8") as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -8,13 +8,14 @@
 //   iflags   interface flags (OR over the central stencil), compaction
 //            into one node-ordered list of interfaces per direction and a
 //            per-node slot (list position or -1)
-//   weno     Lax-Friedrichs characteristic WENO5 flux on the listed
-//            interfaces, stored compacted at the list position
+//   weno     Lax-Friedrichs characteristic WENO flux (order 3, 5 or 7) on
+//            the listed interfaces, stored compacted at the list position
 //   rhs      fused central convective + pressure flux in x, y, z and
-//            Laplacian-form viscous/heat terms, 2.5-D tiling: an (x,y) tile
-//            with a 2-node halo is staged in LDS plane by plane while each
-//            thread keeps its own z column in registers; flagged interfaces
-//            take the compacted WENO flux through their slot
+//            Laplacian-form viscous/heat terms (order 2L = 2, 4 or 6),
+//            2.5-D tiling: an (x,y) tile with an L-node halo is staged in
+//            LDS plane by plane while each thread keeps its own z column in
+//            registers; flagged interfaces take the compacted WENO flux
+//            through their slot
 //   force    bulk force from the per-block partial sums (fixed order)
 //   rk       w' = w + dt (alpha R_prev + beta R), forcing applied here
 //
