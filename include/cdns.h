@@ -202,6 +202,16 @@ cdns_status cdns_set_tiling(cdns_ctx* ctx, int32_t tile_x, int32_t tile_y, int32
  * CDNS_EINVAL for other orders or too small a grid. */
 cdns_status cdns_set_scheme(cdns_ctx* ctx, int32_t central_order, int32_t weno_order);
 
+/* Copy a state w [5][nz][ny][nx] (the conserved vector of Sec. 2.2) into
+ * the context's state array (from_host != 0: w is host memory and the call
+ * returns after the copy; else w is device memory and the copy is
+ * stream-ordered), or the state out of it (to_host != 0: synchronous copy
+ * to host memory; else stream-ordered to device memory).  The state array
+ * is the caller's own allocation; these calls are conveniences for callers
+ * that do not address it directly. */
+cdns_status cdns_set_state(cdns_ctx* ctx, const double* w, int32_t from_host);
+cdns_status cdns_get_state(cdns_ctx* ctx, double* w, int32_t to_host);
+
 /* Full right-hand side R(w) of dw/dt = R(w) (Sec. 2.2) for the device
  * array w_dev [5][nz][ny][nx], written to r_dev (same layout), including
  * boundary conditions, sensor switching and bulk forcing. */
@@ -242,6 +252,17 @@ cdns_status cdns_stats_reset(cdns_ctx* ctx);
  * theta_dev may be NULL. */
 cdns_status cdns_export_sensor(cdns_ctx* ctx, double* theta_dev, uint8_t* nflags_dev,
                                uint8_t* iflags_dev);
+
+/* Test hooks for the sensor switch (eq. sensor): cdns_export_flags copies
+ * the node flags (theta > theta*) of the last cdns_rhs into the device
+ * array flags_dev [nz][ny][nx] (bytes 0/1); cdns_import_flags copies such a
+ * mask in and makes the next cdns_rhs use it instead of evaluating the
+ * sensor (hybrid mode only, CDNS_EINVAL otherwise; the interface flags and
+ * lists are rebuilt from it; theta is not recomputed; stepping calls
+ * always evaluate the sensor).  For comparing runs whose sensor decisions
+ * differ only where theta is within round-off of the threshold. */
+cdns_status cdns_export_flags(cdns_ctx* ctx, uint8_t* flags_dev);
+cdns_status cdns_import_flags(cdns_ctx* ctx, const uint8_t* flags_dev);
 
 /* Test hook: shock-capturing interface fluxes of direction dir (0..2) from
  * the last cdns_rhs, interface i+1/2 at node i, layout [5][nz][ny][nx]

@@ -22,7 +22,8 @@ NSTAT = 16  # running-statistics products (CDNS_NSTAT)
 
 EXPORTED = [
     "cdns_version", "cdns_workspace_bytes", "cdns_create", "cdns_set_bc", "cdns_set_tiling",
-    "cdns_set_scheme",
+    "cdns_set_scheme", "cdns_set_state", "cdns_get_state", "cdns_export_flags",
+    "cdns_import_flags",
     "cdns_rhs", "cdns_rk_step", "cdns_advance_n", "cdns_diagnostics", "cdns_export_sensor",
     "cdns_export_iface_flux", "cdns_time_phases", "cdns_stats_accumulate", "cdns_stats_export",
     "cdns_stats_reset",
@@ -90,6 +91,14 @@ def load() -> ctypes.CDLL:
     lib.cdns_set_tiling.restype = i32
     lib.cdns_set_scheme.argtypes = [vp, i32, i32]
     lib.cdns_set_scheme.restype = i32
+    lib.cdns_set_state.argtypes = [vp, vp, i32]
+    lib.cdns_set_state.restype = i32
+    lib.cdns_get_state.argtypes = [vp, vp, i32]
+    lib.cdns_get_state.restype = i32
+    lib.cdns_export_flags.argtypes = [vp, dp]
+    lib.cdns_export_flags.restype = i32
+    lib.cdns_import_flags.argtypes = [vp, dp]
+    lib.cdns_import_flags.restype = i32
     lib.cdns_rhs.argtypes = [vp, dp, dp]
     lib.cdns_rhs.restype = i32
     lib.cdns_rk_step.argtypes = [vp, f64, f64]

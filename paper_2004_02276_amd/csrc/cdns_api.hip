@@ -30,6 +30,7 @@ struct cdns_ctx {
   hipGraphExec_t gexec = nullptr;
   double g_cfl = -1.0, g_dt = -1.0;
   bool last_rhs_valid = false;
+  bool flags_imported = false;        // next cdns_rhs uses the imported node flags
   int batch_refs = 0;
   int64_t stat_samples = 0;           // samples in the statistics accumulator
 };
@@ -140,12 +141,17 @@ void default_tiling(Desc& D) {
 }
 
 // Enqueue the right-hand-side phases of one stage (ghosts .. forcing sum).
-hipError_t enqueue_rhs_phases(const Desc& D, int stage, bool export_theta, hipStream_t st) {
+// keep_flags: use the node flags already in place (imported) instead of
+// running the sensor.
+hipError_t enqueue_rhs_phases(const Desc& D, int stage, bool export_theta, hipStream_t st,
+                              bool keep_flags = false) {
   hipError_t e;
   // list counters: reset by the sensor kernel in hybrid mode, else here
-  if (D.sensor_mode == 2 && (e = cdns::launch_stage_begin(D, st)) != hipSuccess) return e;
+  if ((D.sensor_mode == 2 || keep_flags) && (e = cdns::launch_stage_begin(D, st)) != hipSuccess)
+    return e;
   if ((e = cdns::launch_ghosts(D, stage, st)) != hipSuccess) return e;
-  if (D.sensor_mode == 1 && (e = cdns::launch_sensor(D, stage, export_theta, st)) != hipSuccess)
+  if (D.sensor_mode == 1 && !keep_flags &&
+      (e = cdns::launch_sensor(D, stage, export_theta, st)) != hipSuccess)
     return e;
   if (D.sensor_mode > 0) {
     if ((e = cdns::launch_iflags(D, st)) != hipSuccess) return e;
@@ -438,10 +444,52 @@ cdns_status cdns_rhs(cdns_ctx* c, const double* w_dev, double* r_dev) {
   Desc D = c->D;
   D.win[3] = w_dev;
   D.rcur[3] = r_dev;
-  hipError_t e = enqueue_rhs_phases(D, 3, true, c->stream);
+  const bool keep = c->flags_imported && D.sensor_mode == 1;
+  c->flags_imported = false;
+  hipError_t e = enqueue_rhs_phases(D, 3, true, c->stream, keep);
   if (e == hipSuccess && D.forcing) e = cdns::launch_apply_force(D, 3, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "rhs launch");
   c->last_rhs_valid = true;
+  return CDNS_OK;
+}
+
+cdns_status cdns_set_state(cdns_ctx* c, const double* w, int32_t from_host) {
+  if (!c || !w) return c ? fail(c, CDNS_EINVAL, "null state") : CDNS_EINVAL;
+  const size_t bytes = (size_t)5 * (size_t)c->D.N * sizeof(double);
+  hipError_t e = hipMemcpyAsync((void*)c->D.win[0], w, bytes,
+                                from_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                                c->stream);
+  if (e == hipSuccess && from_host) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "set_state copy");
+  return CDNS_OK;
+}
+
+cdns_status cdns_get_state(cdns_ctx* c, double* w, int32_t to_host) {
+  if (!c || !w) return c ? fail(c, CDNS_EINVAL, "null output") : CDNS_EINVAL;
+  const size_t bytes = (size_t)5 * (size_t)c->D.N * sizeof(double);
+  hipError_t e = hipMemcpyAsync(w, c->D.win[0], bytes,
+                                to_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess && to_host) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "get_state copy");
+  return CDNS_OK;
+}
+
+cdns_status cdns_export_flags(cdns_ctx* c, uint8_t* flags_dev) {
+  if (!c || !flags_dev) return c ? fail(c, CDNS_EINVAL, "null output") : CDNS_EINVAL;
+  if (!c->last_rhs_valid) return fail(c, CDNS_EINVAL, "no right-hand side evaluated yet");
+  hipError_t e = hipMemcpyAsync(flags_dev, c->D.nflag, (size_t)c->D.N, hipMemcpyDeviceToDevice,
+                                c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "export_flags copy");
+  return CDNS_OK;
+}
+
+cdns_status cdns_import_flags(cdns_ctx* c, const uint8_t* flags_dev) {
+  if (!c || !flags_dev) return c ? fail(c, CDNS_EINVAL, "null flags") : CDNS_EINVAL;
+  if (c->D.sensor_mode != 1) return fail(c, CDNS_EINVAL, "node flags are used in hybrid mode only");
+  hipError_t e = hipMemcpyAsync(c->D.nflag, flags_dev, (size_t)c->D.N, hipMemcpyDeviceToDevice,
+                                c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "import_flags copy");
+  c->flags_imported = true;
   return CDNS_OK;
 }
 

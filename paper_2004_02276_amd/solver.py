@@ -68,16 +68,44 @@ class Solver:
 
     # ------------------------------------------------------------ state
     def set_state(self, w) -> None:
+        """Copy a state (host numpy array or device tensor) into the solver."""
         t = self.torch
         if isinstance(w, np.ndarray):
-            w = t.from_numpy(np.ascontiguousarray(w, dtype=np.float64))
-        with t.cuda.stream(self.stream):
-            self.state.copy_(w.to(self.device, dtype=t.float64))
+            h = np.ascontiguousarray(w, dtype=np.float64)
+            assert h.size == self.state.numel()
+            B.check(self.lib, self.ctx, self.lib.cdns_set_state(self.ctx, h.ctypes.data, 1),
+                    "cdns_set_state")
+            return
+        d = w.to(self.device, dtype=t.float64).contiguous()
+        assert d.numel() == self.state.numel()
+        B.check(self.lib, self.ctx, self.lib.cdns_set_state(self.ctx, d.data_ptr(), 0),
+                "cdns_set_state")
+        self.stream.synchronize()  # keeps d alive until the copy is done
 
     def get_state(self) -> np.ndarray:
-        with self.torch.cuda.stream(self.stream):
-            out = self.state.cpu()
-        return out.numpy()
+        out = np.empty(tuple(self.state.shape), dtype=np.float64)
+        B.check(self.lib, self.ctx, self.lib.cdns_get_state(self.ctx, out.ctypes.data, 1),
+                "cdns_get_state")
+        return out
+
+    def export_flags(self):
+        """Node flags of the last right-hand side (device uint8 tensor)."""
+        t = self.torch
+        out = t.empty((self.pr.nz, self.pr.ny, self.pr.nx), dtype=t.uint8, device=self.device)
+        B.check(self.lib, self.ctx, self.lib.cdns_export_flags(self.ctx, out.data_ptr()),
+                "cdns_export_flags")
+        return out
+
+    def import_flags(self, flags) -> None:
+        """Node flags to use in the next right-hand side instead of the sensor."""
+        t = self.torch
+        if isinstance(flags, np.ndarray):
+            flags = t.from_numpy(np.ascontiguousarray(flags, dtype=np.uint8))
+        d = flags.to(self.device, dtype=t.uint8).contiguous()
+        assert d.numel() == self.state.numel() // 5
+        B.check(self.lib, self.ctx, self.lib.cdns_import_flags(self.ctx, d.data_ptr()),
+                "cdns_import_flags")
+        self.stream.synchronize()
 
     # ------------------------------------------------------------ operations
     def set_tiling(self, tile_x: int, tile_y: int, kz: int) -> None:

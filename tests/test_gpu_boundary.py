@@ -1,0 +1,64 @@
+"""State copies and the sensor-mask hooks of the C ABI (cdns_set_state,
+cdns_get_state, cdns_export_flags, cdns_import_flags) on the GPU."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import problems as P
+from tests.test_gpu_parity import RHS_TOL, field_errors, say, torch_cuda  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+
+def test_state_copies_round_trip(torch_cuda):
+    from paper_2004_02276_amd import Solver
+    pr = P.small_channel(24, 20, 12)
+    say("[state copies]")
+    s = Solver(pr)
+    assert np.array_equal(s.get_state(), pr.w0)  # host upload at creation
+    w2 = pr.w0 * 1.01
+    s.set_state(w2)                               # from host
+    assert np.array_equal(s.get_state(), w2)
+    d = torch_cuda.from_numpy(pr.w0).to("cuda")
+    s.set_state(d)                                # device to device
+    assert np.array_equal(s.get_state(), pr.w0)
+    s.close()
+
+
+def test_flag_export_and_import(torch_cuda):
+    from paper_2004_02276_amd import Solver
+    from paper_2004_02276_amd import _binding as B
+    pr = P.decaying_turbulence(24, mach=1.5, re=800.0, seed=11)
+    say("[flag hooks]")
+    _, _, nf_o, _, _ = oracle.rhs(pr, want_flags=True)
+    s = Solver(pr)
+    r_ref = s.rhs(s.state).cpu().numpy()
+    nf = s.export_flags().cpu().numpy()
+    assert np.array_equal(nf, s.export_sensor()[1].cpu().numpy())
+    assert np.array_equal(nf, nf_o)
+    # the oracle's mask imported: the same right-hand side, bit for bit
+    s.import_flags(nf_o)
+    r_imp = s.rhs(s.state).cpu().numpy()
+    assert np.array_equal(r_imp, r_ref)
+    # every node flagged: the interface set of the WENO-everywhere mode
+    s.import_flags(np.ones_like(nf_o))
+    r_all = s.rhs(s.state).cpu().numpy()
+    assert np.array_equal(s.export_flags().cpu().numpy(), np.ones_like(nf_o))
+    # the import is used once: the next evaluation runs the sensor again
+    assert np.array_equal(s.rhs(s.state).cpu().numpy(), r_ref)
+    s.close()
+    pr2 = dataclasses.replace(pr, sensor_mode=P.SENSOR_WENO_ALL)
+    s2 = Solver(pr2)
+    r_mode2 = s2.rhs(s2.state).cpu().numpy()
+    s2.close()
+    assert np.array_equal(r_all, r_mode2)
+    errs = field_errors(r_all, oracle.rhs(pr2))
+    assert max(errs) <= RHS_TOL, errs
+    # node flags are a hybrid-mode input only
+    s3 = Solver(P.taylor_green(16))
+    with pytest.raises(B.CdnsError) as err:
+        s3.import_flags(np.zeros((16, 16, 16), np.uint8))
+    assert err.value.status == B.CDNS_EINVAL
+    s3.close()
