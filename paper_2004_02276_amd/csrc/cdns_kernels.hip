@@ -1299,6 +1299,24 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
   }
   double fsum = 0.0;
 
+  // list positions of the interfaces of plane c (x i+-1/2, y j+-1/2, z
+  // c+1/2; -1: central flux), loaded one plane ahead so that their latency
+  // overlaps a whole plane instead of delaying the flux loads behind them
+  int sxr, sxl, syr, syl, szr;
+  auto load_slots = [&](int cp, int& xr, int& xl, int& yr, int& yl, int& zr) {
+    xr = xl = yr = yl = zr = -1;
+    if (!hybrid || !valid) return;
+    if (cp >= kb - 1 && cp < ke) zr = D.slot[2][nidx32(D, i, j, wrap1(cp, D.nz))];
+    if (cp >= kb && cp < ke) {
+      const int n0 = nidx32(D, i, j, cp);
+      xr = D.slot[0][n0];
+      if (i > 0 || D.per_x) xl = D.slot[0][i > 0 ? n0 - 1 : n0 + (D.nx - 1)];
+      yr = D.slot[1][n0];
+      if (j > 0 || D.per_y) yl = D.slot[1][j > 0 ? n0 - D.nx : n0 + (D.ny - 1) * D.nx];
+    }
+  };
+  load_slots(kb - L, sxr, sxl, syr, syl, szr);
+
   auto load_col = [&](int plane, PV<F>& s) {
     double q[5];
     if (col_in) {
@@ -1330,6 +1348,8 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
   for (int c = kb - L; c <= ke + L - 1; ++c) {
 #pragma unroll
     for (int s = 0; s < 2 * L; ++s) win[s] = win[s + 1];
+    int nxr, nxl, nyr, nyl, nzr;
+    load_slots(c + 1, nxr, nxl, nyr, nyl, nzr);
     load_col(c + L, win[2 * L]);
     // stage plane c into LDS: interior from the window, halo cooperatively
     lds_store<F, TX, TY, L>(S, ty + L, tx + L, full(L, c));
@@ -1377,8 +1397,7 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
     // z-direction interface flux at c+1/2 (own column)
     F Fzp[5] = {F(0), F(0), F(0), F(0), F(0)};
     if (c >= kb - 1 && c < ke && valid) {
-      int ez = -1;
-      if (hybrid) ez = D.slot[2][nidx32(D, i, j, wrap1(c, D.nz))];
+      const int ez = szr;
       if (ez >= 0) {
 #pragma unroll
         for (int m = 0; m < 5; ++m) Fzp[m] = (F)D.Fw[2][(size_t)m * N + ez];
@@ -1402,17 +1421,14 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
         cflux<F, 0, L>(nd + 1, fr);
         cflux<F, 0, L>(nd, fl);
         if (hybrid) {
-          const int er = D.slot[0][n0];
+          const int er = sxr, el = sxl;
           if (er >= 0) {
 #pragma unroll
             for (int m = 0; m < 5; ++m) fr[m] = (F)D.Fw[0][(size_t)m * N + er];
           }
-          if (i > 0 || D.per_x) {
-            const int el = D.slot[0][i > 0 ? n0 - 1 : n0 + (D.nx - 1)];
-            if (el >= 0) {
+          if (el >= 0) {
 #pragma unroll
-              for (int m = 0; m < 5; ++m) fl[m] = (F)D.Fw[0][(size_t)m * N + el];
-            }
+            for (int m = 0; m < 5; ++m) fl[m] = (F)D.Fw[0][(size_t)m * N + el];
           }
         }
 #pragma unroll
@@ -1432,17 +1448,14 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
         if (wall_lo) wflux<F, 1, L>(nd, fl);
         else cflux<F, 1, L>(nd, fl);
         if (hybrid) {
-          const int er = D.slot[1][n0];
+          const int er = syr, el = syl;
           if (er >= 0) {
 #pragma unroll
             for (int m = 0; m < 5; ++m) fr[m] = (F)D.Fw[1][(size_t)m * N + er];
           }
-          if (j > 0 || D.per_y) {
-            const int el = D.slot[1][j > 0 ? n0 - D.nx : n0 + (D.ny - 1) * D.nx];
-            if (el >= 0) {
+          if (el >= 0) {
 #pragma unroll
-              for (int m = 0; m < 5; ++m) fl[m] = (F)D.Fw[1][(size_t)m * N + el];
-            }
+            for (int m = 0; m < 5; ++m) fl[m] = (F)D.Fw[1][(size_t)m * N + el];
           }
         }
 #pragma unroll
@@ -1543,6 +1556,7 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
 #pragma unroll
       for (int m = 0; m < 5; ++m) S.pend[pslot][m][tid] = Ra0[m];
     }
+    sxr = nxr; sxl = nxl; syr = nyr; syl = nyl; szr = nzr;
     __syncthreads();
   }
   // block partial sum of R_rhou dV (fixed order)
