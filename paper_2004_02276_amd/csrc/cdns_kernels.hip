@@ -1317,8 +1317,9 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
   };
   load_slots(kb - L, sxr, sxl, syr, syl, szr);
 
-  auto load_col = [&](int plane, PV<F>& s) {
-    double q[5];
+  // the column's conserved state at `plane` (issue), then its primitives
+  // into the window slot s and (rho, p, H) into the ring (complete)
+  auto issue_col = [&](int plane, double q[5]) {
     if (col_in) {
       const int b = nidx32(D, i, j, wrap1(plane, D.nz));  // plane in [-L, nz+2L-1], nz >= 2L
 #pragma unroll
@@ -1326,11 +1327,18 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
     } else {
       load_node(D, w, i, j, plane, q);
     }
+  };
+  auto finish_col = [&](int plane, const double q[5], PV<F>& s) {
     to_prim<F>(D, q, s);
     const int slot = modp<2 * L>(plane);
     S.zr[slot][0][tid] = s.r;
     S.zr[slot][1][tid] = s.p;
     S.zr[slot][2][tid] = s.h;
+  };
+  auto load_col = [&](int plane, PV<F>& s) {
+    double q[5];
+    issue_col(plane, q);
+    finish_col(plane, q, s);
   };
   // window slot with (rho, p, H) restored from the ring
   auto full = [&](int ws, int plane) {
@@ -1350,7 +1358,9 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
     for (int s = 0; s < 2 * L; ++s) win[s] = win[s + 1];
     int nxr, nxl, nyr, nyl, nzr;
     load_slots(c + 1, nxr, nxl, nyr, nyl, nzr);
-    load_col(c + L, win[2 * L]);
+    // the column's plane c+L is loaded while the halo of plane c is staged
+    double qcol[5];
+    issue_col(c + L, qcol);
     // stage plane c into LDS: interior from the window, halo cooperatively
     lds_store<F, TX, TY, L>(S, ty + L, tx + L, full(L, c));
     {
@@ -1382,6 +1392,7 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
         lds_store<F, TX, TY, L>(S, ly, lx, s);
       }
     }
+    finish_col(c + L, qcol, win[2 * L]);
     __syncthreads();
     const int ly = ty + L, lx = tx + L;
     // in-plane first derivatives feeding the z-mixed terms
