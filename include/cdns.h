@@ -171,7 +171,8 @@ cdns_status cdns_create(const cdns_grid* grid, const cdns_phys* phys, int32_t pr
 /* Set the boundary condition of one face (CDNS_BC_*, see above).  params
  * is a host array of nparams doubles (copied).  Both faces of an axis must
  * be periodic or both non-periodic; combinations not listed above return
- * CDNS_EUNSUP.  Call before stepping. */
+ * CDNS_EUNSUP.  Call before stepping; CDNS_EBUSY while the context is
+ * attached to a batch (as for cdns_set_tiling and cdns_set_scheme). */
 cdns_status cdns_set_bc(cdns_ctx* ctx, int32_t face, int32_t kind, const double* params,
                         int64_t nparams);
 
@@ -259,7 +260,7 @@ cdns_status cdns_export_sensor(cdns_ctx* ctx, double* theta_dev, uint8_t* nflags
  * mask in and makes the next cdns_rhs use it instead of evaluating the
  * sensor (hybrid mode only, CDNS_EINVAL otherwise; the interface flags and
  * lists are rebuilt from it; theta is not recomputed; stepping calls
- * always evaluate the sensor).  For comparing runs whose sensor decisions
+ * always evaluate the sensor and drop a pending import).  For comparing runs whose sensor decisions
  * differ only where theta is within round-off of the threshold. */
 cdns_status cdns_export_flags(cdns_ctx* ctx, uint8_t* flags_dev);
 cdns_status cdns_import_flags(cdns_ctx* ctx, const uint8_t* flags_dev);

@@ -337,6 +337,7 @@ cdns_status cdns_create(const cdns_grid* grid, const cdns_phys* phys, int32_t pr
 cdns_status cdns_set_bc(cdns_ctx* c, int32_t face, int32_t kind, const double* params,
                         int64_t nparams) {
   if (!c) return CDNS_EINVAL;
+  if (c->batch_refs > 0) return fail(c, CDNS_EBUSY, "context attached to a batch");
   if (face < 0 || face > 5) return fail(c, CDNS_EINVAL, "face out of range");
   if (kind < 0 || kind > 6) return fail(c, CDNS_EINVAL, "unknown boundary kind");
   if (nparams < 0 || (nparams > 0 && !params)) return fail(c, CDNS_EINVAL, "bad parameters");
@@ -403,6 +404,7 @@ static cdns_status check_bcs(cdns_ctx* c) {
 
 cdns_status cdns_set_tiling(cdns_ctx* c, int32_t tx, int32_t ty, int32_t kz) {
   if (!c) return CDNS_EINVAL;
+  if (c->batch_refs > 0) return fail(c, CDNS_EBUSY, "context attached to a batch");
   if (!cdns::rhs_tile_supported(tx, ty) || kz < 1)
     return fail(c, CDNS_EINVAL, "unsupported tile shape");
   if (c->D.cl != 2 && (tx != 64 || ty != 4))
@@ -417,6 +419,7 @@ cdns_status cdns_set_tiling(cdns_ctx* c, int32_t tx, int32_t ty, int32_t kz) {
 
 cdns_status cdns_set_scheme(cdns_ctx* c, int32_t central_order, int32_t weno_order) {
   if (!c) return CDNS_EINVAL;
+  if (c->batch_refs > 0) return fail(c, CDNS_EBUSY, "context attached to a batch");
   if (central_order != 2 && central_order != 4 && central_order != 6)
     return fail(c, CDNS_EINVAL, "central order must be 2, 4 or 6");
   if (weno_order != 3 && weno_order != 5 && weno_order != 7)
@@ -498,6 +501,7 @@ cdns_status cdns_rk_step(cdns_ctx* c, double cfl, double dt_fixed) {
   if (!(dt_fixed > 0.0) && !(cfl > 0.0)) return fail(c, CDNS_EINVAL, "need cfl > 0 or dt > 0");
   cdns_status s = check_bcs(c);
   if (s) return s;
+  c->flags_imported = false;  // the step's sensor overwrites the node flags
   Desc D = c->D;
   D.cfl = cfl;
   D.dt_fixed = dt_fixed > 0.0 ? dt_fixed : 0.0;
@@ -513,6 +517,7 @@ cdns_status cdns_advance_n(cdns_ctx* c, int32_t n, double cfl, double dt_fixed) 
   cdns_status s = check_bcs(c);
   if (s) return s;
   if (n == 0) return CDNS_OK;
+  c->flags_imported = false;  // the steps' sensor overwrites the node flags
   const double dtf = dt_fixed > 0.0 ? dt_fixed : 0.0;
   hipError_t e;
   if (!c->gexec || c->g_cfl != cfl || c->g_dt != dtf) {
@@ -627,6 +632,7 @@ cdns_status cdns_time_phases(cdns_ctx* c, int32_t nsteps, double cfl, double dt_
   if (!(dt_fixed > 0.0) && !(cfl > 0.0)) return fail(c, CDNS_EINVAL, "need cfl > 0 or dt > 0");
   cdns_status s = check_bcs(c);
   if (s) return s;
+  c->flags_imported = false;  // the steps' sensor overwrites the node flags
   Desc D = c->D;
   D.cfl = cfl;
   D.dt_fixed = dt_fixed > 0.0 ? dt_fixed : 0.0;

@@ -48,6 +48,15 @@ def test_flag_export_and_import(torch_cuda):
     assert np.array_equal(s.export_flags().cpu().numpy(), np.ones_like(nf_o))
     # the import is used once: the next evaluation runs the sensor again
     assert np.array_equal(s.rhs(s.state).cpu().numpy(), r_ref)
+    # a step drops a pending import (its sensor overwrites the node flags)
+    w_start = s.get_state()
+    s.import_flags(np.ones_like(nf_o))
+    s.rk_step(dt_fixed=1e-4)
+    s.rhs(s.state)
+    nf_next = s.export_flags().cpu().numpy()
+    _, _, nf_o2, _, _ = oracle.rhs(P.with_state(pr, s.get_state()), want_flags=True)
+    assert np.array_equal(nf_next, nf_o2)
+    s.set_state(w_start)
     s.close()
     pr2 = dataclasses.replace(pr, sensor_mode=P.SENSOR_WENO_ALL)
     s2 = Solver(pr2)
@@ -62,3 +71,26 @@ def test_flag_export_and_import(torch_cuda):
         s3.import_flags(np.zeros((16, 16, 16), np.uint8))
     assert err.value.status == B.CDNS_EINVAL
     s3.close()
+
+
+def test_configuration_refused_while_batched(torch_cuda):
+    """A batch runs an attached context from a snapshot of its descriptor,
+    so boundary, tiling and scheme changes wait for the detach."""
+    from paper_2004_02276_amd import Solver
+    from paper_2004_02276_amd import _binding as B
+    from paper_2004_02276_amd.serve import Batch
+    say("[batched configuration]")
+    pr = P.small_channel(24, 20, 12)
+    s = Solver(pr)
+    b = Batch(4)
+    slot = b.attach(s)
+    for call in (lambda: s.set_scheme(6, 7), lambda: s.set_tiling(64, 4, 8),
+                 lambda: B.check(s.lib, s.ctx, s.lib.cdns_set_bc(
+                     s.ctx, 2, P.BC_WALL_ADIABATIC, None, 0), "cdns_set_bc")):
+        with pytest.raises(B.CdnsError) as err:
+            call()
+        assert err.value.status == B.CDNS_EBUSY
+    b.detach(slot)
+    s.set_scheme(6, 7)
+    b.close()
+    s.close()
