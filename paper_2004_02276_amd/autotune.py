@@ -21,10 +21,17 @@ KZS = [4, 8, 16, 32]
 
 
 def size_class(pr) -> str:
-    """Bucket by point count (powers of two) and aspect (nx >= 64 or not)."""
+    """Bucket by point count (powers of two) and aspect (nx >= 64 or not);
+    scheme orders other than the default (4, 5) form classes of their own."""
     n = pr.nx * pr.ny * pr.nz
     b = max(0, int(n).bit_length() - 1)
-    return f"2^{b}-{'wide' if pr.nx >= 64 else 'narrow'}"
+    co, wo = orders(pr)
+    scheme = "" if (co, wo) == (4, 5) else f"-c{co}w{wo}"
+    return f"2^{b}-{'wide' if pr.nx >= 64 else 'narrow'}{scheme}"
+
+
+def orders(pr) -> Tuple[int, int]:
+    return int(getattr(pr, "central_order", 4)), int(getattr(pr, "weno_order", 5))
 
 
 def _key(device: str, precision: int, cls: str) -> str:
@@ -56,6 +63,8 @@ def tune(pr, precision: int = 0, steps: int = 2, tiles=TILES, kzs=KZS,
     dev = torch.cuda.get_device_name(0)
     results = {}
     cand_tiles = [fixed_tile] if fixed_tile else tiles
+    if orders(pr)[0] != 4:
+        cand_tiles = [(64, 4)]  # the only tile compiled for central orders 2 and 6
     for (tx, ty) in cand_tiles:
         for kz in kzs:
             if kz > pr.nz:
@@ -91,6 +100,8 @@ def lookup(pr, precision: int = 0, device: Optional[str] = None,
     if ent and (fixed_tile is None or tuple(ent["tile"]) == tuple(fixed_tile)):
         return ent["tile"][0], ent["tile"][1], ent["kz"]
     tx, ty = fixed_tile or (64, 4)
+    if orders(pr)[0] != 4:
+        tx, ty = 64, 4
     tiles = -(-pr.nx // tx) * -(-pr.ny // ty)
     kz = 16
     while kz > 4 and tiles * -(-pr.nz // kz) < 1024:
