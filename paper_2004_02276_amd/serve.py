@@ -113,10 +113,19 @@ class Server:
         self.device = device
 
     def _admit(self, spec, pr, now, batch, resident, used):
+        """Make the instance resident; (used bytes, False) if the batched
+        kernels do not run its configuration (digital-filter inflow or
+        scheme orders other than 4/5)."""
         s = Solver(pr, device=self.device, tiling=(self.tiling[0], self.tiling[1], self.kz_for(pr)))
-        slot = batch.attach(s)
+        try:
+            slot = batch.attach(s)
+        except B.CdnsError as err:
+            s.close()
+            if err.status != B.CDNS_EUNSUP:
+                raise
+            return used, False
         resident[spec.rid] = (spec, s, slot)
-        return used + footprint_bytes(pr)
+        return used + footprint_bytes(pr), True
 
     def run(self, specs, mode: str = "batch", prebuilt: Optional[Dict] = None) -> Dict:
         """Serve the trace.  mode 'batch' (continuous batching) or 'serial'
@@ -149,7 +158,10 @@ class Server:
                     if used + need > self.budget:
                         break
                     queue.pop(0)
-                    used = self._admit(spec, problems[spec.rid], now, batch, resident, used)
+                    used, ok = self._admit(spec, problems[spec.rid], now, batch, resident, used)
+                    if not ok:
+                        results[spec.rid].status = "rejected: configuration not batchable"
+                        continue
                     results[spec.rid].admitted = time.perf_counter() - t0
                     last_done[spec.rid] = time.perf_counter()
                 if not resident:
@@ -211,6 +223,7 @@ class Server:
                                          if r.finished >= 0])),
             "completed": sum(r.status == "ok" for r in results.values()),
             "failed": sum(r.status.startswith("failed") for r in results.values()),
+            "rejected": sum(r.status.startswith("rejected") for r in results.values()),
             "results": results,
         }
 

@@ -123,3 +123,21 @@ def test_server_admission_and_results(gpu):
         assert np.array_equal(a, b), rid
     # the budget really bounded the resident set: admissions waited
     assert rep["mean_queue_s"] >= 0.0
+
+
+def test_server_rejects_unbatchable_configurations(gpu):
+    """A request the batched kernels do not run (here sixth-order central
+    and seventh-order WENO) is rejected with a status in batch mode while
+    the others complete; the serial loop runs all of them."""
+    import dataclasses
+    from paper_2004_02276_amd.serve import Server
+    specs = [P.RequestSpec(i, 0.0, "turbulence" if i % 2 else "channel", 16 + 4 * i,
+                           0.5 + 0.3 * i, 1000.0 + 200 * i, 20, 8) for i in range(3)]
+    prbs = {s.rid: P.request_problem(s) for s in specs}
+    prbs[1] = dataclasses.replace(prbs[1], central_order=6, weno_order=7)
+    say("[server] unbatchable request")
+    rep = Server(P.request_problem, 1 << 34, max_slots=8).run(specs, mode="batch", prebuilt=prbs)
+    assert rep["completed"] == 2 and rep["rejected"] == 1
+    assert rep["results"][1].status == "rejected: configuration not batchable"
+    rep_s = Server(P.request_problem, 1 << 34, max_slots=8).run(specs, mode="serial", prebuilt=prbs)
+    assert rep_s["completed"] == 3
