@@ -1170,14 +1170,21 @@ template <typename F, int R>
 __global__ void __launch_bounds__(256) k_weno(Desc D, const double* __restrict__ w) {
   const int dir = blockIdx.y;
   const unsigned cnt = D.count[dir];
-  // each block streams through one contiguous segment of the list, and
-  // consecutive segments sit on the same XCD: neighbouring interfaces share
-  // stencil nodes in that XCD's L2
+  // The list is cut into chunks of 256 entries (one per block and pass, so
+  // every wave but the list's last is full) and the chunks into eight equal
+  // contiguous ranges, one per XCD; the blocks of an XCD take consecutive
+  // chunks in each pass, so neighbouring interfaces share stencil nodes in
+  // that XCD's L2.
   const unsigned G = gridDim.x;
   const unsigned lb = (unsigned)xcd_swizzle_blk(blockIdx.x, G);
-  const unsigned per = (cnt + G - 1) / G;  // even split: every XCD gets work
-  const unsigned e1 = min(cnt, (lb + 1) * per);
-  for (unsigned e = lb * per + threadIdx.x; e < e1; e += 256u) {
+  const unsigned groups = G % 8u == 0u ? 8u : 1u, per_g = G / groups;
+  const unsigned g = lb / per_g, q = lb - g * per_g;
+  const unsigned chunks = (cnt + 255u) / 256u;
+  const unsigned c0 = (unsigned)((unsigned long long)chunks * g / groups);
+  const unsigned c1 = (unsigned)((unsigned long long)chunks * (g + 1u) / groups);
+  for (unsigned ch = c0 + q; ch < c1; ch += per_g) {
+    const unsigned e = ch * 256u + threadIdx.x;
+    if (e >= cnt) break;
     const int n = D.list[dir][e];
     if (dir == 0) weno_entry<F, 0, R>(D, w, n, e);
     else if (dir == 1) weno_entry<F, 1, R>(D, w, n, e);
@@ -1984,7 +1991,7 @@ hipError_t launch_iflags(const Desc& D, hipStream_t st) {
 
 hipError_t launch_weno(const Desc& D, int stage, hipStream_t st) {
   long long b = nblk(D.N, 256);
-  if (b > 4096) b = 4096;
+  if (b > 1024) b = 1024;  // a few passes per block: fewer, longer-lived blocks
   dim3 grid((unsigned)b, 3);
   const double* w = D.win[stage];
   if (D.precision == 1) {
