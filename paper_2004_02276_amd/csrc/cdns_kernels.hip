@@ -1147,7 +1147,16 @@ __device__ __forceinline__ void weno_entry(const Desc& D, const double* __restri
     for (int s = 0; s < NS; ++s)
 #pragma unroll
       for (int m = 0; m < 5; ++m) qn[s][m] = b[m * D.N + s * st];
-  } else {
+  } else if (DIR == 2 || (DIR == 0 ? D.per_x : D.per_y)) {
+    // periodic direction: the stencil wraps (|offset| < nd), still direct
+    const int st = DIR == 0 ? 1 : (DIR == 1 ? D.nx : D.nx * D.ny);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int ns = n + (wrap1(c + s - (R - 1), nd) - c) * st;
+#pragma unroll
+      for (int m = 0; m < 5; ++m) qn[s][m] = w[(size_t)m * D.N + ns];
+    }
+  } else {  // a wall or open boundary within reach: ghost planes
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int o = s - (R - 1);
