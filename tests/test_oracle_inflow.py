@@ -10,6 +10,7 @@ variance, and the prescribed Reynolds stresses through the Cholesky
 factor; tolerances cover the sampling error of the sample sizes used.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -18,13 +19,17 @@ import oracle
 import problems as P
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
 def test_splitmix64_published_outputs():
-    # reference outputs of the published SplitMix64 generator (seed 1234567
-    # and seed 0, first outputs)
-    assert oracle.splitmix64(1234567, 1) == 6457827717110365317
-    assert oracle.splitmix64(1234567, 2) == 3203168211198807973
-    assert oracle.splitmix64(1234567, 3) == 9817491932198370423
-    assert oracle.splitmix64(0, 1) == 16294208416658607535
+    """Reference outputs of the published SplitMix64 generator
+    (tests/golden/splitmix64_reference.txt, with its citation)."""
+    rows = [line.split() for line in open(os.path.join(GOLDEN, "splitmix64_reference.txt"))
+            if line.strip() and not line.startswith("#")]
+    assert len(rows) >= 4
+    for seed, n, out in rows:
+        assert oracle.splitmix64(int(seed), int(n)) == int(out), (seed, n)
 
 
 def _plane_problem(ny=48, nz=64, ny_len=3.0, nz_len=4.0, t_lag=0.5, stresses=None):

@@ -389,6 +389,21 @@ def _sod_run(n, axis):
     return s, rho, exact_rho, w
 
 
+def test_exact_riemann_solver_matches_tabulated_sod_solution():
+    """The exact solver used as reference below reproduces the star state of
+    Sod's problem tabulated in Toro's textbook (tests/golden/sod_star_state.txt)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sod_star_state.txt")
+    ref = {k: float(v) for k, v in (line.split() for line in open(path)
+                                     if line.strip() and not line.startswith("#"))}
+    ps, us = exact.riemann_star(P.SOD_LEFT, P.SOD_RIGHT)
+    assert abs(ps - ref["p_star"]) < 6e-6 and abs(us - ref["u_star"]) < 6e-6
+    eps = 1e-6
+    rho_l = exact.riemann_sample(P.SOD_LEFT, P.SOD_RIGHT, np.array([us - eps]))[0][0]
+    rho_r = exact.riemann_sample(P.SOD_LEFT, P.SOD_RIGHT, np.array([us + eps]))[0][0]
+    assert abs(rho_l - ref["rho_star_left"]) < 6e-6 and abs(rho_r - ref["rho_star_right"]) < 6e-6
+
+
 @pytest.mark.parametrize("axis", [0, 1, 2])
 def test_sod_shock_tube_against_exact_riemann(axis):
     errs = []
