@@ -174,11 +174,12 @@ __device__ __forceinline__ double wrcp<double>(double x) {
 }
 
 // Square root of a positive normal x for the shock-capturing flux and the
-// viscosity: the
-// hardware reciprocal-square-root estimate refined by two coupled Newton
-// steps and a final residual correction (about one ulp; no scaling for
-// denormals or infinities, which a valid state never produces here; a
-// negative argument gives NaN like sqrt).  FP32: the ordinary square root.
+// viscosity: the hardware reciprocal-square-root estimate (relative error
+// about 2^-24) refined by one coupled Newton step and a final residual
+// correction, within one ulp (measured over 2^20 arguments in [1e-6, 1e6]:
+// a second coupled step changes nothing); no scaling for denormals or
+// infinities, which a valid state never produces here; a negative argument
+// gives NaN like sqrt.  FP32: the ordinary square root.
 template <typename F>
 __device__ __forceinline__ F wsqrt(F x) {
   return sqrt(x);
@@ -187,10 +188,7 @@ template <>
 __device__ __forceinline__ double wsqrt<double>(double x) {
   const double y = __builtin_amdgcn_rsq(x);
   double g = x * y, h = 0.5 * y;
-  double r = fma(-g, h, 0.5);
-  g = fma(g, r, g);
-  h = fma(h, r, h);
-  r = fma(-g, h, 0.5);
+  const double r = fma(-g, h, 0.5);
   g = fma(g, r, g);
   h = fma(h, r, h);
   const double d = fma(-g, g, x);
