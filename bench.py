@@ -36,9 +36,16 @@ FP64_VECTOR_TFLOPS = 78.6
 # (stage 0), read w, R_prev and write w', R (stage 1), read w, R_prev and
 # write w' (stage 2) = 400 B; the lazy bulk forcing adds one 8-byte field
 # per stage written and read = 448 B with forcing.
+STEP_BYTES_PER_PT = 400.0
 STEP_BYTES_PER_PT_FORCED = 448.0
 # The fused right-hand-side kernel must read w (40 B) and write R (40 B).
-RHS_BYTES_PER_PT = 80.0
+# Without bulk forcing it also does the stage's update: read w, write w', R
+# (stage 0), read w, R_prev and write w', R (stage 1), read w, R_prev and
+# write w' (stage 2), a mean of 400 / 3 B per point and stage.  With bulk
+# forcing it writes R (the force is reduced from it) and updates rho, rho v,
+# rho w: 80 B + 24 B of w' + 24 B of R_prev (stages 1, 2), a mean of 120 B.
+RHS_RK_BYTES_PER_PT = 400.0 / 3.0
+RHS_RK_SPLIT_BYTES_PER_PT = 120.0
 # FP64 operations of one shock-capturing interface flux, counted from the
 # formula (a fused multiply-add counts two, a division or square root one),
 # by WENO order 2r-1: Roe average and eigenvalue constants 64; 2r nodes x
@@ -78,9 +85,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel):
+def load_traffic(kernel, workload):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source (else None)."""
+    taken on the current kernel source and this workload (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -88,7 +95,7 @@ def load_traffic(kernel):
     except (OSError, ValueError):
         return None
     ent = t.get(kernel)
-    if not ent or ent.get("source_hash") != kernel_source_hash():
+    if not ent or ent.get("source_hash") != kernel_source_hash() or ent.get("workload") != workload:
         return None
     return ent.get("hbm_bytes_per_launch")
 
@@ -186,19 +193,25 @@ def main():
         achieved = flops / (mean_ms * 1e-3) / 1e12
         roof = {"kernel": "k_weno", "bound": "alu", "achieved": achieved,
                 "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_TFLOPS,
-                "traffic": load_traffic("k_weno") if default_scheme else None,
+                "traffic": load_traffic("k_weno", args.workload) if default_scheme else None,
                 "algorithmic_per_launch": f"{fl_if:.0f} flop x {n_iface:.0f} "
                                           f"interfaces (mean over the timed launches)"}
     else:
-        nbytes = RHS_BYTES_PER_PT * pr.npts
+        # the default 64x4 tiling (the one used here) does the stage update
+        # inside the flux kernel: whole without forcing (no update
+        # launches), the part without the force otherwise
+        bpp = RHS_RK_SPLIT_BYTES_PER_PT if pr.forcing else RHS_RK_BYTES_PER_PT
+        nbytes = bpp * pr.npts
         achieved = nbytes / (ph["rhs"][0] * 1e-3) / 1e9
         roof = {"kernel": "k_rhs", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic("k_rhs") if default_scheme else None,
-                "algorithmic_per_launch": f"{RHS_BYTES_PER_PT:.0f} B x {pr.npts} points"}
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": load_traffic("k_rhs", args.workload) if default_scheme else None,
+                "algorithmic_per_launch": f"{bpp:.1f} B x {pr.npts} points (RK update included)"}
     roof["mean_launch_ms"] = mean_ms
     scheme = ("" if (args.central_order, args.weno_order) == (4, 5) else
               f"; central order {args.central_order}, WENO order {args.weno_order}")
-    hbm_frac_step = value * 1e6 * STEP_BYTES_PER_PT_FORCED / (HBM_PEAK_GBS * 1e9)
+    step_bytes = STEP_BYTES_PER_PT_FORCED if pr.forcing else STEP_BYTES_PER_PT
+    hbm_frac_step = value * 1e6 * step_bytes / (HBM_PEAK_GBS * 1e9)
 
     out = {
         "metric": METRIC,

@@ -220,7 +220,10 @@ cdns_status cdns_rhs(cdns_ctx* ctx, const double* w_dev, double* r_dev);
 
 /* One RK3 step of the state.  dt_fixed > 0 sets the step; otherwise
  * dt = cfl * min(1/max sum_d (|u_d|+c)/dx_d, 2.5/max[max(4/3,gamma/Pr)
- * (mu/rho)(16/3) sum_d dx_d^-2]) is computed on the device from w^n. */
+ * (mu/rho)(16/3) sum_d dx_d^-2]) is computed on the device from w^n.
+ * Without bulk forcing and in the default 64x4 tiling, each stage's update
+ * is done by the right-hand-side kernel as it finishes a point (the same
+ * rounding as the separate update kernel used otherwise). */
 cdns_status cdns_rk_step(cdns_ctx* ctx, double cfl, double dt_fixed);
 
 /* n RK3 steps, replayed from one captured HIP graph per step. */
@@ -276,7 +279,9 @@ cdns_status cdns_export_iface_flux(cdns_ctx* ctx, int32_t dir, double* out_dev);
  * each phase, launches_out[CDNS_NPHASES] (may be NULL) the number of
  * launches timed, weno_ifaces_out (may be NULL) the total number of
  * shock-capturing interfaces (all directions) processed by the timed WENO
- * launches.  Advances the state like cdns_rk_step; synchronises. */
+ * launches.  Where the update runs inside the right-hand-side kernel (see
+ * cdns_rk_step), CDNS_PH_RHS covers both and CDNS_PH_RK has no launches.
+ * Advances the state like cdns_rk_step; synchronises. */
 enum { CDNS_PH_DT = 0, CDNS_PH_GHOSTS, CDNS_PH_SENSOR, CDNS_PH_IFLAGS, CDNS_PH_WENO,
        CDNS_PH_RHS, CDNS_PH_FORCE, CDNS_PH_RK, CDNS_NPHASES };
 cdns_status cdns_time_phases(cdns_ctx* ctx, int32_t nsteps, double cfl, double dt_fixed,

@@ -144,7 +144,7 @@ void default_tiling(Desc& D) {
 // keep_flags: use the node flags already in place (imported) instead of
 // running the sensor.
 hipError_t enqueue_rhs_phases(const Desc& D, int stage, bool export_theta, hipStream_t st,
-                              bool keep_flags = false) {
+                              bool keep_flags = false, bool fuse_rk = false) {
   hipError_t e;
   // list counters: reset by the sensor kernel in hybrid mode, else here
   if ((D.sensor_mode == 2 || keep_flags) && (e = cdns::launch_stage_begin(D, st)) != hipSuccess)
@@ -157,7 +157,7 @@ hipError_t enqueue_rhs_phases(const Desc& D, int stage, bool export_theta, hipSt
     if ((e = cdns::launch_iflags(D, st)) != hipSuccess) return e;
     if ((e = cdns::launch_weno(D, stage, st)) != hipSuccess) return e;
   }
-  if ((e = cdns::launch_rhs(D, stage, st)) != hipSuccess) return e;
+  if ((e = cdns::launch_rhs(D, stage, st, fuse_rk)) != hipSuccess) return e;
   if (D.forcing && (e = cdns::launch_force(D, st)) != hipSuccess) return e;
   return hipSuccess;
 }
@@ -167,9 +167,12 @@ hipError_t enqueue_step(const Desc& D, hipStream_t st) {
   if ((e = cdns::launch_dt(D, st)) != hipSuccess) return e;
   // inflow plane of this step (needs the step's dt and counter)
   if (D.bc[0] == cdns::BC_DF_INFLOW && (e = cdns::launch_df(D, false, st)) != hipSuccess) return e;
+  const bool fuse = cdns::rk_fused(D);  // update inside the right-hand-side pass
   for (int stage = 0; stage < 3; ++stage) {
-    if ((e = enqueue_rhs_phases(D, stage, false, st)) != hipSuccess) return e;
-    if ((e = cdns::launch_rk(D, stage, st)) != hipSuccess) return e;
+    if ((e = enqueue_rhs_phases(D, stage, false, st, false, fuse)) != hipSuccess) return e;
+    if (!fuse) e = cdns::launch_rk(D, stage, st);
+    else if (D.forcing) e = cdns::launch_rk_forced(D, stage, st);
+    if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -667,9 +670,11 @@ cdns_status cdns_time_phases(cdns_ctx* c, int32_t nsteps, double cfl, double dt_
         timed(CDNS_PH_WENO, [&] { return cdns::launch_weno(D, stage, st); });
         if (e == hipSuccess) e = cdns::launch_count_iface(D, false, st);  // outside the events
       }
-      timed(CDNS_PH_RHS, [&] { return cdns::launch_rhs(D, stage, st); });
+      const bool fuse = cdns::rk_fused(D);
+      timed(CDNS_PH_RHS, [&] { return cdns::launch_rhs(D, stage, st, fuse); });
       if (D.forcing) timed(CDNS_PH_FORCE, [&] { return cdns::launch_force(D, st); });
-      timed(CDNS_PH_RK, [&] { return cdns::launch_rk(D, stage, st); });
+      if (!fuse) timed(CDNS_PH_RK, [&] { return cdns::launch_rk(D, stage, st); });
+      else if (D.forcing) timed(CDNS_PH_RK, [&] { return cdns::launch_rk_forced(D, stage, st); });
     }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(st);

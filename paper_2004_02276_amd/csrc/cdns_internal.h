@@ -89,7 +89,11 @@ hipError_t launch_ghosts(const Desc& D, int stage, hipStream_t st);
 hipError_t launch_sensor(const Desc& D, int stage, bool export_theta, hipStream_t st);
 hipError_t launch_iflags(const Desc& D, hipStream_t st);
 hipError_t launch_weno(const Desc& D, int stage, hipStream_t st);
-hipError_t launch_rhs(const Desc& D, int stage, hipStream_t st);
+// fuse_rk: the RK update of the stage in the same pass (rk_fused(D) only)
+hipError_t launch_rhs(const Desc& D, int stage, hipStream_t st, bool fuse_rk = false);
+bool rk_fused(const Desc& D);
+// completion of a fused update under bulk forcing (after launch_force)
+hipError_t launch_rk_forced(const Desc& D, int stage, hipStream_t st);
 hipError_t launch_force(const Desc& D, hipStream_t st);
 hipError_t launch_apply_force(const Desc& D, int stage, hipStream_t st);
 hipError_t launch_rk(const Desc& D, int stage, hipStream_t st);

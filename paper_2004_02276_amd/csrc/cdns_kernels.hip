@@ -1253,6 +1253,51 @@ __device__ __forceinline__ int modp(int x) {
   else return (int)((unsigned)(x + P) % (unsigned)P);
 }
 
+// Low-storage RK3 update of one point (Sec. 2.2, eq. RK) from its finished
+// right-hand side r: the same arithmetic as k_rk, done where r is produced.
+// Without bulk forcing (SPLIT false) all five components are updated, R is
+// stored for the next stage (stages 0 and 1) and non-physical results set
+// `bad`.  With forcing (SPLIT true) the force is not yet known: R is stored
+// unforced by the caller and only rho, rho v, rho w are updated here; the
+// update of rho u, rho E and the state check follow in k_rk_forced once
+// the force has been reduced.
+template <bool SPLIT>
+__device__ __forceinline__ void rk_point(const Desc& D, int stage, double dt,
+                                         const double* __restrict__ w, int no, const double r[5],
+                                         bool& bad) {
+  const double alpha = stage == 0 ? 0.0 : (stage == 1 ? -17.0 / 60.0 : -5.0 / 12.0);
+  const double beta = stage == 0 ? 8.0 / 15.0 : (stage == 1 ? 5.0 / 12.0 : 3.0 / 4.0);
+  const size_t N = (size_t)D.N;
+  const double* __restrict__ Rp = D.rprev[stage];
+  double* __restrict__ Rc = D.rcur[stage];
+  double* __restrict__ wo = D.wout[stage];
+  double q[5], rp[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    if (SPLIT && (m == 1 || m == 4)) continue;
+    q[m] = w[m * N + no];
+    rp[m] = stage > 0 ? Rp[m * N + no] : 0.0;
+  }
+  if (!SPLIT && stage < 2) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) Rc[m * N + no] = r[m];
+  }
+  double o[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    if (SPLIT && (m == 1 || m == 4)) continue;
+    double acc = beta * r[m];
+    if (stage > 0) acc = fma(alpha, rp[m], acc);
+    o[m] = fma(dt, acc, q[m]);
+    wo[m * N + no] = o[m];
+  }
+  if constexpr (!SPLIT) {
+    const double ke = 0.5 * (o[1] * o[1] + o[2] * o[2] + o[3] * o[3]) / o[0];
+    const double pe = o[4] - ke;
+    bad |= !(o[0] > 0.0) || !(pe > 0.0) || !(fabs(o[4]) < 1e300);
+  }
+}
+
 // One block of the fused kernel: tile (tile index lb) of the instance D,
 // central stencils of half-width L (order 2L).  Each thread owns one (i, j)
 // column of the tile and walks its z chunk; plane c is staged in LDS with an
@@ -1262,9 +1307,12 @@ __device__ __forceinline__ int modp(int x) {
 // derivatives of plane c are known.  VISC_ON false compiles the viscous
 // terms out (inviscid problems: fewer registers); true evaluates them when
 // the instance is viscous.
-template <typename F, int TX, int TY, bool VISC_ON, int L>
+// RKM: 0 stores R for the update kernel; 1 (no bulk forcing) does the
+// point's RK update of stage rk_stage in the same pass; 2 (bulk forcing)
+// stores R and does the part of the update that does not involve the force.
+template <typename F, int TX, int TY, bool VISC_ON, int L, int RKM = 0>
 __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict__ w, double* __restrict__ R,
-                         int lb, RhsSmem<F, TX, TY, L>& S) {
+                         int lb, RhsSmem<F, TX, TY, L>& S, int rk_stage = -1) {
   constexpr int LX = TX + 2 * L, LY = TY + 2 * L;
   constexpr int NT = TX * TY;
   constexpr int NH = LX * LY - TX * TY;
@@ -1312,6 +1360,8 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
     Fzm[m] = F(0);
   }
   double fsum = 0.0;
+  const double dt_rk = RKM ? D.scal[SC_DT] : 0.0;
+  bool rk_bad = false;
 
   // list positions of the interfaces of plane c (x i+-1/2, y j+-1/2, z
   // c+1/2; -1: central flux), loaded one plane ahead so that their latency
@@ -1573,9 +1623,14 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
         Ra2[4] += (double)(o2.u * ax + o2.v * ay + o2.w * az);
       }
       const int no = nidx32(D, i, j, m2);
+      if constexpr (RKM == 1) {
+        rk_point<false>(D, rk_stage, dt_rk, w, no, Ra2, rk_bad);
+      } else {
 #pragma unroll
-      for (int m = 0; m < 5; ++m) R[(size_t)m * N + no] = Ra2[m];
-      fsum += Ra2[1] * D.y_eta[j];
+        for (int m = 0; m < 5; ++m) R[(size_t)m * N + no] = Ra2[m];
+        fsum += Ra2[1] * D.y_eta[j];
+        if constexpr (RKM == 2) rk_point<true>(D, rk_stage, dt_rk, w, no, Ra2, rk_bad);
+      }
     }
     if (c >= kb && c < ke && valid) {
 #pragma unroll
@@ -1584,8 +1639,9 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
     sxr = nxr; sxl = nxl; syr = nyr; syl = nyl; szr = nzr;
     __syncthreads();
   }
+  if (RKM == 1 && rk_bad) atomicOr(D.status, (unsigned)ST_BAD_STATE);
   // block partial sum of R_rhou dV (fixed order)
-  if (D.forcing) {
+  if (RKM != 1 && D.forcing) {
     double v = fsum;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
@@ -1608,12 +1664,12 @@ __device__ __forceinline__ int xcd_swizzle(int b, int nb) {
 
 // Sixth-order stencils need more shared memory than two blocks of a CU can
 // hold, so that variant runs one block per CU with the full register file.
-template <typename F, int TX, int TY, bool VISC_ON, int L>
+template <typename F, int TX, int TY, bool VISC_ON, int L, int RKM = 0>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(L == 3 ? 1 : 2)))
-k_rhs(Desc D, const double* __restrict__ w, double* __restrict__ R) {
+k_rhs(Desc D, const double* __restrict__ w, double* __restrict__ R, int rk_stage) {
   __shared__ RhsSmem<F, TX, TY, L> S;
   const int lb = xcd_swizzle(blockIdx.x, gridDim.x);
-  rhs_body<F, TX, TY, VISC_ON, L>(D, w, R, lb, S);
+  rhs_body<F, TX, TY, VISC_ON, L, RKM>(D, w, R, lb, S, rk_stage);
 }
 
 // ------------------------------------------------------------------ reductions
@@ -1715,7 +1771,7 @@ __device__ __forceinline__ void rk_block_s(const Desc& D, long long blk) {
     if (n[p] >= D.N) continue;
     if (D.forcing) {
       r[p][1] += f;
-      r[p][4] += f * (q[p][1] * (1.0 / q[p][0]));
+      r[p][4] = fma(f, q[p][1] * (1.0 / q[p][0]), r[p][4]);
       if (stage < 2) {
         R[1 * N + n[p]] = r[p][1];
         R[4 * N + n[p]] = r[p][4];
@@ -1724,9 +1780,11 @@ __device__ __forceinline__ void rk_block_s(const Desc& D, long long blk) {
     double o[5];
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
+      // explicit fused multiply-adds: rounded as in rk_point, the update
+      // done inside the flux kernel
       double acc = beta * r[p][m];
-      if (stage > 0) acc += alpha * rp[p][m];
-      o[m] = q[p][m] + dt * acc;
+      if (stage > 0) acc = fma(alpha, rp[p][m], acc);
+      o[m] = fma(dt, acc, q[p][m]);
       wo[m * N + n[p]] = o[m];
     }
     const double ke = 0.5 * (o[1] * o[1] + o[2] * o[2] + o[3] * o[3]) / o[0];
@@ -1746,6 +1804,73 @@ __device__ __forceinline__ void rk_block(const Desc& D, int stage, long long blk
 __global__ void __launch_bounds__(256) k_rk(Desc D, int stage) {
   __shared__ double sm[8];
   rk_block(D, stage, blockIdx.x, sm);
+}
+
+// Completion of a split update (bulk forcing, rk_point<true> in the flux
+// kernel): adds the reduced force to R_rhou and R_rhoE, stores them for the
+// next stage, updates rho u and rho E with the arithmetic of k_rk and checks
+// the new state (rho, rho v, rho w as written by the flux kernel).
+template <int stage>
+__device__ __forceinline__ void rk_forced_block_s(const Desc& D, long long blk) {
+  const double f = D.scal[SC_FORCE];
+  const double alpha = stage == 0 ? 0.0 : (stage == 1 ? -17.0 / 60.0 : -5.0 / 12.0);
+  const double beta = stage == 0 ? 8.0 / 15.0 : (stage == 1 ? 5.0 / 12.0 : 3.0 / 4.0);
+  const double* __restrict__ w = D.win[stage];
+  double* __restrict__ wo = D.wout[stage];
+  double* __restrict__ R = D.rcur[stage];
+  const double* __restrict__ Rp = D.rprev[stage];
+  const size_t N = (size_t)D.N;
+  const double dt = D.scal[SC_DT];
+  long long n[kRkPer];
+  double q0[kRkPer], q1[kRkPer], q4[kRkPer], r1[kRkPer], r4[kRkPer], p1[kRkPer], p4[kRkPer];
+  double o0[kRkPer], o2[kRkPer], o3[kRkPer];
+#pragma unroll
+  for (int p = 0; p < kRkPer; ++p) {
+    n[p] = (blk * kRkPer + p) * 256 + threadIdx.x;
+    const size_t c = (size_t)(n[p] < D.N ? n[p] : D.N - 1);
+    q0[p] = w[c];
+    q1[p] = w[N + c];
+    q4[p] = w[4 * N + c];
+    r1[p] = R[N + c];
+    r4[p] = R[4 * N + c];
+    if (stage > 0) {
+      p1[p] = Rp[N + c];
+      p4[p] = Rp[4 * N + c];
+    }
+    o0[p] = wo[c];
+    o2[p] = wo[2 * N + c];
+    o3[p] = wo[3 * N + c];
+  }
+  bool bad = false;
+#pragma unroll
+  for (int p = 0; p < kRkPer; ++p) {
+    if (n[p] >= D.N) continue;
+    const double fr1 = r1[p] + f;
+    const double fr4 = fma(f, q1[p] * (1.0 / q0[p]), r4[p]);
+    if (stage < 2) {
+      R[1 * N + n[p]] = fr1;
+      R[4 * N + n[p]] = fr4;
+    }
+    double a1 = beta * fr1, a4 = beta * fr4;
+    if (stage > 0) {
+      a1 = fma(alpha, p1[p], a1);
+      a4 = fma(alpha, p4[p], a4);
+    }
+    const double o1 = fma(dt, a1, q1[p]);
+    const double o4 = fma(dt, a4, q4[p]);
+    wo[1 * N + n[p]] = o1;
+    wo[4 * N + n[p]] = o4;
+    const double ke = 0.5 * (o1 * o1 + o2[p] * o2[p] + o3[p] * o3[p]) / o0[p];
+    const double pe = o4 - ke;
+    bad |= !(o0[p] > 0.0) || !(pe > 0.0) || !(fabs(o4) < 1e300);
+  }
+  if (bad) atomicOr(D.status, (unsigned)ST_BAD_STATE);
+}
+
+__global__ void __launch_bounds__(256) k_rk_forced(Desc D, int stage) {
+  if (stage == 0) rk_forced_block_s<0>(D, blockIdx.x);
+  else if (stage == 1) rk_forced_block_s<1>(D, blockIdx.x);
+  else rk_forced_block_s<2>(D, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ time step
@@ -2022,31 +2147,47 @@ bool rhs_tile_supported(int tx, int ty) {
 
 // The fourth-order kernel comes in every supported tile shape; the second-
 // and sixth-order ones in the 64x4 tile only (the scheme setter enforces it).
+// The RK update joins the right-hand-side pass in the default 64x4 tile:
+// whole without bulk forcing; with forcing the rho, rho v, rho w part,
+// the rest following in k_rk_forced once the force is reduced.
+bool rk_fused(const Desc& D) { return D.tile_x == 64 && D.tile_y == 4; }
+
 template <typename F, bool VISC_ON>
-static hipError_t launch_rhs_v(const Desc& D, int stage, hipStream_t st) {
+static hipError_t launch_rhs_v(const Desc& D, int stage, bool fuse, hipStream_t st) {
   const unsigned nb = (unsigned)rhs_blocks(D);
   const double* w = D.win[stage];
   double* R = D.rcur[stage];
-  if (D.cl != 2) {
+  if (fuse && D.forcing) {
+    if (D.cl == 1) k_rhs<F, 64, 4, VISC_ON, 1, 2><<<nb, 256, 0, st>>>(D, w, R, stage);
+    else if (D.cl == 3) k_rhs<F, 64, 4, VISC_ON, 3, 2><<<nb, 256, 0, st>>>(D, w, R, stage);
+    else k_rhs<F, 64, 4, VISC_ON, 2, 2><<<nb, 256, 0, st>>>(D, w, R, stage);
+  } else if (fuse) {
+    if (D.cl == 1) k_rhs<F, 64, 4, VISC_ON, 1, 1><<<nb, 256, 0, st>>>(D, w, R, stage);
+    else if (D.cl == 3) k_rhs<F, 64, 4, VISC_ON, 3, 1><<<nb, 256, 0, st>>>(D, w, R, stage);
+    else k_rhs<F, 64, 4, VISC_ON, 2, 1><<<nb, 256, 0, st>>>(D, w, R, stage);
+  } else if (D.cl != 2) {
     if (D.tile_x != 64 || D.tile_y != 4) return hipErrorInvalidValue;
-    if (D.cl == 1) k_rhs<F, 64, 4, VISC_ON, 1><<<nb, 256, 0, st>>>(D, w, R);
-    else k_rhs<F, 64, 4, VISC_ON, 3><<<nb, 256, 0, st>>>(D, w, R);
-  } else if (D.tile_x == 64 && D.tile_y == 4) k_rhs<F, 64, 4, VISC_ON, 2><<<nb, 256, 0, st>>>(D, w, R);
-  else if (D.tile_x == 32 && D.tile_y == 8) k_rhs<F, 32, 8, VISC_ON, 2><<<nb, 256, 0, st>>>(D, w, R);
-  else if (D.tile_x == 64 && D.tile_y == 2) k_rhs<F, 64, 2, VISC_ON, 2><<<nb, 128, 0, st>>>(D, w, R);
-  else if (D.tile_x == 128 && D.tile_y == 2) k_rhs<F, 128, 2, VISC_ON, 2><<<nb, 256, 0, st>>>(D, w, R);
-  else if (D.tile_x == 64 && D.tile_y == 8) k_rhs<F, 64, 8, VISC_ON, 2><<<nb, 512, 0, st>>>(D, w, R);
+    if (D.cl == 1) k_rhs<F, 64, 4, VISC_ON, 1><<<nb, 256, 0, st>>>(D, w, R, -1);
+    else k_rhs<F, 64, 4, VISC_ON, 3><<<nb, 256, 0, st>>>(D, w, R, -1);
+  } else if (D.tile_x == 64 && D.tile_y == 4) k_rhs<F, 64, 4, VISC_ON, 2><<<nb, 256, 0, st>>>(D, w, R, -1);
+  else if (D.tile_x == 32 && D.tile_y == 8) k_rhs<F, 32, 8, VISC_ON, 2><<<nb, 256, 0, st>>>(D, w, R, -1);
+  else if (D.tile_x == 64 && D.tile_y == 2) k_rhs<F, 64, 2, VISC_ON, 2><<<nb, 128, 0, st>>>(D, w, R, -1);
+  else if (D.tile_x == 128 && D.tile_y == 2) k_rhs<F, 128, 2, VISC_ON, 2><<<nb, 256, 0, st>>>(D, w, R, -1);
+  else if (D.tile_x == 64 && D.tile_y == 8) k_rhs<F, 64, 8, VISC_ON, 2><<<nb, 512, 0, st>>>(D, w, R, -1);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 template <typename F>
-static hipError_t launch_rhs_t(const Desc& D, int stage, hipStream_t st) {
-  return D.viscous ? launch_rhs_v<F, true>(D, stage, st) : launch_rhs_v<F, false>(D, stage, st);
+static hipError_t launch_rhs_t(const Desc& D, int stage, bool fuse, hipStream_t st) {
+  return D.viscous ? launch_rhs_v<F, true>(D, stage, fuse, st)
+                   : launch_rhs_v<F, false>(D, stage, fuse, st);
 }
 
-hipError_t launch_rhs(const Desc& D, int stage, hipStream_t st) {
-  return D.precision == 1 ? launch_rhs_t<float>(D, stage, st) : launch_rhs_t<double>(D, stage, st);
+hipError_t launch_rhs(const Desc& D, int stage, hipStream_t st, bool fuse_rk) {
+  if (fuse_rk && (stage > 2 || !rk_fused(D))) return hipErrorInvalidValue;
+  return D.precision == 1 ? launch_rhs_t<float>(D, stage, fuse_rk, st)
+                          : launch_rhs_t<double>(D, stage, fuse_rk, st);
 }
 
 hipError_t launch_force(const Desc& D, hipStream_t st) {
@@ -2061,6 +2202,12 @@ hipError_t launch_apply_force(const Desc& D, int stage, hipStream_t st) {
 
 hipError_t launch_rk(const Desc& D, int stage, hipStream_t st) {
   k_rk<<<nblk(D.N, 256 * kRkPer), 256, 0, st>>>(D, stage);
+  return hipGetLastError();
+}
+
+hipError_t launch_rk_forced(const Desc& D, int stage, hipStream_t st) {
+  if (!D.forcing || stage > 2) return hipErrorInvalidValue;
+  k_rk_forced<<<nblk(D.N, 256 * kRkPer), 256, 0, st>>>(D, stage);
   return hipGetLastError();
 }
 

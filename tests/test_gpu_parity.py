@@ -248,15 +248,49 @@ def test_fp32_flux_mode_error_report(torch_cuda):
     assert max(errs) < 1e-3
 
 
-def test_bad_state_is_reported(torch_cuda):
+@pytest.mark.parametrize("forced", [False, True])
+def test_bad_state_is_reported(torch_cuda, forced):
+    """Both forms of the update inside the flux kernel check the new state:
+    whole (no bulk forcing) and completed after the force reduction."""
     from paper_2004_02276_amd import Solver
-    pr = P.taylor_green(16)
+    pr = P.small_channel(24, 20, 12) if forced else P.taylor_green(16)
+    say(f"[bad state] forced={forced}")
     w0 = pr.w0.copy()
     w0[4, 3, 3, 3] = -1.0  # negative total energy -> negative pressure
     s = Solver(P.with_state(pr, w0))
-    s.advance(1, cfl=0.5)
+    s.advance(1, dt_fixed=1e-4)
     d = s.diagnostics(raise_on_error=False)
     assert d["rc"] == -4 and d["status"] != 0
+    s.close()
+
+
+@pytest.mark.parametrize("forced", [False, True])
+def test_update_in_flux_kernel_matches_update_kernel(torch_cuda, forced):
+    """The default 64x4 tiling does each stage's update in the flux kernel
+    (whole without bulk forcing; with forcing rho, rho v, rho w there and
+    rho u, rho E once the force is reduced); other tilings launch the
+    separate update kernel.  The arithmetic is the same: without forcing
+    the states agree bit for bit; with forcing the force is summed from
+    other block partials, so they agree to rounding."""
+    from paper_2004_02276_amd import Solver
+    pr = P.small_channel(24, 20, 12) if forced else P.small_sbli(64, 32, 8)
+    say(f"[update in flux kernel] forced={forced}")
+    dt = oracle.dt(pr)
+    out = []
+    for tiling in [(64, 4, 4), (32, 8, 4)]:
+        s = Solver(pr, tiling=tiling)
+        ph = s.time_phases(10, dt_fixed=dt)
+        assert (ph["rk"][1] > 0) == (forced or tiling[0] != 64)
+        out.append(s.get_state())
+        s.close()
+    if forced:
+        errs = field_errors(out[0], out[1])
+        assert max(errs) <= 1e-13, errs
+    else:
+        assert np.array_equal(out[0], out[1])
+    s = Solver(pr, tiling=(64, 4, 4))  # graph replay: the same steps
+    s.advance(10, dt_fixed=dt)
+    assert np.array_equal(s.get_state(), out[0])
     s.close()
 
 
