@@ -230,7 +230,11 @@ cdns_status cdns_rk_step(cdns_ctx* ctx, double cfl, double dt_fixed);
 cdns_status cdns_advance_n(cdns_ctx* ctx, int32_t n, double cfl, double dt_fixed);
 
 /* Volume integrals, extrema and status of the current state; synchronises
- * the stream.  Returns CDNS_ESTATE if the device flagged a bad state. */
+ * the stream.  Returns CDNS_ESTATE if the device flagged a bad state (an RK
+ * stage produced a point with rho <= 0, p <= 0 or a non-finite energy;
+ * with bulk forcing in the default tiling this is detected when the next
+ * stage reads the point) or the current state has rho_min <= 0,
+ * p_min <= 0 or non-finite values. */
 cdns_status cdns_diagnostics(cdns_ctx* ctx, cdns_diag* out);
 
 /* Running statistics for mean profiles and turbulent stresses (the

@@ -586,7 +586,8 @@ cdns_status cdns_diagnostics(cdns_ctx* c, cdns_diag* out) {
                          (double)D.nx * (D.per_y ? D.ny : D.ny - 1) * D.nz, (double)D.N};
   for (int d = 0; d < 3; ++d) out->weno_frac[d] = D.sensor_mode > 0 ? cnt[d] / nif[d] : 0.0;
   out->status = (int32_t)st[0];
-  if (st[0] != 0 || out->nonfinite != 0) return fail(c, CDNS_ESTATE, "device flagged a bad state");
+  if (st[0] != 0 || out->nonfinite != 0 || !(out->rho_min > 0.0) || !(out->p_min > 0.0))
+    return fail(c, CDNS_ESTATE, "device flagged a bad state");
   return CDNS_OK;
 }
 

@@ -1361,7 +1361,7 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
   }
   double fsum = 0.0;
   const double dt_rk = RKM ? D.scal[SC_DT] : 0.0;
-  bool rk_bad = false;
+  bool bad_state = false;  // a non-physical update result (or input, RKM 2)
 
   // list positions of the interfaces of plane c (x i+-1/2, y j+-1/2, z
   // c+1/2; -1: central flux), loaded one plane ahead so that their latency
@@ -1394,6 +1394,15 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
   };
   auto finish_col = [&](int plane, const double q[5], PV<F>& s) {
     to_prim<F>(D, q, s);
+    // split update: the previous update's result is checked here, once per
+    // point (the block's own planes), with the test the update kernels
+    // apply to their results
+    if constexpr (RKM == 2) {
+      if (valid && plane >= kb && plane < ke) {
+        const double kq = 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
+        bad_state |= !(q[0] > 0.0) || !(q[4] - kq > 0.0) || !(fabs(q[4]) < 1e300);
+      }
+    }
     const int slot = modp<2 * L>(plane);
     S.zr[slot][0][tid] = s.r;
     S.zr[slot][1][tid] = s.p;
@@ -1624,12 +1633,12 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
       }
       const int no = nidx32(D, i, j, m2);
       if constexpr (RKM == 1) {
-        rk_point<false>(D, rk_stage, dt_rk, w, no, Ra2, rk_bad);
+        rk_point<false>(D, rk_stage, dt_rk, w, no, Ra2, bad_state);
       } else {
 #pragma unroll
         for (int m = 0; m < 5; ++m) R[(size_t)m * N + no] = Ra2[m];
         fsum += Ra2[1] * D.y_eta[j];
-        if constexpr (RKM == 2) rk_point<true>(D, rk_stage, dt_rk, w, no, Ra2, rk_bad);
+        if constexpr (RKM == 2) rk_point<true>(D, rk_stage, dt_rk, w, no, Ra2, bad_state);
       }
     }
     if (c >= kb && c < ke && valid) {
@@ -1639,7 +1648,7 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
     sxr = nxr; sxl = nxl; syr = nyr; syl = nyl; szr = nzr;
     __syncthreads();
   }
-  if (RKM == 1 && rk_bad) atomicOr(D.status, (unsigned)ST_BAD_STATE);
+  if (bad_state) atomicOr(D.status, (unsigned)ST_BAD_STATE);
   // block partial sum of R_rhou dV (fixed order)
   if (RKM != 1 && D.forcing) {
     double v = fsum;
@@ -1808,8 +1817,10 @@ __global__ void __launch_bounds__(256) k_rk(Desc D, int stage) {
 
 // Completion of a split update (bulk forcing, rk_point<true> in the flux
 // kernel): adds the reduced force to R_rhou and R_rhoE, stores them for the
-// next stage, updates rho u and rho E with the arithmetic of k_rk and checks
-// the new state (rho, rho v, rho w as written by the flux kernel).
+// next stage and updates rho u and rho E with the arithmetic of k_rk.  The
+// new state is checked where it is next read: by the flux kernel of the
+// next stage (every input point) or, after the last stage, by the next
+// step's flux kernel and by the diagnostics.
 template <int stage>
 __device__ __forceinline__ void rk_forced_block_s(const Desc& D, long long blk) {
   const double f = D.scal[SC_FORCE];
@@ -1823,7 +1834,6 @@ __device__ __forceinline__ void rk_forced_block_s(const Desc& D, long long blk) 
   const double dt = D.scal[SC_DT];
   long long n[kRkPer];
   double q0[kRkPer], q1[kRkPer], q4[kRkPer], r1[kRkPer], r4[kRkPer], p1[kRkPer], p4[kRkPer];
-  double o0[kRkPer], o2[kRkPer], o3[kRkPer];
 #pragma unroll
   for (int p = 0; p < kRkPer; ++p) {
     n[p] = (blk * kRkPer + p) * 256 + threadIdx.x;
@@ -1837,11 +1847,7 @@ __device__ __forceinline__ void rk_forced_block_s(const Desc& D, long long blk) 
       p1[p] = Rp[N + c];
       p4[p] = Rp[4 * N + c];
     }
-    o0[p] = wo[c];
-    o2[p] = wo[2 * N + c];
-    o3[p] = wo[3 * N + c];
   }
-  bool bad = false;
 #pragma unroll
   for (int p = 0; p < kRkPer; ++p) {
     if (n[p] >= D.N) continue;
@@ -1860,11 +1866,7 @@ __device__ __forceinline__ void rk_forced_block_s(const Desc& D, long long blk) 
     const double o4 = fma(dt, a4, q4[p]);
     wo[1 * N + n[p]] = o1;
     wo[4 * N + n[p]] = o4;
-    const double ke = 0.5 * (o1 * o1 + o2[p] * o2[p] + o3[p] * o3[p]) / o0[p];
-    const double pe = o4 - ke;
-    bad |= !(o0[p] > 0.0) || !(pe > 0.0) || !(fabs(o4) < 1e300);
   }
-  if (bad) atomicOr(D.status, (unsigned)ST_BAD_STATE);
 }
 
 __global__ void __launch_bounds__(256) k_rk_forced(Desc D, int stage) {

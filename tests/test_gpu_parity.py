@@ -258,6 +258,8 @@ def test_bad_state_is_reported(torch_cuda, forced):
     w0 = pr.w0.copy()
     w0[4, 3, 3, 3] = -1.0  # negative total energy -> negative pressure
     s = Solver(P.with_state(pr, w0))
+    d = s.diagnostics(raise_on_error=False)  # the state itself: p_min < 0
+    assert d["rc"] == -4 and d["status"] == 0 and d["p_min"] < 0
     s.advance(1, dt_fixed=1e-4)
     d = s.diagnostics(raise_on_error=False)
     assert d["rc"] == -4 and d["status"] != 0
