@@ -389,8 +389,9 @@ __device__ __forceinline__ void wflux(const PV<F>* nd, F f[5]) {
 // (the factor 1/2 of the splitting is applied once to the sum), and
 // scaling the inputs by 2 scales the smoothness indicators by exactly 4,
 // so the weights are those of the unscaled reconstruction.
+// The reconstruction is num / den; the caller divides.
 template <typename F>
-__device__ __forceinline__ F weno5(F vm2, F vm1, F v0, F vp1, F vp2, F eps4) {
+__device__ __forceinline__ void weno5(F vm2, F vm1, F v0, F vp1, F vp2, F eps4, F& num, F& den) {
   // candidate reconstructions, times 6 (the 1/6 is applied with the weights)
   const F q0 = F(2) * vm2 - F(7) * vm1 + F(11) * v0;
   const F q1 = -vm1 + F(5) * v0 + F(2) * vp1;
@@ -406,24 +407,22 @@ __device__ __forceinline__ F weno5(F vm2, F vm1, F v0, F vp1, F vp2, F eps4) {
   // 0.3 become 1, 6, 3): a = (t1 t2, 6 t0 t2, 3 t0 t1), one reciprocal
   const F t0 = s0 * s0, t1 = s1 * s1, t2 = s2 * s2;
   const F P = t1 * t2, B = F(3) * t1, C = F(6) * t2;
-  const F num = P * q0 + t0 * (C * q1 + B * q2);
-  const F den = P + t0 * (C + B);
-  return num * wrcp<F>(F(6) * den);
+  num = P * q0 + t0 * (C * q1 + B * q2);
+  den = F(6) * (P + t0 * (C + B));
 }
 
 // WENO3-JS (two candidate stencils, linear weights 1/3, 2/3) at i+1/2 from
 // v_{i-1..i+1}, same input scaling as weno5; numerator and denominator are
 // multiplied by 3 t0 t1 (a = (t1, 2 t0)) and the candidates by 2.
 template <typename F>
-__device__ __forceinline__ F weno3(F vm1, F v0, F vp1, F eps4) {
+__device__ __forceinline__ void weno3(F vm1, F v0, F vp1, F eps4, F& num, F& den) {
   const F q0 = F(3) * v0 - vm1;
   const F q1 = v0 + vp1;
   const F d0 = v0 - vm1, d1 = vp1 - v0;
   const F s0 = eps4 + d0 * d0, s1 = eps4 + d1 * d1;
   const F t0 = s0 * s0, t1 = s1 * s1;
-  const F num = t1 * q0 + F(2) * t0 * q1;
-  const F den = t1 + F(2) * t0;
-  return num * wrcp<F>(F(2) * den);
+  num = t1 * q0 + F(2) * t0 * q1;
+  den = F(2) * (t1 + F(2) * t0);
 }
 
 // WENO7-JS (four candidate stencils, linear weights (1, 12, 18, 4)/35) at
@@ -434,7 +433,7 @@ __device__ __forceinline__ F weno3(F vm1, F v0, F vp1, F eps4) {
 // candidates are multiplied by 12 and the weights formed with one
 // reciprocal each (a product form would overflow in FP32).
 template <typename F>
-__device__ __forceinline__ F weno7(const F* v, F eps4) {
+__device__ __forceinline__ void weno7(const F* v, F eps4, F& num, F& den) {
   const F a = v[0], b = v[1], d = v[2], e = v[3], f = v[4], g = v[5], h = v[6];
   const F q0 = F(-3) * a + F(13) * b - F(23) * d + F(25) * e;
   const F q1 = b - F(5) * d + F(13) * e + F(3) * f;
@@ -456,17 +455,27 @@ __device__ __forceinline__ F weno7(const F* v, F eps4) {
   const F s0 = eps4 + b0, s1 = eps4 + b1, s2 = eps4 + b2, s3 = eps4 + b3;
   const F w0 = wrcp<F>(s0 * s0), w1 = F(12) * wrcp<F>(s1 * s1);
   const F w2 = F(18) * wrcp<F>(s2 * s2), w3 = F(4) * wrcp<F>(s3 * s3);
-  const F num = w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3;
-  const F den = w0 + w1 + w2 + w3;
-  return num * wrcp<F>(F(12) * den);
+  num = w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3;
+  den = F(12) * (w0 + w1 + w2 + w3);
 }
 
-// Reconstruction of order 2R-1 at i+1/2 from v[0..2R-2] = v_{i-R+1..i+R-1}.
+// Reconstruction of order 2R-1 at i+1/2 from v[0..2R-2] = v_{i-R+1..i+R-1},
+// as num / den.
 template <typename F, int R>
-__device__ __forceinline__ F wrec(const F* v, F eps4) {
-  if constexpr (R == 2) return weno3<F>(v[0], v[1], v[2], eps4);
-  else if constexpr (R == 3) return weno5<F>(v[0], v[1], v[2], v[3], v[4], eps4);
-  else return weno7<F>(v, eps4);
+__device__ __forceinline__ void wrec(const F* v, F eps4, F& num, F& den) {
+  if constexpr (R == 2) weno3<F>(v[0], v[1], v[2], eps4, num, den);
+  else if constexpr (R == 3) weno5<F>(v[0], v[1], v[2], v[3], v[4], eps4, num, den);
+  else weno7<F>(v, eps4, num, den);
+}
+
+// Half the sum of the two reconstructions np/dp + nm/dm.  In FP64 with one
+// reciprocal, (np dm + nm dp) / (2 dp dm): the denominators are products of
+// up to four squared indicators (each at least the regulariser), so their
+// product stays far inside the FP64 range; FP32 takes one reciprocal each.
+template <typename F>
+__device__ __forceinline__ F half_sum(F np, F dp, F nm, F dm) {
+  if constexpr (sizeof(F) == 8) return (np * dm + nm * dp) * wrcp<F>(F(2) * (dp * dm));
+  else return F(0.5) * (np * wrcp<F>(dp) + nm * wrcp<F>(dm));
 }
 
 // Lax-Friedrichs split characteristic WENO flux of order 2R-1 at interface
@@ -479,6 +488,11 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
   constexpr int NS = 2 * R;
   constexpr int PN = 1 + DIR, P1 = 1 + (DIR + 1) % 3, P2 = 1 + (DIR + 2) % 3;
   const F gm1 = (F)D.gm1, gam = (F)D.gamma;
+  const F hgm1 = F(0.5) * gm1;
+  // pressure from the momentum and the velocity: (gamma-1)(E - m.u/2)
+  auto press = [&](F E, F m0, F u0, F m1, F u1, F m2, F u2) {
+    return gm1 * E - hgm1 * (m0 * u0 + m1 * u1 + m2 * u2);
+  };
   // Roe average of nodes i (s=R-1) and i+1 (s=R)
   F ur, vr, wr, Hr;
   {
@@ -490,8 +504,8 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
     const F una = (F)qa[PN] * ira, t1a = (F)qa[P1] * ira, t2a = (F)qa[P2] * ira;
     const F unb = (F)qb[PN] * irb, t1b = (F)qb[P1] * irb, t2b = (F)qb[P2] * irb;
     const F Ea = (F)qa[4], Eb = (F)qb[4];
-    const F pa = gm1 * (Ea - F(0.5) * ra * (una * una + t1a * t1a + t2a * t2a));
-    const F pb = gm1 * (Eb - F(0.5) * rb * (unb * unb + t1b * t1b + t2b * t2b));
+    const F pa = press(Ea, (F)qa[PN], una, (F)qa[P1], t1a, (F)qa[P2], t2a);
+    const F pb = press(Eb, (F)qb[PN], unb, (F)qb[P1], t1b, (F)qb[P2], t2b);
     const F Ha = (Ea + pa) * ira, Hb = (Eb + pb) * irb;
     const F sl = wsqrt<F>(ra), sr = wsqrt<F>(rb);
     const F iw = wrcp<F>(sl + sr);
@@ -531,7 +545,7 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
     const F ir = wrcp<F>(r);
     const F mn = (F)qd[PN], m1 = (F)qd[P1], m2 = (F)qd[P2], E = (F)qd[4];
     const F un = mn * ir, t1 = m1 * ir, t2 = m2 * ir;
-    const F p = gm1 * (E - F(0.5) * r * (un * un + t1 * t1 + t2 * t2));
+    const F p = press(E, mn, un, m1, t1, m2, t2);
     const F c = wsqrt<F>(gam * p * ir);
     const F wq[5] = {r, mn, m1, m2, E};
     const F fq[5] = {mn, mn * un + p, mn * t1, mn * t2, un * (E + p)};
@@ -554,7 +568,10 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
       vp[t] = g[t][k] + a * v[t][k];                    // i-R+1..i+R-1
       vm[t] = g[NS - 1 - t][k] - a * v[NS - 1 - t][k];  // i+R..i-R+2 (mirrored)
     }
-    gh[k] = F(0.5) * (wrec<F, R>(vp, eps4) + wrec<F, R>(vm, eps4));
+    F np, dp, nm, dm;
+    wrec<F, R>(vp, eps4, np, dp);
+    wrec<F, R>(vm, eps4, nm, dm);
+    gh[k] = half_sum<F>(np, dp, nm, dm);
   }
   // right eigenvectors applied to the reconstructed characteristic flux
   const F f0 = gh[0] + gh[1] + gh[4];
