@@ -1326,7 +1326,8 @@ __device__ __forceinline__ void rk_point(const Desc& D, int stage, double dt,
 // the instance is viscous.
 // RKM: 0 stores R for the update kernel; 1 (no bulk forcing) does the
 // point's RK update of stage rk_stage in the same pass; 2 (bulk forcing)
-// stores R and does the part of the update that does not involve the force.
+// stores R and does the part of the update that does not involve the force;
+// 3 chooses between 1 and 2 by the instance's forcing (batched instances).
 template <typename F, int TX, int TY, bool VISC_ON, int L, int RKM = 0>
 __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict__ w, double* __restrict__ R,
                          int lb, RhsSmem<F, TX, TY, L>& S, int rk_stage = -1) {
@@ -1414,8 +1415,8 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
     // split update: the previous update's result is checked here, once per
     // point (the block's own planes), with the test the update kernels
     // apply to their results
-    if constexpr (RKM == 2) {
-      if (valid && plane >= kb && plane < ke) {
+    if constexpr (RKM >= 2) {
+      if ((RKM == 2 || D.forcing) && valid && plane >= kb && plane < ke) {
         const double kq = 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
         bad_state |= !(q[0] > 0.0) || !(q[4] - kq > 0.0) || !(fabs(q[4]) < 1e300);
       }
@@ -1649,13 +1650,13 @@ __device__ __forceinline__ void rhs_body(const Desc& D, const double* __restrict
         Ra2[4] += (double)(o2.u * ax + o2.v * ay + o2.w * az);
       }
       const int no = nidx32(D, i, j, m2);
-      if constexpr (RKM == 1) {
+      if (RKM == 1 || (RKM == 3 && !D.forcing)) {
         rk_point<false>(D, rk_stage, dt_rk, w, no, Ra2, bad_state);
       } else {
 #pragma unroll
         for (int m = 0; m < 5; ++m) R[(size_t)m * N + no] = Ra2[m];
         fsum += Ra2[1] * D.y_eta[j];
-        if constexpr (RKM == 2) rk_point<true>(D, rk_stage, dt_rk, w, no, Ra2, bad_state);
+        if constexpr (RKM >= 2) rk_point<true>(D, rk_stage, dt_rk, w, no, Ra2, bad_state);
       }
     }
     if (c >= kb && c < ke && valid) {
@@ -1886,10 +1887,14 @@ __device__ __forceinline__ void rk_forced_block_s(const Desc& D, long long blk) 
   }
 }
 
+__device__ __forceinline__ void rk_forced_block(const Desc& D, int stage, long long blk) {
+  if (stage == 0) rk_forced_block_s<0>(D, blk);
+  else if (stage == 1) rk_forced_block_s<1>(D, blk);
+  else rk_forced_block_s<2>(D, blk);
+}
+
 __global__ void __launch_bounds__(256) k_rk_forced(Desc D, int stage) {
-  if (stage == 0) rk_forced_block_s<0>(D, blockIdx.x);
-  else if (stage == 1) rk_forced_block_s<1>(D, blockIdx.x);
-  else rk_forced_block_s<2>(D, blockIdx.x);
+  rk_forced_block(D, stage, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ time step
@@ -2368,7 +2373,10 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))
                                                   const BatchTable* __restrict__ T, int stage) {
   __shared__ RhsSmem<F, TX, TY, 2> S;
   BATCH_FOR(WK_RHS)
-  rhs_body<F, TX, TY, true, 2>(D, D.win[stage], D.rcur[stage], local, S);
+  // the 64x4 tiling does each instance's stage update here (whole, or the
+  // part without the force), as for a single instance
+  rhs_body<F, TX, TY, true, 2, (TX == 64 && TY == 4) ? 3 : 0>(D, D.win[stage], D.rcur[stage],
+                                                              local, S, stage);
   BATCH_END
 }
 
@@ -2381,11 +2389,15 @@ __global__ void __launch_bounds__(256) k_b_force(const Desc* __restrict__ descs,
   }
 }
 
+// fused: the right-hand-side kernel did the update (64x4 tiling); only the
+// completion of forced instances remains
 __global__ void __launch_bounds__(256) k_b_rk(const Desc* __restrict__ descs,
-                                              const BatchTable* __restrict__ T, int stage) {
+                                              const BatchTable* __restrict__ T, int stage,
+                                              int fused) {
   __shared__ double sm[8];
   BATCH_FOR(WK_RK)
-  rk_block(D, stage, local, sm);
+  if (!fused) rk_block(D, stage, local, sm);
+  else if (D.forcing) rk_forced_block(D, stage, local);
   BATCH_END
 }
 
@@ -2420,7 +2432,7 @@ hipError_t launch_batch_phase(int phase, const Desc* d, const BatchTable* t, int
       return precision == 1 ? launch_b_rhs<float>(d, t, stage, tx, ty, st)
                             : launch_b_rhs<double>(d, t, stage, tx, ty, st);
     case BPH_FORCE: k_b_force<<<kMaxSlots, 256, 0, st>>>(d, t); break;
-    case BPH_RK: k_b_rk<<<4096, 256, 0, st>>>(d, t, stage); break;
+    case BPH_RK: k_b_rk<<<4096, 256, 0, st>>>(d, t, stage, tx == 64 && ty == 4 ? 1 : 0); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
