@@ -548,9 +548,16 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
     const F p = press(E, mn, un, m1, t1, m2, t2);
     const F c = wsqrt<F>(gam * p * ir);
     const F wq[5] = {r, mn, m1, m2, E};
-    const F fq[5] = {mn, mn * un + p, mn * t1, mn * t2, un * (E + p)};
     project(wq, v[s]);
-    project(fq, g[s]);
+    // the flux is f = u_n w + p (0, 1, 0, 0, u_n), so its projection is
+    // u_n (L w) + p L(0, 1, 0, 0, u_n), whose rows are p (X + Y, -2 X,
+    // 0, 0, X - Y) with X = b1 (u_n - u)/2 and Y = -1/(2c)
+    const F pX = p * (hb1 * (un - ur)), pY = p * hic;
+    g[s][0] = un * v[s][0] + (pX - pY);
+    g[s][1] = un * v[s][1] - F(2) * pX;
+    g[s][2] = un * v[s][2];
+    g[s][3] = un * v[s][3];
+    g[s][4] = un * v[s][4] + (pX + pY);
     am0 = fmax(am0, fabs(un - c));
     am1 = fmax(am1, fabs(un));
     am4 = fmax(am4, fabs(un + c));
