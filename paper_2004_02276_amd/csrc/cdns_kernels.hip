@@ -2153,9 +2153,10 @@ hipError_t launch_iflags(const Desc& D, hipStream_t st) {
 }
 
 hipError_t launch_weno(const Desc& D, int stage, hipStream_t st) {
-  // a few passes per block: fewer, longer-lived blocks (the FP64 WENO5
-  // kernel, at three waves per SIMD, measured fastest with 512 per direction)
-  const long long cap = (D.precision == 0 && D.wr == 3) ? 512 : 1024;
+  // a few passes per block: fewer, longer-lived blocks (the WENO5 kernels,
+  // at three (FP64) and four (FP32) waves per SIMD, measured fastest with
+  // 512 per direction)
+  const long long cap = D.wr == 3 ? 512 : 1024;
   long long b = nblk(D.N, 256);
   if (b > cap) b = cap;
   dim3 grid((unsigned)b, 3);
