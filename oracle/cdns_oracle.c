@@ -120,8 +120,8 @@ static inline size_t uidx(const geom* g, int i, int j, int k) {
 typedef struct { double rho, u, v, w, p, T, Ht, mu; } prim_t;
 
 static prim_t to_prim(const ora_problem* P, const geom* g, const double q[5]) {
-  /* evaluation order shared with the GPU library's FP64 path (both without
-   * contraction): one reciprocal of the density, then products */
+  /* one reciprocal of the density, then products; T from the internal
+   * energy per unit mass, p from the gas law, H = E + p/rho */
   prim_t s;
   double ir = 1.0 / q[0];
   s.rho = q[0];
@@ -709,51 +709,47 @@ static void interface_flags(const ora_problem* P, work_t* a) {
 
 /* Energy-preserving central flux of order 2L at interface i+1/2, node i at
  * padded index q, stride s along the direction d (eq. encflux):
- * f = 2 sum_{l=1}^{L} a_l sum_{m=0}^{l-1} avg(rho, u_n, phi)_{i-m,l}, with
- * phi = 1, u, v, w, H.  The pressure term of the momentum equation is put
- * in the same conservative form with two-point averages,
- * 2 sum_l a_l sum_m (p_{i-m} + p_{i-m+l})/2.  Output in natural order;
- * conv/pres select the two parts (both for the full operator).
- *
- * Evaluation order (fixed, so that results can be compared bit for bit at
- * low Mach number, where the residual is a small difference of large
- * fluxes): the pairs (i-m, i-m+l) are taken with l ascending and m
- * ascending within l; per pair t the mass-flux factor M_t = (2 a_l)
- * (1/8)(rho_a + rho_b)(u_a + u_b); per component f = M_0 (phi_a + phi_b)_0,
- * then f = fma(M_t, (phi_a + phi_b)_t, f) for the following pairs; the
- * pressure part a_l (p_a + p_b) accumulated the same way. */
+ *   f = 2 sum_{l=1}^{L} a_l sum_{m=0}^{l-1} avg(rho, u_n, phi)_{i-m,l},
+ * phi = 1, u, v, w, H, with the average operator of eq. avg_operator,
+ *   avg(F, G, H)_{i,l} = (1/8)(F_i + F_{i+l})(G_i + G_{i+l})(H_i + H_{i+l}).
+ * The pressure term of the momentum equation is put in the same
+ * conservative form with two-point averages,
+ *   2 sum_l a_l sum_m (p_{i-m} + p_{i-m+l})/2.
+ * Written out as the formula reads: each average is the product of its
+ * three pair sums times 1/8, taken left to right; the inner sum runs over
+ * m ascending, the outer over l ascending, plain additions throughout (the
+ * file is compiled without contraction).  Output in natural component
+ * order; conv/pres select the two parts (both for the full operator). */
 static void central_flux(const work_t* a, size_t q, size_t s, int d, int conv, int pres,
                          double f[5]) {
   const double* un = d == 0 ? a->u : (d == 1 ? a->v : a->w);
   const double* r = a->rho;
   const double* phis[5] = {NULL, a->u, a->v, a->w, a->Ht};
   const int L = a->g.L;
-  /* pairs (i-m, i-m+l), l = 1..L, m = 0..l-1 */
-  size_t pa[6], pb[6];
-  double al[6];
-  int np = 0;
-  for (int l = 1; l <= L; ++l)
-    for (int m = 0; m < l; ++m) {
-      pa[np] = q - (size_t)m * s;
-      pb[np] = q + (size_t)(l - m) * s;
-      al[np] = ACOEF[L][l - 1];
-      ++np;
-    }
-  double M[6];
-  for (int t = 0; t < np; ++t)
-    M[t] = (2.0 * al[t]) * (0.125 * (r[pa[t]] + r[pb[t]]) * (un[pa[t]] + un[pb[t]]));
   for (int c = 0; c < 5; ++c) {
-    double sum[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int t = 0; t < np; ++t)
-      sum[t] = c == 0 ? 2.0 : phis[c][pa[t]] + phis[c][pb[t]];
-    double acc = M[0] * sum[0];
-    for (int t = 1; t < np; ++t) acc = fma(M[t], sum[t], acc);
-    f[c] = conv ? acc : 0.0;
+    double outer = 0.0;
+    for (int l = 1; l <= L; ++l) {
+      double inner = 0.0;
+      for (int m = 0; m < l; ++m) {
+        size_t ia = q - (size_t)m * s, ib = q + (size_t)(l - m) * s;
+        double phi_sum = c == 0 ? 1.0 + 1.0 : phis[c][ia] + phis[c][ib];
+        inner += 0.125 * (r[ia] + r[ib]) * (un[ia] + un[ib]) * phi_sum;
+      }
+      outer += ACOEF[L][l - 1] * inner;
+    }
+    f[c] = conv ? 2.0 * outer : 0.0;
   }
   if (pres) {
-    double acc = al[0] * (a->p[pa[0]] + a->p[pb[0]]);
-    for (int t = 1; t < np; ++t) acc = fma(al[t], a->p[pa[t]] + a->p[pb[t]], acc);
-    f[1 + d] += acc;
+    double outer = 0.0;
+    for (int l = 1; l <= L; ++l) {
+      double inner = 0.0;
+      for (int m = 0; m < l; ++m) {
+        size_t ia = q - (size_t)m * s, ib = q + (size_t)(l - m) * s;
+        inner += (a->p[ia] + a->p[ib]) / 2.0;
+      }
+      outer += ACOEF[L][l - 1] * inner;
+    }
+    f[1 + d] += 2.0 * outer;
   }
 }
 

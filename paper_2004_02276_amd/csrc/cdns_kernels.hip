@@ -297,50 +297,69 @@ __device__ __forceinline__ void central_flux(const PV<F>* nd, F f[5]) {
   f[1 + DIR] += pf;
 }
 
-// FP64 version in a fixed evaluation order without contraction: per pair
-// the mass-flux factor M = (2 a_l)(1/8)(rho_a + rho_b)(u_a + u_b), each
-// component M_0 (phi_a + phi_b)_0 followed by fused multiply-adds of the
-// later pairs, the pressure part sum a_l (p_a + p_b) the same way.
+// Pressure part of the central flux, 2 sum_l a_l sum_m (p_{i-m} + p_{i-m+l})/2,
+// in FP64 without contraction, m ascending inside l, l ascending.
+template <int L>
+__device__ __forceinline__ double comp_pressure_f64(const PV<double>* nd) {
+#pragma clang fp contract(off)
+  double outer = 0.0;
+#pragma unroll
+  for (int l = 1; l <= L; ++l) {
+    double inner = 0.0;
+#pragma unroll
+    for (int m = 0; m < l; ++m) {
+      const double term = (nd[L - 1 - m].p + nd[L - 1 - m + l].p) * 0.5;
+      inner = m == 0 ? term : inner + term;
+    }
+    outer = l == 1 ? coef_a(L, 1) * inner : outer + coef_a(L, l) * inner;
+  }
+  return 2.0 * outer;
+}
+
+// FP64 version, evaluated as eq. encflux reads, without contraction: per
+// pair (l, m) the average (1/8)(rho_a + rho_b)(u_a + u_b)(phi_a + phi_b),
+// taken left to right (its first two factors are shared by the five
+// components); the averages summed over m ascending, each inner sum
+// weighted by a_l and summed over l ascending, the total doubled; the
+// pressure part 2 sum_l a_l sum_m (p_a + p_b)/2 the same way.
 template <int DIR, int L>
 __device__ __forceinline__ void central_flux_f64(const PV<double>* nd, double f[5]) {
 #pragma clang fp contract(off)
   constexpr int NP = L * (L + 1) / 2;
   double M[NP];
-  int ia[NP], ib[NP];
-  double al[NP];
   {
     int t = 0;
 #pragma unroll
     for (int l = 1; l <= L; ++l)
 #pragma unroll
       for (int m = 0; m < l; ++m, ++t) {
-        ia[t] = L - 1 - m;
-        ib[t] = L - 1 - m + l;
-        al[t] = coef_a(L, l);
+        const PV<double>& A = nd[L - 1 - m];
+        const PV<double>& B = nd[L - 1 - m + l];
+        M[t] = 0.125 * (A.r + B.r) * (normal_vel<DIR>(A) + normal_vel<DIR>(B));
       }
   }
-#pragma unroll
-  for (int t = 0; t < NP; ++t) {
-    const PV<double>& A = nd[ia[t]];
-    const PV<double>& B = nd[ib[t]];
-    M[t] = (2.0 * al[t]) * (0.125 * (A.r + B.r) * (normal_vel<DIR>(A) + normal_vel<DIR>(B)));
-  }
-  // one component at a time, pairs in order
+  // 2 sum_l a_l sum_m M_t (phi_a + phi_b)_t for one component
   auto comp = [&](auto phi) {
-    double acc = M[0] * phi(nd[ia[0]], nd[ib[0]]);
+    double outer = 0.0;
+    int t = 0;
 #pragma unroll
-    for (int t = 1; t < NP; ++t) acc = fma(M[t], phi(nd[ia[t]], nd[ib[t]]), acc);
-    return acc;
+    for (int l = 1; l <= L; ++l) {
+      double inner = 0.0;
+#pragma unroll
+      for (int m = 0; m < l; ++m, ++t) {
+        const double term = M[t] * phi(nd[L - 1 - m], nd[L - 1 - m + l]);
+        inner = m == 0 ? term : inner + term;
+      }
+      outer = l == 1 ? coef_a(L, 1) * inner : outer + coef_a(L, l) * inner;
+    }
+    return 2.0 * outer;
   };
   f[0] = comp([](const PV<double>&, const PV<double>&) { return 2.0; });
   f[1] = comp([](const PV<double>& A, const PV<double>& B) { return A.u + B.u; });
   f[2] = comp([](const PV<double>& A, const PV<double>& B) { return A.v + B.v; });
   f[3] = comp([](const PV<double>& A, const PV<double>& B) { return A.w + B.w; });
   f[4] = comp([](const PV<double>& A, const PV<double>& B) { return A.h + B.h; });
-  double pf = al[0] * (nd[ia[0]].p + nd[ib[0]].p);
-#pragma unroll
-  for (int t = 1; t < NP; ++t) pf = fma(al[t], nd[ia[t]].p + nd[ib[t]].p, pf);
-  f[1 + DIR] = f[1 + DIR] + pf;
+  f[1 + DIR] = f[1 + DIR] + comp_pressure_f64<L>(nd);
 }
 
 // Pressure-only flux at a staggered wall (convective fluxes vanish there).
@@ -361,15 +380,8 @@ __device__ __forceinline__ void wall_flux(const PV<F>* nd, F f[5]) {
 
 template <int DIR, int L>
 __device__ __forceinline__ void wall_flux_f64(const PV<double>* nd, double f[5]) {
-#pragma clang fp contract(off)
   f[0] = f[1] = f[2] = f[3] = f[4] = 0.0;
-  double pf = coef_a(L, 1) * (nd[L - 1].p + nd[L].p);
-#pragma unroll
-  for (int l = 1; l <= L; ++l)
-#pragma unroll
-    for (int m = 0; m < l; ++m)
-      if (l > 1 || m > 0) pf = fma(coef_a(L, l), nd[L - 1 - m].p + nd[L - 1 - m + l].p, pf);
-  f[1 + DIR] = pf;
+  f[1 + DIR] = comp_pressure_f64<L>(nd);
 }
 
 // Dispatch: FP64 uses the fixed-order forms above.  nd points at node i-L+1.
