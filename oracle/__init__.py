@@ -7,18 +7,24 @@ literal formulas of the paper) and shares no code with the GPU path.  Both
 sides receive the same seeded inputs from the `problems` package.
 
 Parity status: every operator is pinned by CPU tests against closed forms,
-invariants or exact solutions (see tests/test_oracle_*.py); the
-characteristic outflow boundary is pinned only by a behaviour check
-(acoustic pulse reflection), so it is "parity unpinned" against the paper;
-the digital-filter inflow generator is pinned by the published SplitMix64
-reference outputs and by its statistics (unit variance of the filtered
-field, prescribed Reynolds stresses, filter and time correlations), its
-constants are readings (the paper gives the method only).  The scheme-order
-variants (central order 2L for L = 1, 2, 3; WENO order 2r - 1 for r = 2, 3,
-4) are pinned in tests/test_oracle_orders.py by Taylor-derived weights,
-polynomial definitions of the WENO candidates and indicators, design-order
-convergence, conservation and kinetic-energy identities and the exact Sod
-solution.
+invariants or exact solutions (see tests/test_oracle_*.py).  The
+characteristic Lax-Friedrichs WENO flux is pinned by its reduction to the
+scalar reconstruction for an entropy wave, exact stationary contacts,
+design-order convergence with WENO at every interface, splitting constants
+against independently computed Jacobian eigenvalues and its exact stencil
+(tests/test_oracle_pins_flux.py); the wall and imposed-shock ghost nodes by
+their closed forms and by the equivalent mirrored periodic domain; the
+volume totals by plain sums.  The characteristic outflow boundary is pinned
+only by a behaviour check (acoustic pulse reflection), so it is "parity
+unpinned" against the paper; the digital-filter inflow generator is pinned
+by the published SplitMix64 reference outputs and by its statistics (unit
+variance of the filtered field, prescribed Reynolds stresses, filter and
+time correlations), its constants are readings (the paper gives the method
+only).  The scheme-order variants (central order 2L for L = 1, 2, 3; WENO
+order 2r - 1 for r = 2, 3, 4) are pinned in tests/test_oracle_orders.py by
+Taylor-derived weights, polynomial definitions of the WENO candidates and
+indicators, design-order convergence, conservation and kinetic-energy
+identities and the exact Sod solution.
 """
 from __future__ import annotations
 
@@ -114,6 +120,11 @@ def _load():
         lib.ora_df_update.argtypes = [pp, ctypes.c_uint64, ctypes.c_double, ctypes.c_int, dp, dp,
                                       dp]
         lib.ora_df_update.restype = ctypes.c_int
+        lib.ora_ghosts_y.argtypes = [pp, dp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int)]
+        lib.ora_ghosts_y.restype = ctypes.c_int
+        lib.ora_lf_alpha.argtypes = [pp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, dp]
+        lib.ora_lf_alpha.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -283,6 +294,35 @@ def iface_flux(pr, d: int, w: Optional[np.ndarray] = None) -> np.ndarray:
     out = np.zeros((5, pr.nz, pr.ny, pr.nx))
     m = _Marshalled(pr)
     _check(lib.ora_iface_flux(ctypes.byref(m.s), _dptr(w), int(d), _dptr(out)), "ora_iface_flux")
+    return out
+
+
+def ghosts_y(pr, face: int, w: Optional[np.ndarray] = None):
+    """Ghost layers of y face `face` (2: y-, 3: y+) as filled for the
+    right-hand side: array (5, hw, nz, nx + 2 hw), layer s-1 = ghost s,
+    x index offset by hw."""
+    lib = _load()
+    w = np.ascontiguousarray(pr.w0 if w is None else w, dtype=np.float64)
+    hw_max = 4
+    buf = np.zeros(5 * hw_max * pr.nz * (pr.nx + 2 * hw_max))
+    hw = ctypes.c_int(0)
+    m = _Marshalled(pr)
+    st = lib.ora_ghosts_y(ctypes.byref(m.s), _dptr(w), int(face), _dptr(buf), ctypes.byref(hw))
+    if st not in (ORA_OK, ORA_ESTATE):
+        _check(st, "ora_ghosts_y")
+    h = hw.value
+    return buf[:5 * h * pr.nz * (pr.nx + 2 * h)].reshape(5, h, pr.nz, pr.nx + 2 * h)
+
+
+def lf_alpha(pr, d: int, i: int, j: int, k: int, w: Optional[np.ndarray] = None) -> np.ndarray:
+    """Lax-Friedrichs splitting constants (waves u-c, u, u, u, u+c) of the
+    shock-capturing flux at interface i+1/2 of direction d."""
+    lib = _load()
+    w = np.ascontiguousarray(pr.w0 if w is None else w, dtype=np.float64)
+    out = np.zeros(5)
+    m = _Marshalled(pr)
+    _check(lib.ora_lf_alpha(ctypes.byref(m.s), _dptr(w), int(d), int(i), int(j), int(k),
+                            _dptr(out)), "ora_lf_alpha")
     return out
 
 

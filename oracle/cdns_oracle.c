@@ -753,13 +753,31 @@ static void central_flux(const work_t* a, size_t q, size_t s, int d, int conv, i
   }
 }
 
+/* Splitting constants of the local Lax-Friedrichs flux at interface i+1/2
+ * (Sec. 2.1): for each characteristic field k (wave order u_n - c, u_n,
+ * u_n, u_n, u_n + c) the largest |lambda_k| over the 2r stencil nodes
+ * i-r+1..i+r, with the sound speed of each node. */
+static void lf_alpha(const ora_problem* P, const work_t* a, size_t q, size_t s, int d,
+                     double alpha[5]) {
+  const double* un_all = d == 0 ? a->u : (d == 1 ? a->v : a->w);
+  const int rw = a->g.r;
+  for (int k = 0; k < 5; ++k) alpha[k] = 0.0;
+  for (int t = 0; t < 2 * rw; ++t) {
+    size_t qs = q + (size_t)((long)(t - rw + 1) * (long)s);
+    double un = un_all[qs];
+    double cs = sqrt(P->gamma * a->p[qs] / a->rho[qs]);
+    double lam[5] = {fabs(un - cs), fabs(un), fabs(un), fabs(un), fabs(un + cs)};
+    for (int k = 0; k < 5; ++k)
+      if (lam[k] > alpha[k]) alpha[k] = lam[k];
+  }
+}
+
 /* Shock-capturing flux at interface i+1/2 (Sec. 2.1): Lax-Friedrichs flux
  * vector splitting of the characteristic fields, each split flux
  * reconstructed with the WENO scheme of order 2r - 1 (the positive part
  * from cells i-r+1..i+r-1, the negative part mirrored about the interface
  * from cells i+r..i-r+2).  Eigenvectors at the Roe average of nodes i and
- * i+1; splitting constant per field = max |eigenvalue| over the 2r stencil
- * nodes i-r+1..i+r (local Lax-Friedrichs). */
+ * i+1; splitting constants from lf_alpha (local Lax-Friedrichs). */
 static void weno_flux(const ora_problem* P, const work_t* a, size_t q, size_t s, int d,
                       double f[5]) {
   int pm[5];
@@ -775,24 +793,24 @@ static void weno_flux(const ora_problem* P, const work_t* a, size_t q, size_t s,
   double croe = sqrt((P->gamma - 1.0) * (Hroe - 0.5 * q2));
   double Rm[5][5], Lm[5][5];
   eigvecs_perm(P->gamma - 1.0, uroe[d], uroe[(d + 1) % 3], uroe[(d + 2) % 3], Hroe, croe, Rm, Lm);
-  /* stencil values, node i-r+1+t */
+  double alpha[5];
+  lf_alpha(P, a, q, s, d, alpha);
+  /* characteristic projections of the state and of the Euler flux (with
+   * pressure) at the stencil nodes, node i-r+1+t */
   const int rw = a->g.r, ns = 2 * rw;
-  double gp[8][5], gmn[8][5], alpha[5] = {0, 0, 0, 0, 0};
+  double gp[8][5], gmn[8][5];
   double vch[8][5], gch[8][5];
   for (int t = 0; t < ns; ++t) {
     size_t qs = q + (size_t)((long)(t - rw + 1) * (long)s);
     double wn[5], fn[5];
     for (int c = 0; c < 5; ++c) wn[c] = a->W[pm[c]][qs];
     double un = vel[d][qs];
-    double cs = sqrt(P->gamma * a->p[qs] / a->rho[qs]);
     fn[0] = a->rho[qs] * un;
     fn[1] = a->rho[qs] * un * un + a->p[qs];
     fn[2] = a->rho[qs] * un * vel[(d + 1) % 3][qs];
     fn[3] = a->rho[qs] * un * vel[(d + 2) % 3][qs];
     fn[4] = un * (a->W[4][qs] + a->p[qs]);
-    double lam[5] = {fabs(un - cs), fabs(un), fabs(un), fabs(un), fabs(un + cs)};
     for (int k = 0; k < 5; ++k) {
-      if (lam[k] > alpha[k]) alpha[k] = lam[k];
       double av = 0.0, ag = 0.0;
       for (int c = 0; c < 5; ++c) { av += Lm[k][c] * wn[c]; ag += Lm[k][c] * fn[c]; }
       vch[t][k] = av;
@@ -1231,6 +1249,50 @@ int ora_iface_flux(const ora_problem* P, const double* w, int d, double* out) {
         if (wall_hi && id[d] == n[d] - 1) central_flux(&a, q, stv[d], d, 0, 1, f);
         for (int c = 0; c < 5; ++c) out[(size_t)c * N + uidx(g, i, j, k)] = f[c];
       }
+  work_free(&a);
+  return ORA_OK;
+}
+
+/* Test hook: the ghost layers of a y face (2: y-, 3: y+) as filled for the
+ * right-hand side, out[5][hw][nz][nx + 2 hw] (conserved variables; layer
+ * s-1 holds ghost s, i.e. row -s below or row ny-1+s above, over the
+ * x-extended range i = -hw..nx+hw-1); *hw_out receives hw. */
+int ora_ghosts_y(const ora_problem* P, const double* w, int face, double* out, int* hw_out) {
+  int st = validate(P);
+  if (st) return st;
+  if (face != 2 && face != 3) return ORA_EINVAL;
+  work_t a;
+  if (work_alloc(P, &a)) return ORA_ENOMEM;
+  st = prepare(P, w, &a);
+  if (st == ORA_EUNSUP) { work_free(&a); return st; }
+  const geom* g = &a.g;
+  const int hw = g->hw, nxe = g->nx + 2 * hw;
+  for (int m = 0; m < 5; ++m)
+    for (int s = 1; s <= hw; ++s)
+      for (int k = 0; k < g->nz; ++k)
+        for (int i = -hw; i < g->nx + hw; ++i) {
+          int j = face == 2 ? -s : g->ny - 1 + s;
+          out[(((size_t)m * hw + (s - 1)) * g->nz + k) * nxe + (i + hw)] = a.W[m][pidx(g, i, j, k)];
+        }
+  *hw_out = hw;
+  work_free(&a);
+  return st;
+}
+
+/* Test hook: the Lax-Friedrichs splitting constants used by the
+ * shock-capturing flux at interface i+1/2 of direction d (node (i, j, k)). */
+int ora_lf_alpha(const ora_problem* P, const double* w, int d, int i, int j, int k,
+                 double* alpha) {
+  int st = validate(P);
+  if (st) return st;
+  if (d < 0 || d > 2 || i < 0 || i >= P->nx || j < 0 || j >= P->ny || k < 0 || k >= P->nz)
+    return ORA_EINVAL;
+  work_t a;
+  if (work_alloc(P, &a)) return ORA_ENOMEM;
+  st = prepare(P, w, &a);
+  if (st) { work_free(&a); return st; }
+  size_t stv[3] = {1, (size_t)a.g.nxp, (size_t)a.g.nxp * a.g.nyp};
+  lf_alpha(P, &a, pidx(&a.g, i, j, k), stv[d], d, alpha);
   work_free(&a);
   return ORA_OK;
 }
