@@ -109,6 +109,8 @@ def _load():
         lib.ora_eigenvectors.restype = None
         lib.ora_totals.argtypes = [pp, dp, dp]
         lib.ora_totals.restype = ctypes.c_int
+        lib.ora_extrema.argtypes = [pp, dp, dp]
+        lib.ora_extrema.restype = ctypes.c_int
         lib.ora_iface_flux.argtypes = [pp, dp, ctypes.c_int, dp]
         lib.ora_iface_flux.restype = ctypes.c_int
         lib.ora_num_threads.argtypes = []
@@ -283,6 +285,16 @@ def totals(pr, w: np.ndarray) -> np.ndarray:
     out = np.zeros(6)
     m = _Marshalled(pr)
     _check(lib.ora_totals(ctypes.byref(m.s), _dptr(w), _dptr(out)), "ora_totals")
+    return out
+
+
+def extrema(pr, w: np.ndarray) -> np.ndarray:
+    """(min rho, min p, max Mach, number of non-finite conserved values)."""
+    lib = _load()
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    out = np.zeros(4)
+    m = _Marshalled(pr)
+    _check(lib.ora_extrema(ctypes.byref(m.s), _dptr(w), _dptr(out)), "ora_extrema")
     return out
 
 

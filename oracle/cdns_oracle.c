@@ -1181,6 +1181,40 @@ int ora_totals(const ora_problem* P, const double* w, double* out6) {
   return ORA_OK;
 }
 
+/* Extrema of the state: out4 = {min rho, min p, max |u|/c, number of
+ * non-finite conserved values}, with the primitives of the perfect gas
+ * (Sec. 2) and the sound speed c = sqrt(gamma p / rho).  Points holding a
+ * non-finite value are counted and left out of the extrema. */
+int ora_extrema(const ora_problem* P, const double* w, double* out4) {
+  geom g;
+  make_geom(P, &g);
+  size_t N = (size_t)g.nx * g.ny * g.nz;
+  double rmin = INFINITY, pmin = INFINITY, mmax = 0.0, bad = 0.0;
+  for (size_t n = 0; n < N; ++n) {
+    double q[5];
+    int fin = 1;
+    for (int m = 0; m < 5; ++m) {
+      q[m] = w[m * N + n];
+      if (!isfinite(q[m])) {
+        bad += 1.0;
+        fin = 0;
+      }
+    }
+    if (!fin) continue;
+    prim_t s = to_prim(P, &g, q);
+    if (s.rho < rmin) rmin = s.rho;
+    if (s.p < pmin) pmin = s.p;
+    double c = sqrt(P->gamma * s.p / s.rho);
+    double mach = sqrt(s.u * s.u + s.v * s.v + s.w * s.w) / c;
+    if (mach > mmax) mmax = mach;
+  }
+  out4[0] = rmin;
+  out4[1] = pmin;
+  out4[2] = mmax;
+  out4[3] = bad;
+  return ORA_OK;
+}
+
 /* Running statistics (the quantities behind the mean profiles and stresses
  * of Sec. 4): for every (i, j) column, the spanwise sums (k ascending) of
  * rho, rho u, rho v, rho w, rho u u, rho v v, rho w w, rho u v, u, u u, T,

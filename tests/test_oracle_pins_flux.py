@@ -343,3 +343,40 @@ def test_totals_are_volume_sums():
     tot = oracle.totals(pr, w)
     assert np.abs(tot - np.array(ref)).max() <= 1e-12 * np.abs(ref).max()
     assert abs(tot[0] - np.sum(w[0] * dv)) <= 1e-13 * tot[0]
+
+
+def test_extrema_closed_form():
+    """Minimum density and pressure and maximum Mach number of a field whose
+    extrema sit at known nodes with known values: rho = 1 + 0.4 cos(x)
+    cos(y) cos(z) reaches 0.6 at the node (pi, 0, 0), p = (1 - 0.3 sin^2 ...)
+    / gamma, and a single node moves at u = 2.5 c where everything else is
+    subsonic; non-finite conserved values are counted one by one and kept
+    out of the extrema."""
+    g = 1.4
+    n = 16
+    pr = P.taylor_green(n)
+    x = np.arange(n) * (2 * np.pi / n)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    rho = 1.0 + 0.4 * np.cos(X) * np.cos(Y) * np.cos(Z)
+    p = (1.0 - 0.3 * np.sin(X) ** 2 * np.sin(Z) ** 2) / g   # min 0.7/g at sin = +-1
+    c = np.sqrt(g * p / rho)
+    u = 0.2 * c * np.sin(Y)
+    v = np.zeros_like(u)
+    ww = np.zeros_like(u)
+    u[3, 5, 7] = 2.5 * c[3, 5, 7]
+    w = P.conserved_from_primitive(rho, u, v, ww, p, pr.gamma)
+    assert pr.gamma == g
+    ex = oracle.extrema(pr, w)
+    assert abs(ex[0] - 0.6) <= 1e-15
+    assert abs(ex[1] - 0.7 / g) <= 1e-15
+    assert abs(ex[2] - 2.5) <= 1e-13
+    assert ex[3] == 0
+    # poison two points: three non-finite values, the extrema unchanged
+    w2 = w.copy()
+    w2[0, 8, 0, 0] = 0.1           # a low density at a point whose energy is infinite
+    w2[4, 8, 0, 0] = np.inf
+    w2[2, 1, 1, 1] = -np.inf
+    w2[3, 1, 1, 1] = np.nan
+    ex2 = oracle.extrema(pr, w2)
+    assert ex2[3] == 3
+    assert abs(ex2[0] - 0.6) <= 1e-15 and abs(ex2[1] - 0.7 / g) <= 1e-15 and abs(ex2[2] - 2.5) <= 1e-13
