@@ -237,6 +237,27 @@ cdns_status cdns_advance_n(cdns_ctx* ctx, int32_t n, double cfl, double dt_fixed
  * p_min <= 0 or non-finite values. */
 cdns_status cdns_diagnostics(cdns_ctx* ctx, cdns_diag* out);
 
+/* For callers that cannot allocate memory or synchronise (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the volume integrals and extrema of cdns_diagnostics, computed on the
+ * device and written to the device array out_dev[CDNS_NDIAG_DEV] in the
+ * order of the CDNS_DV_* slots (the non-finite count as a double).  w_dev is
+ * a device state [5][nz][ny][nx] of the context's grid, or NULL for the
+ * context's state array.  Enqueued on the context's stream; no host
+ * synchronisation, no allocation, no use of the context's workspace.  The
+ * per-block partial sums live in one static device array per GPU (8192
+ * blocks x 16 doubles = 1 MiB, one block per 4096 points), held until the
+ * process ends: grids of more than CDNS_NOALLOC_MAX_POINTS points return
+ * CDNS_EINVAL.  All calls on one GPU share that array, so calls that overlap
+ * in time on one GPU (different streams, or different host threads) race;
+ * calls ordered on one stream do not.  The sums are grouped differently from
+ * cdns_diagnostics (rounding differs in the last bits; extrema and counts are
+ * identical).  Status checks of the state are left to the caller. */
+enum { CDNS_DV_MASS = 0, CDNS_DV_MOMX, CDNS_DV_MOMY, CDNS_DV_MOMZ, CDNS_DV_ENERGY, CDNS_DV_KINETIC,
+       CDNS_DV_RHOMIN, CDNS_DV_PMIN, CDNS_DV_MACHMAX, CDNS_DV_NONFINITE, CDNS_NDIAG_DEV };
+#define CDNS_NOALLOC_MAX_POINTS 33554432LL
+cdns_status cdns_diagnostics_noalloc(cdns_ctx* ctx, const double* w_dev, double* out_dev);
+
 /* Running statistics for mean profiles and turbulent stresses (the
  * quantities of Sec. 4's validation figures; the paper does not describe
  * how they are gathered).  cdns_stats_accumulate adds, for every (i, j)

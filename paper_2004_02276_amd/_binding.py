@@ -19,12 +19,17 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -
 CDNS_FP64, CDNS_FP32_FLUX = 0, 1
 PHASES = ["dt", "ghosts", "sensor", "iflags", "weno", "rhs", "force", "rk"]
 NSTAT = 16  # running-statistics products (CDNS_NSTAT)
+NDIAG_DEV = 10  # slots of cdns_diagnostics_noalloc's output (CDNS_NDIAG_DEV)
+DIAG_DEV_NAMES = ["mass", "mom_x", "mom_y", "mom_z", "energy", "kinetic", "rho_min", "p_min",
+                  "mach_max", "nonfinite"]
+NOALLOC_MAX_POINTS = 33554432  # CDNS_NOALLOC_MAX_POINTS
 
 EXPORTED = [
     "cdns_version", "cdns_workspace_bytes", "cdns_create", "cdns_set_bc", "cdns_set_tiling",
     "cdns_set_scheme", "cdns_set_state", "cdns_get_state", "cdns_export_flags",
     "cdns_import_flags",
-    "cdns_rhs", "cdns_rk_step", "cdns_advance_n", "cdns_diagnostics", "cdns_export_sensor",
+    "cdns_rhs", "cdns_rk_step", "cdns_advance_n", "cdns_diagnostics",
+    "cdns_diagnostics_noalloc", "cdns_export_sensor",
     "cdns_export_iface_flux", "cdns_time_phases", "cdns_stats_accumulate", "cdns_stats_export",
     "cdns_stats_reset",
     "cdns_last_error", "cdns_destroy", "cdns_batch_create", "cdns_batch_workspace_bytes",
@@ -107,6 +112,8 @@ def load() -> ctypes.CDLL:
     lib.cdns_advance_n.restype = i32
     lib.cdns_diagnostics.argtypes = [vp, ctypes.POINTER(Diag)]
     lib.cdns_diagnostics.restype = i32
+    lib.cdns_diagnostics_noalloc.argtypes = [vp, dp, dp]
+    lib.cdns_diagnostics_noalloc.restype = i32
     lib.cdns_export_sensor.argtypes = [vp, dp, dp, dp]
     lib.cdns_export_sensor.restype = i32
     lib.cdns_export_iface_flux.argtypes = [vp, i32, dp]

@@ -33,6 +33,7 @@ struct cdns_ctx {
   bool flags_imported = false;        // next cdns_rhs uses the imported node flags
   int batch_refs = 0;
   int64_t stat_samples = 0;           // samples in the statistics accumulator
+  int device = 0;                     // device current at creation
 };
 
 namespace {
@@ -207,6 +208,7 @@ cdns_status cdns_create(const cdns_grid* grid, const cdns_phys* phys, int32_t pr
 
   cdns_ctx* c = new cdns_ctx();
   c->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
   c->precision = precision;
   c->ws = (char*)workspace_dev;
   c->ws_bytes = workspace_bytes;
@@ -588,6 +590,27 @@ cdns_status cdns_diagnostics(cdns_ctx* c, cdns_diag* out) {
   out->status = (int32_t)st[0];
   if (st[0] != 0 || out->nonfinite != 0 || !(out->rho_min > 0.0) || !(out->p_min > 0.0))
     return fail(c, CDNS_ESTATE, "device flagged a bad state");
+  return CDNS_OK;
+}
+
+cdns_status cdns_diagnostics_noalloc(cdns_ctx* c, const double* w_dev, double* out_dev) {
+  if (!c) return CDNS_EINVAL;
+  if (!out_dev) return fail(c, CDNS_EINVAL, "null output");
+  const Desc& D = c->D;
+  if (D.N > CDNS_NOALLOC_MAX_POINTS)
+    return fail(c, CDNS_EINVAL,
+                "grid of " + std::to_string(D.N) + " points exceeds the " +
+                    std::to_string((long long)CDNS_NOALLOC_MAX_POINTS) +
+                    "-point maximum of cdns_diagnostics_noalloc");
+  static_assert(CDNS_NOALLOC_MAX_POINTS == (long long)cdns::kNoallocBlocks * cdns::kNoallocPoints,
+                "header maximum must match the scratch array");
+  static_assert(CDNS_NDIAG_DEV <= cdns::DG_COUNT, "output slots");
+  double* part = nullptr;
+  hipError_t e = cdns::noalloc_scratch(c->device, &part);
+  if (e != hipSuccess) return hip_fail(c, e, "scratch address");
+  e = cdns::launch_diag_noalloc(D, w_dev ? w_dev : D.win[0], part, out_dev, CDNS_NDIAG_DEV,
+                                 c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "diag launch");
   return CDNS_OK;
 }
 

@@ -99,6 +99,16 @@ hipError_t launch_apply_force(const Desc& D, int stage, hipStream_t st);
 hipError_t launch_rk(const Desc& D, int stage, hipStream_t st);
 hipError_t launch_dt(const Desc& D, hipStream_t st);
 hipError_t launch_diag(const Desc& D, hipStream_t st);
+// No-allocation diagnostics: partials in a static per-device array of
+// kNoallocBlocks * DG_COUNT doubles (one block per kNoallocPoints points,
+// so grids of at most kNoallocBlocks * kNoallocPoints points).
+constexpr int kMaxDevices = 64;
+constexpr int kNoallocBlocks = 8192;
+constexpr long long kNoallocPoints = 4096;
+hipError_t noalloc_scratch(int dev, double** out);  // device address of the array on dev
+long long noalloc_diag_blocks(long long N);
+hipError_t launch_diag_noalloc(const Desc& D, const double* w, double* part, double* out,
+                               int nout, hipStream_t st);
 hipError_t launch_export_iflags(const Desc& D, uint8_t* out, hipStream_t st);
 hipError_t launch_count_iface(const Desc& D, bool reset, hipStream_t st);  // scal[SC_WACC]
 // digital-filter inflow: the initial plane (key 0), or the update at the

@@ -23,6 +23,7 @@
 // x-contiguous rows, so a wavefront touches 512 contiguous bytes per field.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <utility>
 
 #include "cdns_internal.h"
@@ -1983,9 +1984,12 @@ __global__ void __launch_bounds__(256) k_dt_final(Desc D, int nb) {
 }
 
 // ------------------------------------------------------------------ diagnostics
-__global__ void __launch_bounds__(256) k_diag_part(Desc D) {
+// Per-block partials of the volume integrals and extrema of the state w,
+// written to part[blockIdx.x][DG_COUNT]; k_diag_final reduces nb of them in
+// block order into res[0..nres-1] (nres <= DG_COUNT).
+__global__ void __launch_bounds__(256) k_diag_part(Desc D, const double* __restrict__ w,
+                                                   double* __restrict__ part) {
   __shared__ double sm[4];
-  const double* w = D.win[0];
   const size_t N = (size_t)D.N;
   double acc[6] = {0, 0, 0, 0, 0, 0};
   double rmin = 1e300, pmin = 1e300, mmax = 0.0, nonf = 0.0;
@@ -2009,7 +2013,7 @@ __global__ void __launch_bounds__(256) k_diag_part(Desc D) {
     const double c = sqrt(fabs(D.gamma * p * ir));
     mmax = fmax(mmax, sqrt(2.0 * ke * ir) / c);
   }
-  double* out = D.redd + (size_t)blockIdx.x * DG_COUNT;
+  double* out = part + (size_t)blockIdx.x * DG_COUNT;
   for (int m = 0; m < 6; ++m) {
     const double t = block_sum<256>(acc[m], sm);
     if (threadIdx.x == 0) out[m] = t;
@@ -2024,26 +2028,27 @@ __global__ void __launch_bounds__(256) k_diag_part(Desc D) {
   if (threadIdx.x == 0) out[DG_NONFINITE] = t;
 }
 
-__global__ void __launch_bounds__(256) k_diag_final(Desc D, int nb) {
+__global__ void __launch_bounds__(256) k_diag_final(const double* __restrict__ part, int nb,
+                                                    double* __restrict__ res, int nres) {
   __shared__ double sm[4];
-  for (int m = 0; m < DG_COUNT; ++m) {
+  for (int m = 0; m < nres; ++m) {
     double v;
     if (m == DG_RHOMIN || m == DG_PMIN) {
       v = 1e300;
-      for (int q = threadIdx.x; q < nb; q += 256) v = fmin(v, D.redd[(size_t)q * DG_COUNT + m]);
+      for (int q = threadIdx.x; q < nb; q += 256) v = fmin(v, part[(size_t)q * DG_COUNT + m]);
       v = block_min<256>(v, sm);
     } else if (m == DG_MACHMAX) {
       v = 0.0;
-      for (int q = threadIdx.x; q < nb; q += 256) v = fmax(v, D.redd[(size_t)q * DG_COUNT + m]);
+      for (int q = threadIdx.x; q < nb; q += 256) v = fmax(v, part[(size_t)q * DG_COUNT + m]);
       v = block_max<256>(v, sm);
     } else if (m <= DG_NONFINITE) {
       v = 0.0;
-      for (int q = threadIdx.x; q < nb; q += 256) v += D.redd[(size_t)q * DG_COUNT + m];
+      for (int q = threadIdx.x; q < nb; q += 256) v += part[(size_t)q * DG_COUNT + m];
       v = block_sum<256>(v, sm);
     } else {
       v = 0.0;
     }
-    if (threadIdx.x == 0) D.diag[m] = v;
+    if (threadIdx.x == 0) res[m] = v;
   }
 }
 
@@ -2269,8 +2274,55 @@ hipError_t launch_dt(const Desc& D, hipStream_t st) {
 hipError_t launch_diag(const Desc& D, hipStream_t st) {
   int nb = (int)nblk(D.N, 256);
   if (nb > kRedBlocks) nb = kRedBlocks;
-  k_diag_part<<<nb, 256, 0, st>>>(D);
-  k_diag_final<<<1, 256, 0, st>>>(D, nb);
+  k_diag_part<<<nb, 256, 0, st>>>(D, D.win[0], D.redd);
+  k_diag_final<<<1, 256, 0, st>>>(D.redd, nb, D.diag, DG_COUNT);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ no-allocation diagnostics
+// Partials of the no-allocation diagnostics live in this file-scope device
+// array (one copy per GPU, alive until the process ends).  Host code never
+// passes the array's name to a kernel: it uses the device address obtained
+// once per device with hipGetSymbolAddress (the name is only a host-side
+// stand-in).  All calls on one GPU share the array, so calls that overlap in
+// time on one GPU race.
+static __device__ __align__(256) double scratch[kNoallocBlocks * DG_COUNT];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    double* p = nullptr;
+    e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+    if (cur != dev) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+long long noalloc_diag_blocks(long long N) { return (N + kNoallocPoints - 1) / kNoallocPoints; }
+
+hipError_t launch_diag_noalloc(const Desc& D, const double* w, double* part, double* out,
+                               int nout, hipStream_t st) {
+  if (nout < 1 || nout > DG_COUNT || noalloc_diag_blocks(D.N) > kNoallocBlocks)
+    return hipErrorInvalidValue;
+  const int nb = (int)noalloc_diag_blocks(D.N);
+  k_diag_part<<<nb, 256, 0, st>>>(D, w, part);
+  k_diag_final<<<1, 256, 0, st>>>(part, nb, out, nout);
   return hipGetLastError();
 }
 

@@ -153,6 +153,22 @@ class Solver:
                 "weno_frac": list(d.weno_frac), "step": d.step, "nonfinite": d.nonfinite,
                 "status": d.status, "rc": st}
 
+    def diagnostics_noalloc(self, w=None, out=None):
+        """Volume integrals and extrema (B.DIAG_DEV_NAMES) of the state, or of
+        the device tensor w, written on the device into out (a float64 tensor
+        of B.NDIAG_DEV values, created if None) without synchronising."""
+        t = self.torch
+        if out is None:
+            out = t.empty(B.NDIAG_DEV, dtype=t.float64, device=self.device)
+        assert out.dtype == t.float64 and out.numel() >= B.NDIAG_DEV and out.is_contiguous()
+        if w is not None:
+            assert w.dtype == t.float64 and w.numel() == self.state.numel() and w.is_contiguous()
+        wp = w.data_ptr() if w is not None else None
+        B.check(self.lib, self.ctx,
+                self.lib.cdns_diagnostics_noalloc(self.ctx, wp, out.data_ptr()),
+                "cdns_diagnostics_noalloc")
+        return out
+
     def export_sensor(self):
         t = self.torch
         shp = (self.pr.nz, self.pr.ny, self.pr.nx)
