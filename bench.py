@@ -46,14 +46,25 @@ STEP_BYTES_PER_PT_FORCED = 448.0
 # rho w: 80 B + 24 B of w' + 24 B of R_prev (stages 1, 2), a mean of 120 B.
 RHS_RK_BYTES_PER_PT = 400.0 / 3.0
 RHS_RK_SPLIT_BYTES_PER_PT = 120.0
-# FP64 operations of one shock-capturing interface flux, counted from the
-# formula (a fused multiply-add counts two, a division or square root one),
-# by WENO order 2r-1: Roe average and eigenvalue constants 64; 2r nodes x
-# (primitives, flux, two characteristic projections, eigenvalue bounds) 74
-# each; Lax-Friedrichs splitting 20 per reconstruction node (2r-1 per side);
-# ten reconstructions of 20 (WENO3), 69 (WENO5) or 149 (WENO7) each;
-# back-projection 26.  WENO5: 64 + 444 + 100 + 690 + 26 = 1324.
-WENO_FLOPS_BY_ORDER = {3: 646.0, 5: 1324.0, 7: 2312.0}
+# FP64 operations of one shock-capturing interface flux in the kernel's
+# formulation (k_weno: weno_flux, weno3/5/7, half_sum), counted from the
+# source with a fused multiply-add as two, a reciprocal or square root as
+# one, comparisons and absolute values as none; by WENO order 2r-1:
+#  - Roe average of nodes i, i+1 (two reciprocals, pressures, enthalpies,
+#    square roots, weighted means) and the eigenvector constants: 65;
+#  - per stencil node (2r of them): primitives, pressure, sound speed 15,
+#    projection of the state on the left eigenvectors 21, projection of the
+#    Euler flux from it (u_n L w + p L(0, 1, 0, 0, u_n)) 15, eigenvalue
+#    bounds 2: 53;
+#  - per characteristic field (5): Lax-Friedrichs splitting 2 (2r - 1) x 2,
+#    two reconstructions (WENO3 18, WENO5 62, WENO7 146 each), the half
+#    sum of the two with one reciprocal 7;
+#  - back-projection on the right eigenvectors: 26.
+# WENO5: 65 + 6 x 53 + 5 x (20 + 124 + 7) + 26 = 1164.
+WENO_FLOPS_BY_ORDER = {3: 578.0, 5: 1164.0, 7: 2150.0}
+# Hash of the source region the count was taken from (weno_source_hash());
+# a CPU test fails when that code changes, so the count cannot go stale.
+WENO_FLOPS_SOURCE_HASH = "1f3e37daafbc24b4"
 WENO_FLOPS_PER_IFACE = WENO_FLOPS_BY_ORDER[5]
 
 
@@ -85,9 +96,27 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel, workload):
+def weno_source_hash():
+    """Hash of the shock-capturing flux code (from the WENO5 reconstruction
+    to the end of weno_flux) without comments and blank lines."""
+    path = os.path.join(ROOT, "paper_2004_02276_amd", "csrc", "cdns_kernels.hip")
+    with open(path, encoding="utf-8") as fh:
+        txt = fh.read()
+    a = txt.index("// WENO5-JS reconstruction at i+1/2")
+    b = txt.index("// ------------------------------------------------------------------ stage begin")
+    h = hashlib.sha256()
+    for line in txt[a:b].splitlines():
+        code = line.split("//", 1)[0].rstrip()
+        if code:
+            h.update(code.encode() + b"\n")
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, workload, steps, warmup):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source and this workload (else None)."""
+    taken on the current kernel source, this workload and this step window
+    (the channel's shock-capturing share decays over the run, so the bytes
+    per launch depend on which steps are timed); else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -95,9 +124,24 @@ def load_traffic(kernel, workload):
     except (OSError, ValueError):
         return None
     ent = t.get(kernel)
-    if not ent or ent.get("source_hash") != kernel_source_hash() or ent.get("workload") != workload:
+    if (not ent or ent.get("source_hash") != kernel_source_hash() or
+            ent.get("workload") != workload or ent.get("steps") != steps or
+            ent.get("warmup") != warmup):
         return None
     return ent.get("hbm_bytes_per_launch")
+
+
+def cpu_model():
+    """Model name of the host CPU (first entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def cpu_baseline(pr):
@@ -115,6 +159,7 @@ def cpu_baseline(pr):
             break
     rate = pr.npts * steps / el / 1e6
     return {"value": rate, "unit": "Mpoint-RK-steps/s", "cores": nthreads, "kind": "oracle",
+            "cpu": cpu_model(),
             "sample": f"{steps} RK3 step(s) of the full {pr.name} workload from the same seeded "
                       f"initial field, {el:.1f} s wall"}
 
@@ -122,8 +167,8 @@ def cpu_baseline(pr):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", choices=["fp64", "fp32flux"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=list(WORKLOADS), default="channel",
@@ -193,7 +238,8 @@ def main():
         achieved = flops / (mean_ms * 1e-3) / 1e12
         roof = {"kernel": "k_weno", "bound": "alu", "achieved": achieved,
                 "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_TFLOPS,
-                "traffic": load_traffic("k_weno", args.workload) if default_scheme else None,
+                "traffic": load_traffic("k_weno", args.workload, args.steps, args.warmup)
+                           if default_scheme else None,
                 "algorithmic_per_launch": f"{fl_if:.0f} flop x {n_iface:.0f} "
                                           f"interfaces (mean over the timed launches)"}
     else:
@@ -205,7 +251,8 @@ def main():
         achieved = nbytes / (ph["rhs"][0] * 1e-3) / 1e9
         roof = {"kernel": "k_rhs", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": load_traffic("k_rhs", args.workload) if default_scheme else None,
+                "traffic": load_traffic("k_rhs", args.workload, args.steps, args.warmup)
+                           if default_scheme else None,
                 "algorithmic_per_launch": f"{bpp:.1f} B x {pr.npts} points (RK update included)"}
     roof["mean_launch_ms"] = mean_ms
     scheme = ("" if (args.central_order, args.weno_order) == (4, 5) else

@@ -1,6 +1,7 @@
 """Host-side logic of the benchmark (no GPU): the counter-based HBM traffic
-is reported only for the kernel source and the workload it was taken on,
-and the source key ignores comments and blank lines."""
+is reported only for the kernel source, workload and step window it was
+taken on; the source key ignores comments and blank lines; the flop count
+of the shock-capturing flux belongs to the current code."""
 import json
 import os
 
@@ -11,12 +12,15 @@ def test_traffic_keyed_to_source_and_workload(monkeypatch):
     with open(os.path.join(bench.ROOT, "profiles", "traffic.json")) as fh:
         t = json.load(fh)
     ent = t["k_weno"]
+    st, wu = ent["steps"], ent["warmup"]
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: ent["source_hash"])
-    assert bench.load_traffic("k_weno", ent["workload"]) == ent["hbm_bytes_per_launch"]
-    assert bench.load_traffic("k_weno", "sbli") is None       # other workload
-    assert bench.load_traffic("k_nonexistent", ent["workload"]) is None
+    assert bench.load_traffic("k_weno", ent["workload"], st, wu) == ent["hbm_bytes_per_launch"]
+    assert bench.load_traffic("k_weno", "sbli", st, wu) is None        # other workload
+    assert bench.load_traffic("k_weno", ent["workload"], st + 1, wu) is None  # other window
+    assert bench.load_traffic("k_weno", ent["workload"], st, wu + 1) is None
+    assert bench.load_traffic("k_nonexistent", ent["workload"], st, wu) is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
-    assert bench.load_traffic("k_weno", ent["workload"]) is None  # other source
+    assert bench.load_traffic("k_weno", ent["workload"], st, wu) is None  # other source
 
 
 def test_source_hash_ignores_comments(tmp_path, monkeypatch):
@@ -35,3 +39,13 @@ def test_source_hash_ignores_comments(tmp_path, monkeypatch):
 
     monkeypatch.setattr("builtins.open", fake_open)
     assert bench.kernel_source_hash() == h0
+
+
+def test_weno_flop_count_belongs_to_the_current_code():
+    """The per-interface flop counts were taken from the shock-capturing flux
+    code as it stands; a change there must come with a recount."""
+    assert bench.weno_source_hash() == bench.WENO_FLOPS_SOURCE_HASH
+    # WENO5 total from its parts: Roe and constants, 6 nodes, 5 fields, back-projection
+    assert bench.WENO_FLOPS_BY_ORDER[5] == 65 + 6 * 53 + 5 * (2 * 5 * 2 + 2 * 62 + 7) + 26
+    assert bench.WENO_FLOPS_BY_ORDER[3] == 65 + 4 * 53 + 5 * (2 * 3 * 2 + 2 * 18 + 7) + 26
+    assert bench.WENO_FLOPS_BY_ORDER[7] == 65 + 8 * 53 + 5 * (2 * 7 * 2 + 2 * 146 + 7) + 26
