@@ -92,22 +92,27 @@ enum { CDNS_SENSOR_OFF = 0, CDNS_SENSOR_HYBRID = 1, CDNS_SENSOR_WENO_ALL = 2 };
  *                  i < i_shock and state 2 otherwise (imposed inviscid
  *                  oblique-shock solution, Sec. 3.3).
  *  DF_INFLOW       x- face only; synthetic inflow turbulence by digital
- *                  filtering (Sec. 3.2).  params = {Ny, Nz, T, seed,
- *                  b_y[2Ny+1], b_z[2Nz+1], mean (rho,u,v,w,p) [5][ny],
- *                  lower Cholesky factor of the Reynolds stresses
- *                  (a11,a21,a22,a31,a32,a33) [6][ny]}.  Deviates uniform
- *                  on [-sqrt 3, sqrt 3) from SplitMix64 (output n of the
- *                  generator seeded with `seed`, n = 1 + (((key*3 + c)*nz +
- *                  k)*(ny + 2Ny) + jj) for component c, plane k, extended
- *                  row jj; key 0 for the initial plane made by this call,
- *                  key s + 1 at the start of step s); filtered along y then
- *                  z (periodic) with the given coefficients; time
- *                  correlation psi = psi E + psi_hat sqrt(1 - E^2),
- *                  E = exp(-pi dt/(2T)); fluctuations u'_i = a_ij psi_j;
- *                  T' = -u_mean u'/c_p at constant pressure (strong
- *                  Reynolds analogy).  The plane is refreshed once per RK
- *                  step and imposed on the ghost layers.  Not
- *                  accepted by batches. */
+ *                  filtering (Sec. 3.2).  params = {n_y, n_z, T, seed,
+ *                  mean (rho,u,v,w,p) [5][ny], Reynolds stresses (R11,
+ *                  R22, R33, R12, R13, R23) [6][ny]} (4 + 11 ny values):
+ *                  n_y, n_z are the integral lengths of the inflow
+ *                  turbulence in grid spacings (y: the caller's mean
+ *                  spacing), T its Lagrangian time scale.  The library
+ *                  derives the Gaussian filter coefficients b_l ~
+ *                  exp(-pi l^2/(2 n^2)), |l| <= N = max(1, ceil(2 n)) <= ny
+ *                  (resp. nz), unit sum of squares, and the lower
+ *                  triangular factor a a^T = R (Lund's transformation).
+ *                  Deviates uniform on [-sqrt 3, sqrt 3) from SplitMix64
+ *                  (output n of the generator seeded with `seed`, n = 1 +
+ *                  (((key*3 + c)*nz + k)*(ny + 2 N_y) + jj) for component
+ *                  c, plane k, extended row jj; key 0 for the initial plane
+ *                  made by this call, key s + 1 at the start of step s);
+ *                  filtered along y then z (periodic); time correlation
+ *                  psi = psi E + psi_hat sqrt(1 - E^2), E = exp(-pi dt/(2T));
+ *                  fluctuations u'_i = a_ij psi_j; T' = -u_mean u'/c_p at
+ *                  constant pressure (strong Reynolds analogy).  The plane
+ *                  is refreshed once per RK step and imposed on the ghost
+ *                  layers.  Not accepted by batches. */
 enum {
   CDNS_BC_PERIODIC = 0,
   CDNS_BC_WALL_ISOTHERMAL = 1,

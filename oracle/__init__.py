@@ -122,6 +122,9 @@ def _load():
         lib.ora_df_update.argtypes = [pp, ctypes.c_uint64, ctypes.c_double, ctypes.c_int, dp, dp,
                                       dp]
         lib.ora_df_update.restype = ctypes.c_int
+        lib.ora_df_coeffs.argtypes = [pp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                      dp, dp, dp]
+        lib.ora_df_coeffs.restype = ctypes.c_int
         lib.ora_ghosts_y.argtypes = [pp, dp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int)]
         lib.ora_ghosts_y.restype = ctypes.c_int
         lib.ora_lf_alpha.argtypes = [pp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -359,6 +362,21 @@ def df_update(pr, key: int, dt: float, first: bool, psi: Optional[np.ndarray] = 
     _check(lib.ora_df_update(ctypes.byref(m.s), ctypes.c_uint64(key), float(dt), int(bool(first)),
                              _dptr(psi), _dptr(plane), _dptr(fl)), "ora_df_update")
     return psi, plane, fl
+
+
+def df_coeffs(pr):
+    """Derived coefficients of the digital-filter inflow of `pr` (face x-):
+    (b_y, b_z, lower triangular factor [6][ny] as a11, a21, a22, a31, a32,
+    a33)."""
+    lib = _load()
+    by = np.zeros(2 * pr.ny + 3)
+    bz = np.zeros(2 * pr.nz + 3)
+    chol = np.zeros((6, pr.ny))
+    ny_, nz_ = ctypes.c_int(0), ctypes.c_int(0)
+    m = _Marshalled(pr)
+    _check(lib.ora_df_coeffs(ctypes.byref(m.s), ctypes.byref(ny_), ctypes.byref(nz_), _dptr(by),
+                             _dptr(bz), _dptr(chol)), "ora_df_coeffs")
+    return by[:2 * ny_.value + 1], bz[:2 * nz_.value + 1], chol
 
 
 STAT_NAMES = ["rho", "rho_u", "rho_v", "rho_w", "rho_uu", "rho_vv", "rho_ww", "rho_uv", "u", "uu",

@@ -285,18 +285,22 @@ double ora_weno5(const double* v) { return ora_weno(3, v); }
  *    seeded with `seed`), n = 1 + (((key*3 + c)*nz + k)*(ny + 2 Ny) + jj)
  *    for velocity component c, plane k, extended row jj, and key = 0 for
  *    the initial plane, key = s + 1 at the start of step s;
- *  - filters: Gaussian coefficients b_l (l = -N..N), normalised to unit
- *    sum of squares, supplied by the caller; applied along y (over the
- *    extended rows) and then along z (periodic), each as a sum in
- *    increasing l;
+ *  - filters: for a filter length of n grid spacings, the Gaussian
+ *    coefficients b_l proportional to exp(-pi l^2 / (2 n^2)), l = -N..N
+ *    with N = max(1, ceil(2 n)), normalised to unit sum of squares;
+ *    applied along y (over the extended rows) and then along z (periodic),
+ *    each as a sum in increasing l;
  *  - time correlation: psi = psi E + psi_hat sqrt(1 - E^2) with
  *    E = exp(-pi dt / (2 T)); the initial plane takes psi = psi_hat;
- *  - fluctuations u'_i = a_ij psi_j with a the lower Cholesky factor of
- *    the Reynolds stresses (supplied per row j), temperature from the
+ *  - fluctuations u'_i = a_ij psi_j with a the lower triangular factor of
+ *    the Reynolds stress tensor R = a a^T (Lund's transformation: a11 =
+ *    sqrt R11, a21 = R21/a11, a22 = sqrt(R22 - a21^2), a31 = R31/a11,
+ *    a32 = (R32 - a21 a31)/a22, a33 = sqrt(R33 - a31^2 - a32^2); a zero
+ *    diagonal entry zeroes the entries below it), temperature from the
  *    strong Reynolds analogy with constant total enthalpy, T' = -u_mean u'/c_p,
  *    constant pressure, so rho = p/(R (T_mean + T')).
- * Parameters (face x-): [Ny, Nz, T, seed, b_y[2Ny+1], b_z[2Nz+1],
- * mean rho, u, v, w, p [5][ny], a11, a21, a22, a31, a32, a33 [6][ny]]. */
+ * Parameters (face x-): [n_y, n_z (filter lengths in grid spacings), T,
+ * seed, mean rho, u, v, w, p [5][ny], R11, R22, R33, R12, R13, R23 [6][ny]]. */
 uint64_t ora_splitmix64(uint64_t seed, uint64_t n) {
   uint64_t z = seed + n * 0x9E3779B97F4A7C15ULL;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
@@ -309,13 +313,60 @@ static double df_deviate(uint64_t seed, uint64_t n) {
   return (2.0 * u - 1.0) * 1.7320508075688772;
 }
 
+static int df_half_width(double n) {
+  const int N = (int)ceil(2.0 * n);
+  return N < 1 ? 1 : N;
+}
+
 static int df_layout(const ora_problem* P, int* Ny, int* Nz) {
   const double* pr = P->bc_params[0];
-  if (P->bc_nparams[0] < 4) return ORA_EINVAL;
-  *Ny = (int)pr[0];
-  *Nz = (int)pr[1];
-  if (*Ny < 0 || *Nz < 0 || !(pr[2] > 0.0)) return ORA_EINVAL;
-  if (P->bc_nparams[0] != 4 + (2 * *Ny + 1) + (2 * *Nz + 1) + 11 * P->ny) return ORA_EINVAL;
+  if (P->bc_nparams[0] != 4 + 11 * P->ny) return ORA_EINVAL;
+  if (!(pr[0] > 0.0) || !(pr[1] > 0.0) || !(pr[2] > 0.0)) return ORA_EINVAL;
+  *Ny = df_half_width(pr[0]);
+  *Nz = df_half_width(pr[1]);
+  return ORA_OK;
+}
+
+/* Gaussian filter coefficients b[0..2N] (l = -N..N) for a length of n
+ * grid spacings, unit sum of squares. */
+static void df_filter(double n, int N, double* b) {
+  double ss = 0.0;
+  for (int l = -N; l <= N; ++l) {
+    b[l + N] = exp(-3.141592653589793 * (double)(l * l) / (2.0 * n * n));
+    ss += b[l + N] * b[l + N];
+  }
+  const double nrm = sqrt(ss);
+  for (int l = 0; l <= 2 * N; ++l) b[l] /= nrm;
+}
+
+/* Lower triangular a with a a^T = R for R = (R11, R22, R33, R12, R13, R23);
+ * a = (a11, a21, a22, a31, a32, a33). */
+static void df_cholesky(const double R[6], double a[6]) {
+  const double a11 = sqrt(fmax(R[0], 0.0));
+  const double a21 = a11 > 0.0 ? R[3] / a11 : 0.0;
+  const double a31 = a11 > 0.0 ? R[4] / a11 : 0.0;
+  const double a22 = sqrt(fmax(R[1] - a21 * a21, 0.0));
+  const double a32 = a22 > 0.0 ? (R[5] - a21 * a31) / a22 : 0.0;
+  const double a33 = sqrt(fmax(R[2] - a31 * a31 - a32 * a32, 0.0));
+  a[0] = a11; a[1] = a21; a[2] = a22; a[3] = a31; a[4] = a32; a[5] = a33;
+}
+
+/* The derived inflow-generator coefficients of a problem: half-widths,
+ * by[2 Ny + 1], bz[2 Nz + 1] (each array at least 2 * ny + 1, resp.
+ * 2 * nz + 1, long) and the factor chol[6][ny]. */
+int ora_df_coeffs(const ora_problem* P, int* Ny, int* Nz, double* by, double* bz, double* chol) {
+  int st = df_layout(P, Ny, Nz);
+  if (st) return st;
+  const double* pr = P->bc_params[0];
+  df_filter(pr[0], *Ny, by);
+  df_filter(pr[1], *Nz, bz);
+  const double* rs = pr + 4 + 5 * P->ny;
+  for (int j = 0; j < P->ny; ++j) {
+    double R[6], a[6];
+    for (int m = 0; m < 6; ++m) R[m] = rs[m * P->ny + j];
+    df_cholesky(R, a);
+    for (int m = 0; m < 6; ++m) chol[m * P->ny + j] = a[m];
+  }
   return ORA_OK;
 }
 
@@ -331,12 +382,16 @@ int ora_df_update(const ora_problem* P, uint64_t key, double dt, int first, doub
   const double* pr = P->bc_params[0];
   const double TL = pr[2];
   const uint64_t seed = (uint64_t)pr[3];
-  const double* by = pr + 4;
-  const double* bz = by + 2 * Ny + 1;
-  const double* mean = bz + 2 * Nz + 1;
-  const double* chol = mean + 5 * ny;
+  const double* mean = pr + 4;
+  double* by = malloc((size_t)(2 * Ny + 1) * sizeof(double));
+  double* bz = malloc((size_t)(2 * Nz + 1) * sizeof(double));
+  double* chol = malloc((size_t)6 * ny * sizeof(double));
   double* fy = malloc((size_t)3 * nz * ny * sizeof(double));
-  if (!fy) return ORA_ENOMEM;
+  if (!by || !bz || !chol || !fy) {
+    free(by); free(bz); free(chol); free(fy);
+    return ORA_ENOMEM;
+  }
+  ora_df_coeffs(P, &Ny, &Nz, by, bz, chol);
   for (int c = 0; c < 3; ++c)
     for (int k = 0; k < nz; ++k)
       for (int j = 0; j < ny; ++j) {
@@ -382,7 +437,7 @@ int ora_df_update(const ora_problem* P, uint64_t key, double dt, int first, doub
         fl[((size_t)2 * nz + k) * ny + j] = dw;
       }
     }
-  free(fy);
+  free(by); free(bz); free(chol); free(fy);
   return ORA_OK;
 }
 
@@ -455,6 +510,7 @@ static int fill_ghosts(const ora_problem* P, const geom* g, double* W[5]) {
           }
         } else if (kind == BC_DF_INFLOW && side == 0) {
           /* the inflow plane of the current step, the same on every layer */
+          if (!P->df_plane) return ORA_EINVAL;
           for (int s = 1; s <= hw; ++s)
             for (int m = 0; m < 5; ++m)
               W[m][pidx(g, -s, j, k)] = P->df_plane[((size_t)m * nz + k) * ny + j];
@@ -593,7 +649,7 @@ static int prepare(const ora_problem* P, const double* w, work_t* a) {
         for (int i = 0; i < g->nx; ++i)
           a->W[m][pidx(g, i, j, k)] = w[(size_t)m * g->nx * g->ny * g->nz + uidx(g, i, j, k)];
   int st = fill_ghosts(P, g, a->W);
-  if (st == ORA_EUNSUP) return st;
+  if (st != ORA_OK && st != ORA_ESTATE) return st;
   int bad = st == ORA_ESTATE;
   const int hw = g->hw;  /* layers beyond hw stay unset and unused */
 #pragma omp parallel for reduction(| : bad)
@@ -1295,10 +1351,24 @@ int ora_ghosts_y(const ora_problem* P, const double* w, int face, double* out, i
   int st = validate(P);
   if (st) return st;
   if (face != 2 && face != 3) return ORA_EINVAL;
+  if (P->bc_kind[0] == BC_DF_INFLOW && !P->df_plane) {
+    /* digital-filter inflow without a plane: the initial plane (key 0), as
+     * for the right-hand side */
+    size_t np = (size_t)P->nz * P->ny;
+    double* psi = malloc(3 * np * sizeof(double));
+    double* plane = malloc(5 * np * sizeof(double));
+    if (!psi || !plane) { free(psi); free(plane); return ORA_ENOMEM; }
+    ora_problem Q = *P;
+    st = ora_df_update(P, 0, 0.0, 1, psi, plane, NULL);
+    Q.df_plane = plane;
+    if (!st) st = ora_ghosts_y(&Q, w, face, out, hw_out);
+    free(psi); free(plane);
+    return st;
+  }
   work_t a;
   if (work_alloc(P, &a)) return ORA_ENOMEM;
   st = prepare(P, w, &a);
-  if (st == ORA_EUNSUP) { work_free(&a); return st; }
+  if (st != ORA_OK && st != ORA_ESTATE) { work_free(&a); return st; }
   const geom* g = &a.g;
   const int hw = g->hw, nxe = g->nx + 2 * hw;
   for (int m = 0; m < 5; ++m)

@@ -339,6 +339,61 @@ cdns_status cdns_create(const cdns_grid* grid, const cdns_phys* phys, int32_t pr
   return CDNS_OK;
 }
 
+// Digital-filter inflow (Sec. 3.2): half-width of the Gaussian filter of a
+// length of n grid spacings, N = max(1, ceil(2 n)).
+static int df_half_width(double n) {
+  const double N = std::ceil(2.0 * n);
+  return N < 1.0 ? 1 : (N > 1e9 ? 1000000000 : (int)N);
+}
+
+// Expands the caller's parameters [n_y, n_z, T, seed, mean[5][ny],
+// R11, R22, R33, R12, R13, R23 [6][ny]] into the block the generator
+// kernels read: [N_y, N_z, T, seed, b_y[2N_y+1], b_z[2N_z+1], mean[5][ny],
+// a11, a21, a22, a31, a32, a33 [6][ny]] with the Gaussian coefficients
+// b_l ~ exp(-pi l^2/(2 n^2)) of unit sum of squares and the lower triangular
+// factor a a^T = R of the stresses (Lund's transformation; a zero diagonal
+// entry zeroes the column below it).
+static void df_derive(int ny, const double* p, std::vector<double>& out) {
+  const int Ny = df_half_width(p[0]), Nz = df_half_width(p[1]);
+  out.assign(4 + (2 * (size_t)Ny + 1) + (2 * (size_t)Nz + 1) + 11 * (size_t)ny, 0.0);
+  out[0] = Ny;
+  out[1] = Nz;
+  out[2] = p[2];
+  out[3] = p[3];
+  double* b = out.data() + 4;
+  for (int f = 0; f < 2; ++f) {
+    const double n = p[f];
+    const int N = f == 0 ? Ny : Nz;
+    double ss = 0.0;
+    for (int l = -N; l <= N; ++l) {
+      b[l + N] = std::exp(-M_PI * (double)l * (double)l / (2.0 * n * n));
+      ss += b[l + N] * b[l + N];
+    }
+    const double inv = 1.0 / std::sqrt(ss);
+    for (int l = 0; l <= 2 * N; ++l) b[l] *= inv;
+    b += 2 * N + 1;
+  }
+  std::memcpy(b, p + 4, 5 * (size_t)ny * sizeof(double));
+  double* a = b + 5 * (size_t)ny;
+  const double* R = p + 4 + 5 * (size_t)ny;
+  for (int j = 0; j < ny; ++j) {
+    const double r11 = R[j], r22 = R[ny + j], r33 = R[2 * ny + j];
+    const double r12 = R[3 * ny + j], r13 = R[4 * ny + j], r23 = R[5 * ny + j];
+    const double a11 = std::sqrt(std::fmax(r11, 0.0));
+    const double a21 = a11 > 0.0 ? r12 / a11 : 0.0;
+    const double a31 = a11 > 0.0 ? r13 / a11 : 0.0;
+    const double a22 = std::sqrt(std::fmax(r22 - a21 * a21, 0.0));
+    const double a32 = a22 > 0.0 ? (r23 - a21 * a31) / a22 : 0.0;
+    const double a33 = std::sqrt(std::fmax(r33 - a31 * a31 - a32 * a32, 0.0));
+    a[j] = a11;
+    a[ny + j] = a21;
+    a[2 * ny + j] = a22;
+    a[3 * ny + j] = a31;
+    a[4 * ny + j] = a32;
+    a[5 * ny + j] = a33;
+  }
+}
+
 cdns_status cdns_set_bc(cdns_ctx* c, int32_t face, int32_t kind, const double* params,
                         int64_t nparams) {
   if (!c) return CDNS_EINVAL;
@@ -359,14 +414,12 @@ cdns_status cdns_set_bc(cdns_ctx* c, int32_t face, int32_t kind, const double* p
       return fail(c, CDNS_EUNSUP,
                   "y faces accept periodic, walls, an imposed shock state or characteristic outflow");
     if (kind == cdns::BC_DF_INFLOW) {
-      if (nparams < 4) return fail(c, CDNS_EINVAL, "digital-filter inflow needs parameters");
-      const double nyh = params[0], nzh = params[1];
-      if (!(nyh >= 0.0 && nyh <= D.ny && nzh >= 0.0 && nzh <= D.nz) || nyh != (double)(int)nyh ||
-          nzh != (double)(int)nzh || !(params[2] > 0.0) || !(params[3] >= 0.0) ||
-          params[3] != (double)(uint64_t)params[3])
-        return fail(c, CDNS_EINVAL, "digital-filter half-widths, time scale or seed invalid");
-      if (nparams != 4 + (2 * (int64_t)nyh + 1) + (2 * (int64_t)nzh + 1) + 11LL * D.ny)
-        return fail(c, CDNS_EINVAL, "digital-filter parameter count does not match the layout");
+      if (nparams != 4 + 11LL * D.ny)
+        return fail(c, CDNS_EINVAL, "digital-filter inflow needs 4 + 11*ny parameters");
+      const double ly = params[0], lz = params[1];
+      if (!(ly > 0.0 && df_half_width(ly) <= D.ny && lz > 0.0 && df_half_width(lz) <= D.nz) ||
+          !(params[2] > 0.0) || !(params[3] >= 0.0) || params[3] != (double)(uint64_t)params[3])
+        return fail(c, CDNS_EINVAL, "digital-filter lengths, time scale or seed invalid");
     }
     if (kind == cdns::BC_DIRICHLET && nparams != 5LL * D.ny)
       return fail(c, CDNS_EINVAL, "Dirichlet profile needs 5*ny values");
@@ -375,11 +428,15 @@ cdns_status cdns_set_bc(cdns_ctx* c, int32_t face, int32_t kind, const double* p
     if (kind == cdns::BC_SHOCK_TOP && nparams != 11)
       return fail(c, CDNS_EINVAL, "shock state needs 11 values");
   }
-  if ((size_t)nparams > c->bcp_cap) return fail(c, CDNS_EINVAL, "too many parameters");
-  c->h_bcp[face].assign(params, params + nparams);
-  if (nparams > 0) {
+  std::vector<double> block;
+  if (kind == cdns::BC_DF_INFLOW) df_derive(D.ny, params, block);
+  else block.assign(params, params + nparams);
+  if (block.size() > c->bcp_cap) return fail(c, CDNS_EINVAL, "too many parameters");
+  c->h_bcp[face].swap(block);
+  if (!c->h_bcp[face].empty()) {
     hipError_t e = hipMemcpyAsync(c->bcp_dev[face], c->h_bcp[face].data(),
-                                  nparams * sizeof(double), hipMemcpyHostToDevice, c->stream);
+                                  c->h_bcp[face].size() * sizeof(double), hipMemcpyHostToDevice,
+                                  c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "sync");
   }

@@ -353,35 +353,16 @@ def bl_vd_uplus(yp, eta, pi_wake: float = 0.45, kappa: float = 0.41):
     return musker_uplus(yp) + 2.0 * pi_wake / kappa * np.sin(0.5 * math.pi * e) ** 2
 
 
-def gaussian_filter_coeffs(n: float) -> np.ndarray:
-    """Digital-filter coefficients for a length of n grid spacings:
-    b_k proportional to exp(-pi k^2 / (2 n^2)), k = -2n..2n (at least one
-    neighbour), normalised to unit sum of squares."""
-    half = max(1, int(math.ceil(2.0 * n)))
-    k = np.arange(-half, half + 1, dtype=np.float64)
-    b = np.exp(-math.pi * k * k / (2.0 * max(n, 1e-12) ** 2))
-    return b / math.sqrt(float(np.sum(b * b)))
-
-
-def df_inflow_params(mean_prim: np.ndarray, rstress: np.ndarray, by: np.ndarray, bz: np.ndarray,
+def df_inflow_params(mean_prim: np.ndarray, rstress: np.ndarray, n_y: float, n_z: float,
                      t_lag: float, seed: int) -> np.ndarray:
-    """Parameter vector of the digital-filter inflow face: [Ny, Nz, T, seed,
-    b_y, b_z, mean (rho,u,v,w,p)[5][ny], lower Cholesky factor of the
-    Reynolds stresses (a11, a21, a22, a31, a32, a33)[6][ny]].  rstress is
-    (R11, R22, R33, R12, R13, R23)[6][ny]."""
-    R11, R22, R33, R12, R13, R23 = rstress
-    a11 = np.sqrt(np.maximum(R11, 0.0))
-    safe = np.where(a11 > 0.0, a11, 1.0)
-    a21 = np.where(a11 > 0.0, R12 / safe, 0.0)
-    a31 = np.where(a11 > 0.0, R13 / safe, 0.0)
-    a22 = np.sqrt(np.maximum(R22 - a21 * a21, 0.0))
-    safe22 = np.where(a22 > 0.0, a22, 1.0)
-    a32 = np.where(a22 > 0.0, (R23 - a21 * a31) / safe22, 0.0)
-    a33 = np.sqrt(np.maximum(R33 - a31 * a31 - a32 * a32, 0.0))
-    ny_half, nz_half = (len(by) - 1) // 2, (len(bz) - 1) // 2
-    head = np.array([float(ny_half), float(nz_half), float(t_lag), float(seed)])
-    return np.concatenate([head, by, bz, np.asarray(mean_prim, np.float64).ravel(),
-                           np.stack([a11, a21, a22, a31, a32, a33]).ravel()])
+    """Parameter vector of the digital-filter inflow face: [n_y, n_z (filter
+    lengths in grid spacings), T (Lagrangian time scale), seed, mean
+    (rho, u, v, w, p)[5][ny], Reynolds stresses (R11, R22, R33, R12, R13,
+    R23)[6][ny]].  The filter coefficients and the stress factorisation are
+    derived by whoever consumes the vector."""
+    head = np.array([float(n_y), float(n_z), float(t_lag), float(seed)])
+    return np.concatenate([head, np.asarray(mean_prim, np.float64).ravel(),
+                           np.asarray(rstress, np.float64).ravel()])
 
 
 def boundary_layer(nx: int = 1024, ny: int = 128, nz: int = 128, lx: float = 30.0,
@@ -433,11 +414,9 @@ def boundary_layer(nx: int = 1024, ny: int = 128, nz: int = 128, lx: float = 30.
     dz = lz / nz
     inside = eta < 1.0
     dy_bl = float(np.mean(np.diff(y[inside]))) if inside.sum() > 1 else float(y[1] - y[0])
-    by = gaussian_filter_coeffs(len_y / dy_bl)
-    bz = gaussian_filter_coeffs(len_z / dz)
     mean = np.stack([rho, u, np.zeros(ny), np.zeros(ny), np.full(ny, pinf)])
     seed = BASE_SEED + seed_index
-    params = df_inflow_params(mean, rs, by, bz, t_lag, seed)
+    params = df_inflow_params(mean, rs, len_y / dy_bl, len_z / dz, t_lag, seed)
     shape = (nz, ny, nx)
     U = np.broadcast_to(u[None, :, None], shape)
     Rh = np.broadcast_to(rho[None, :, None], shape)

@@ -36,19 +36,66 @@ def _plane_problem(ny=48, nz=64, ny_len=3.0, nz_len=4.0, t_lag=0.5, stresses=Non
     """A channel-shaped problem whose x- face carries a digital-filter
     inflow with uniform mean state and the given constant stresses."""
     pr = P.small_channel(16, ny, nz)
-    by = P.gaussian_filter_coeffs(ny_len)
-    bz = P.gaussian_filter_coeffs(nz_len)
     mean = np.stack([np.ones(ny), np.full(ny, 1.0), np.zeros(ny), np.zeros(ny),
                      np.full(ny, pr.R_gas)])
     R11, R22, R33, R12 = stresses if stresses is not None else (4.0, 2.0, 1.0, -1.0)
     rs = np.stack([np.full(ny, R11), np.full(ny, R22), np.full(ny, R33), np.full(ny, R12),
                    np.zeros(ny), np.zeros(ny)])
-    params = P.df_inflow_params(mean, rs, by, bz, t_lag, 777)
+    params = P.df_inflow_params(mean, rs, ny_len, nz_len, t_lag, 777)
     bcs = list(pr.bcs)
     bcs[P.FACE_XM] = (P.BC_DF_INFLOW, params)
     bcs[P.FACE_XP] = (P.BC_OUTFLOW_CHAR, np.zeros(0))
     import dataclasses
-    return dataclasses.replace(pr, bcs=bcs), by, bz
+    pr = dataclasses.replace(pr, bcs=bcs)
+    by, bz, _ = oracle.df_coeffs(pr)
+    return pr, by, bz
+
+
+@pytest.mark.parametrize("n", [1.0, 2.5, 4.0, 7.3])
+def test_df_filter_coefficients_give_the_integral_length(n):
+    """The filtered white noise has the autocorrelation rho(r) = sum_l b_l
+    b_(l+r); with the Gaussian coefficients its integral length
+    int_0^inf rho(r) dr (trapezoidal over the lags) is the prescribed n grid
+    spacings (Klein, Sadiki and Janicka 2003, the digital filter's design
+    rule) and rho(0) = 1 (unit variance); the half-width is ceil(2 n)."""
+    pr, by, bz = _plane_problem(ny=48, nz=64, ny_len=n, nz_len=n)
+    for b in (by, bz):
+        half = (len(b) - 1) // 2
+        assert half == max(1, math.ceil(2 * n))
+        assert np.allclose(b, b[::-1], rtol=0, atol=0)               # symmetric
+        rho = np.array([np.sum(b[: len(b) - r] * b[r:]) for r in range(len(b))])
+        assert abs(rho[0] - 1.0) <= 1e-14
+        length = rho.sum() - 0.5 * rho[0]
+        # the truncation at 2n drops the tail beyond exp(-4 pi) of the kernel
+        assert abs(length - n) <= (1e-3 * n if n >= 2 else 0.08), (n, length)
+
+
+def test_df_stress_factor_reproduces_the_stresses():
+    """Lund's factor a of the Reynolds stresses satisfies a a^T = R for
+    positive definite tensors, and zeroes the rows of a vanishing stress
+    (the free stream outside the layer)."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    ny = 48
+    rs = np.zeros((6, ny))
+    for j in range(ny - 4):
+        m = rng.normal(size=(3, 3))
+        R = m @ m.T + 0.1 * np.eye(3)
+        rs[:, j] = [R[0, 0], R[1, 1], R[2, 2], R[0, 1], R[0, 2], R[1, 2]]
+    pr0 = P.small_channel(16, ny, 32)
+    mean = np.stack([np.ones(ny), np.ones(ny), np.zeros(ny), np.zeros(ny), np.full(ny, pr0.R_gas)])
+    params = P.df_inflow_params(mean, rs, 2.0, 2.0, 0.5, 1)
+    bcs = list(pr0.bcs)
+    bcs[P.FACE_XM] = (P.BC_DF_INFLOW, params)
+    bcs[P.FACE_XP] = (P.BC_OUTFLOW_CHAR, np.zeros(0))
+    import dataclasses
+    pr = dataclasses.replace(pr0, bcs=bcs)
+    _, _, a = oracle.df_coeffs(pr)
+    for j in range(ny):
+        A = np.array([[a[0, j], 0, 0], [a[1, j], a[2, j], 0], [a[3, j], a[4, j], a[5, j]]])
+        R = np.array([[rs[0, j], rs[3, j], rs[4, j]], [rs[3, j], rs[1, j], rs[5, j]],
+                      [rs[4, j], rs[5, j], rs[2, j]]])
+        assert np.abs(A @ A.T - R).max() <= 1e-13 * max(1.0, np.abs(R).max())
+    assert np.all(a[:, ny - 4:] == 0.0)
 
 
 def test_df_filtered_field_variance_and_spatial_correlation():

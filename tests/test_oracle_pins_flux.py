@@ -380,3 +380,42 @@ def test_extrema_closed_form():
     ex2 = oracle.extrema(pr, w2)
     assert ex2[3] == 3
     assert abs(ex2[0] - 0.6) <= 1e-15 and abs(ex2[1] - 0.7 / g) <= 1e-15 and abs(ex2[2] - 2.5) <= 1e-13
+
+
+def test_boundary_layer_wall_is_a_reflecting_recovery_temperature_wall():
+    """The boundary-layer wall (Sec. 3.2: characteristic treatment at the
+    no-slip wall with the temperature at its nominal recovery value T_r =
+    1 + (gamma-1)/2 Pr^(1/3) M^2) is the staggered isothermal wall at T_r.
+    Linearised about the wall state with any impedance Z = rho c, the
+    acoustic invariant entering the domain from each ghost equals the one
+    leaving through the wall from its mirror node, p_g + Z v_g = p_m - Z v_m
+    (total reflection of the outgoing wave, as the characteristic wall
+    condition of zero normal velocity prescribes), the tangential velocity
+    and the temperature interpolate to 0 and T_r at the wall, and the ghost
+    pressure equals the mirror's (no pressure gradient forced through the
+    wall)."""
+    pr = P.small_boundary_layer()
+    kind, params = pr.bcs[P.FACE_YM]
+    M = 2.0
+    T_r = 1.0 + 0.5 * (pr.gamma - 1.0) * pr.Pr ** (1.0 / 3.0) * M * M
+    assert kind == P.BC_WALL_ISOTHERMAL and abs(params[0] - T_r) <= 1e-15 * T_r
+    rng = np.random.Generator(np.random.PCG64(3))
+    w0 = pr.w0.copy()
+    w0[2] += 0.05 * rng.uniform(-1, 1, w0[2].shape) * w0[0]   # wall-normal motion to reflect
+    prw = P.with_state(pr, w0)
+    g, Rg = pr.gamma, pr.R_gas
+    gh = oracle.ghosts_y(prw, 2)
+    hw = gh.shape[1]
+    for s in range(1, hw + 1):
+        mirror = w0[:, :, s - 1, :]
+        ghost = gh[:, s - 1, :, hw:hw + pr.nx]
+        rm, um, vm, wm, pm, Tm = _prims(mirror, g, Rg)
+        rg, ug, vg, wg, pg, Tg = _prims(ghost, g, Rg)
+        for Z in (0.5, 1.0, float(np.sqrt(g * pm.mean() / rm.mean()) * rm.mean())):
+            w_in = pg + Z * vg
+            w_out = pm - Z * vm
+            assert np.abs(w_in - w_out).max() <= 1e-13 * np.abs(pm).max()
+        assert np.abs(0.5 * (ug + um)).max() <= 1e-15 and np.abs(0.5 * (wg + wm)).max() <= 1e-15
+        assert np.abs(0.5 * (Tg + Tm) - T_r).max() <= 1e-13 * T_r
+        assert np.abs(pg - pm).max() <= 1e-13 * np.abs(pm).max()
+    assert np.abs(w0[2][:, 0, :]).max() > 1e-3  # the reflected wave is not trivial
