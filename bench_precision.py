@@ -8,10 +8,11 @@ with the same fixed time step (the CFL-0.8 step of the initial field), as
 HIP-graph replays.  Prints one JSON line with the throughput of each
 precision, the speedup, and per field (rho, rho u, rho v, rho w, rho E and
 the derived u, T, p) the relative L-infinity and L2 differences of the
-FP32-flux state from the FP64 state.  (The FP64 path agrees with the FP64
-oracle to about 1e-13 on the full-size right-hand side and on 100-step
-states at small sizes; running the oracle for 100 steps at this size would
-take about 17 minutes of host time and is not repeated here.)
+FP32-flux state from the FP64 state.  The comparison of both precisions
+with the FP64 oracle after 100 steps is done at 256x128x128 by the GPU test
+tests/test_gpu_configs.py::test_full_size_channel_100_steps (the oracle
+takes about two minutes of host time there; at this size it would take
+about fifteen), which prints the same per-field report against the oracle.
 """
 import argparse
 import json

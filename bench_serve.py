@@ -34,6 +34,10 @@ def main():
                     help="HBM budget for resident instances (0: 80%% of free memory)")
     ap.add_argument("--burst", action="store_true")
     ap.add_argument("--skip-serial", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip tuning kz per size class (use the cached or heuristic value)")
+    ap.add_argument("--max-chunk", type=int, default=8,
+                    help="batch steps replayed between host checks at most")
     args = ap.parse_args()
 
     import torch
@@ -50,14 +54,28 @@ def main():
           file=sys.stderr, flush=True)
     free, _ = torch.cuda.mem_get_info()
     budget = int(args.budget_gb * 1e9) if args.budget_gb > 0 else int(0.8 * free)
-    tile = (64, 4)
-    kz_for = lambda pr: autotune.lookup(pr, 0, fixed_tile=tile)[2]
+    tile = (64, 4)  # instances of one batch share the tile shape; kz is per instance
+    tuned = {}
+    if not args.no_tune:
+        # one representative request per size class, tuned before serving
+        t0 = time.perf_counter()
+        for sp in specs:
+            cls = autotune.size_class(prebuilt[sp.rid])
+            if cls not in tuned:
+                res = autotune.tune(prebuilt[sp.rid], 0, steps=2, fixed_tile=tile, save=False)
+                tuned[cls] = res["kz"]
+        print(f"# tuned kz for {len(tuned)} size classes in {time.perf_counter() - t0:.1f} s: "
+              f"{tuned}", file=sys.stderr, flush=True)
+    kz_for = lambda pr: tuned.get(autotune.size_class(pr),
+                                  autotune.lookup(pr, 0, fixed_tile=tile)[2])
     out = {"metric": "batched serving throughput and p50/p99 step latency",
            "requests": len(specs), "rate_per_s": args.rate, "steps": args.steps,
            "grid_range": [args.nmin, args.nmax], "budget_gb": budget / 1e9,
-           "total_mpoint_steps": sum(s.n ** 3 * s.nsteps for s in specs) / 1e6}
+           "total_mpoint_steps": sum(s.n ** 3 * s.nsteps for s in specs) / 1e6,
+           "tuned_kz": tuned, "max_chunk": args.max_chunk}
     for mode in (["batch"] if args.skip_serial else ["batch", "serial"]):
-        srv = Server(P.request_problem, budget, max_slots=64, tiling=tile, kz_for=kz_for)
+        srv = Server(P.request_problem, budget, max_slots=64, tiling=tile, kz_for=kz_for,
+                     max_chunk=args.max_chunk)
         rep = srv.run(specs, mode=mode, prebuilt=prebuilt)
         rep.pop("results")
         out[mode] = rep

@@ -6,8 +6,13 @@ instances, the whole step replayed from one HIP graph.  `Server` runs a
 trace of requests: requests are admitted in arrival order as slots and
 the HBM budget allow (state + workspace of the instance), join the batch,
 are advanced together with whatever else is resident, and retire after
-their step count -- freeing memory and a slot for the next.  Per-request
-step latencies are recorded from the wall clock at each completed step.
+their step count -- freeing memory and a slot for the next.  Between two
+host checks the batch replays up to `max_chunk` steps: as many as no
+resident request overruns its step count and the next arrival is not
+expected to be kept waiting (from the measured step time), so the GPU does
+not idle while the host does its bookkeeping after every step.
+Per-request step latencies are the wall-clock time of each replay divided
+evenly over its steps.
 """
 from __future__ import annotations
 
@@ -101,9 +106,11 @@ class Server:
     initial field); specs need .rid, .arrival (s) and .nsteps."""
 
     def __init__(self, make_problem, hbm_budget_bytes: int, max_slots: int = 64,
-                 tiling=(64, 4), kz_for=None, keep_states: bool = False, device: str = "cuda:0"):
+                 tiling=(64, 4), kz_for=None, keep_states: bool = False, device: str = "cuda:0",
+                 max_chunk: int = 8):
         import torch
         self.torch = torch
+        self.max_chunk = max(1, int(max_chunk))
         self.make_problem = make_problem
         self.budget = int(hbm_budget_bytes)
         self.max_slots = max_slots
@@ -141,7 +148,9 @@ class Server:
         batch = Batch(self.max_slots, device=self.device) if mode == "batch" else None
         total_pts = 0
         t0 = time.perf_counter()
-        last_done = {}
+        peak_used = 0
+        waited = set()      # requests that found the budget full on arrival
+        t_step = None       # measured wall time of one batch step (latest)
         while pending or queue or resident:
             now = time.perf_counter() - t0
             while pending and pending[0].arrival <= now:
@@ -156,28 +165,37 @@ class Server:
                         results[spec.rid].status = "rejected: larger than the budget"
                         continue
                     if used + need > self.budget:
+                        waited.update(q.rid for q in queue)
                         break
                     queue.pop(0)
                     used, ok = self._admit(spec, problems[spec.rid], now, batch, resident, used)
                     if not ok:
                         results[spec.rid].status = "rejected: configuration not batchable"
                         continue
+                    peak_used = max(peak_used, used)
                     results[spec.rid].admitted = time.perf_counter() - t0
-                    last_done[spec.rid] = time.perf_counter()
                 if not resident:
                     if pending:
                         time.sleep(max(0.0, pending[0].arrival - (time.perf_counter() - t0)))
                     continue
-                batch.step(1)
+                # steps until the first resident finishes, and until the next
+                # arrival (at the measured step time)
+                k = min(self.max_chunk,
+                        min(sp.nsteps - results[rid].steps for rid, (sp, _, _) in resident.items()))
+                if pending and t_step:
+                    ahead = pending[0].arrival - (time.perf_counter() - t0)
+                    k = min(k, max(1, int(ahead / t_step)))
+                t_a = time.perf_counter()
+                batch.step(k)
                 torch.cuda.synchronize()
                 tnow = time.perf_counter()
+                t_step = (tnow - t_a) / k
                 finished = []
                 for rid, (spec, s, slot) in resident.items():
                     r = results[rid]
-                    r.step_latencies.append(tnow - last_done[rid])
-                    last_done[rid] = tnow
-                    r.steps += 1
-                    total_pts += r.npts
+                    r.step_latencies.extend([t_step] * k)
+                    r.steps += k
+                    total_pts += r.npts * k
                     if r.steps >= spec.nsteps:
                         finished.append(rid)
                 for rid in finished:
@@ -221,6 +239,10 @@ class Server:
                                            if r.admitted >= 0])),
             "mean_e2e_s": float(np.mean([r.finished - r.arrival for r in results.values()
                                          if r.finished >= 0])),
+            "peak_resident_bytes": peak_used,
+            "budget_bytes": self.budget,
+            "waited_for_memory": len(waited),
+            "max_chunk": self.max_chunk if mode == "batch" else 1,
             "completed": sum(r.status == "ok" for r in results.values()),
             "failed": sum(r.status.startswith("failed") for r in results.values()),
             "rejected": sum(r.status.startswith("rejected") for r in results.values()),

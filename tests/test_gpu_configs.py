@@ -166,21 +166,55 @@ def _full_size_steps(pr, nsteps, label):
     return w_o, dt
 
 
+def precision_report(pr, states, w_o):
+    """Per-field relative L-infinity and L2 differences from the oracle state
+    w_o: conserved variables and the derived u, T, p."""
+    cv = pr.R_gas / (pr.gamma - 1.0)
+
+    def fields(w):
+        r = w[0]
+        ke = 0.5 * (w[1] ** 2 + w[2] ** 2 + w[3] ** 2) / r ** 2
+        T = (w[4] / r - ke) / cv
+        out = dict(zip(["rho", "rho_u", "rho_v", "rho_w", "rho_E"], w))
+        out.update(u=w[1] / r, T=T, p=r * pr.R_gas * T)
+        return out
+
+    ref = fields(w_o)
+    rep = {}
+    for name, w in states.items():
+        f = fields(w)
+        rep[name] = {k: {"linf_rel": float(np.abs(f[k] - ref[k]).max() / np.abs(ref[k]).max()),
+                         "l2_rel": float(np.linalg.norm(f[k] - ref[k]) / np.linalg.norm(ref[k]))}
+                     for k in ref}
+    return rep
+
+
 def test_full_size_channel_100_steps(torch_cuda):
     """Channel 256x128x128 (Mach 1.5, Re_b 3000, hybrid, bulk forcing) over
-    100 RK steps; the FP32-flux mode's error against the same oracle state
-    is reported per field and bounded loosely (its pointwise maxima sit
-    where the flow is shocked; see the precision notes)."""
+    100 RK steps.  The FP32-flux mode's difference from the same oracle
+    state is reported per field (conserved and u, T, p; printed as one
+    JSON line) next to the FP64 path's, and bounded loosely: its L2
+    differences stay at 1e-5 - 1e-3, its pointwise maxima reach the
+    percent level where the flow is shocked (single-precision rounding
+    moves sensor decisions near the threshold over this shock-capturing
+    transient)."""
+    import json
     from paper_2004_02276_amd import Solver
     pr = P.channel()
     w_o, dt = _full_size_steps(pr, 100, "channel")
-    s = Solver(pr, precision=1)
-    s.advance(100, dt_fixed=dt)
-    w_f = s.get_state()
-    s.close()
-    linf, l2 = field_errors(w_f, w_o), field_l2(w_f, w_o)
-    say(f"    fp32-flux vs oracle: rel Linf {['%.1e' % e for e in linf]}  rel L2 {['%.1e' % e for e in l2]}")
+    states = {}
+    for name, prec in (("fp64", 0), ("fp32flux", 1)):
+        s = Solver(pr, precision=prec)
+        s.advance(100, dt_fixed=dt)
+        states[name] = s.get_state()
+        s.close()
+    rep = precision_report(pr, states, w_o)
+    say("    precision vs oracle " + json.dumps({"workload": pr.name, "steps": 100, "dt": dt,
+                                                 "vs_oracle": rep}))
+    l2 = [v["l2_rel"] for v in rep["fp32flux"].values()]
+    linf = [v["linf_rel"] for v in rep["fp32flux"].values()]
     assert max(l2) <= 1e-3 and max(linf) <= 0.2
+    assert max(v["linf_rel"] for v in rep["fp64"].values()) <= STATE_TOL
 
 
 def test_half_resolution_sbli_200_steps(torch_cuda):
