@@ -280,6 +280,20 @@ cdns_status cdns_stats_accumulate(cdns_ctx* ctx);
 cdns_status cdns_stats_export(cdns_ctx* ctx, double* host_out, int64_t* samples);
 cdns_status cdns_stats_reset(cdns_ctx* ctx);
 
+/* Mean fields of the accumulated statistics, written on the device to
+ * out_dev [CDNS_NMEAN][ny][nx], or [CDNS_NMEAN][ny] with average_x != 0
+ * (the x sums taken i ascending); asynchronous.  With m the sums divided by
+ * samples * nz (* nx): Reynolds mean density, Favre mean velocities
+ * m(rho u_i)/rho, Favre stresses m(rho u_i u_j)/rho - u~_i u~_j for ij = 11,
+ * 22, 33, 12, the Reynolds mean u and its rms, mean T, Favre mean T
+ * m(rho T)/rho, rms of T, mean p and its rms, rms of rho (each rms from the
+ * second moment, clipped at zero).  CDNS_EINVAL when no sample was
+ * accumulated. */
+enum { CDNS_MN_RHO = 0, CDNS_MN_U_FAVRE, CDNS_MN_V_FAVRE, CDNS_MN_W_FAVRE, CDNS_MN_R11,
+       CDNS_MN_R22, CDNS_MN_R33, CDNS_MN_R12, CDNS_MN_U, CDNS_MN_U_RMS, CDNS_MN_T,
+       CDNS_MN_T_FAVRE, CDNS_MN_T_RMS, CDNS_MN_P, CDNS_MN_P_RMS, CDNS_MN_RHO_RMS, CDNS_NMEAN };
+cdns_status cdns_stats_means(cdns_ctx* ctx, int32_t average_x, double* out_dev);
+
 /* Test hooks: node sensor value theta, node flags and interface flags
  * (bit d: interface i+1/2 in direction d is shock-capturing) of the last
  * right-hand side evaluated by cdns_rhs (device arrays [nz][ny][nx]).

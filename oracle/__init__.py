@@ -117,6 +117,8 @@ def _load():
         lib.ora_num_threads.restype = ctypes.c_int
         lib.ora_stats.argtypes = [pp, dp, dp]
         lib.ora_stats.restype = ctypes.c_int
+        lib.ora_stats_means.argtypes = [pp, dp, ctypes.c_long, ctypes.c_int, dp]
+        lib.ora_stats_means.restype = ctypes.c_int
         lib.ora_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         lib.ora_splitmix64.restype = ctypes.c_uint64
         lib.ora_df_update.argtypes = [pp, ctypes.c_uint64, ctypes.c_double, ctypes.c_int, dp, dp,
@@ -392,3 +394,20 @@ def stats(pr, w: np.ndarray, acc: Optional[np.ndarray] = None) -> np.ndarray:
     m = _Marshalled(pr)
     _check(lib.ora_stats(ctypes.byref(m.s), _dptr(w), _dptr(acc)), "ora_stats")
     return acc
+
+
+MEAN_NAMES = ["rho", "u_favre", "v_favre", "w_favre", "R11", "R22", "R33", "R12", "u", "u_rms",
+              "T", "T_favre", "T_rms", "p", "p_rms", "rho_rms"]
+
+
+def stats_means(pr, acc: np.ndarray, samples: int, average_x: bool = False) -> dict:
+    """Mean fields (MEAN_NAMES) from sums accumulated by `stats` over
+    `samples` states: arrays over (y, x), or over y with average_x."""
+    lib = _load()
+    acc = np.ascontiguousarray(acc, dtype=np.float64)
+    shp = (16, pr.ny) if average_x else (16, pr.ny, pr.nx)
+    out = np.zeros(shp)
+    m = _Marshalled(pr)
+    _check(lib.ora_stats_means(ctypes.byref(m.s), _dptr(acc), int(samples), int(bool(average_x)),
+                               _dptr(out)), "ora_stats_means")
+    return {name: out[q] for q, name in enumerate(MEAN_NAMES)}

@@ -1102,22 +1102,34 @@ static int rhs_core(const ora_problem* P, const double* w, double* r, double* th
  * (Sec. 2.2).  theta (node sensor values), nflags (node flags) and iflags
  * (bit d set when interface i+1/2 in direction d is shock-capturing) are
  * optional outputs; forcing_out receives the bulk force. */
-int ora_rhs(const ora_problem* P, const double* w, double* r, double* theta,
-            unsigned char* nflags, unsigned char* iflags, double* forcing_out) {
-  if (P->bc_kind[0] != BC_DF_INFLOW || P->df_plane)
-    return rhs_core(P, w, r, theta, nflags, iflags, forcing_out);
-  /* digital-filter inflow without a plane: the initial plane (key 0) */
+/* A copy Q of the problem whose digital-filter inflow (if any, and without
+ * a plane of its own) uses the generator's initial plane (key 0), held in
+ * *buf until the caller frees it. */
+static int with_inflow_plane(const ora_problem* P, ora_problem* Q, double** buf) {
+  *Q = *P;
+  *buf = NULL;
+  if (P->bc_kind[0] != BC_DF_INFLOW || P->df_plane) return ORA_OK;
   int st = validate(P);
   if (st) return st;
   size_t np = (size_t)P->nz * P->ny;
   double* psi = malloc(3 * np * sizeof(double));
   double* plane = malloc(5 * np * sizeof(double));
   if (!psi || !plane) { free(psi); free(plane); return ORA_ENOMEM; }
-  ora_problem Q = *P;
   st = ora_df_update(P, 0, 0.0, 1, psi, plane, NULL);
-  Q.df_plane = plane;
+  free(psi);
+  if (st) { free(plane); return st; }
+  Q->df_plane = plane;
+  *buf = plane;
+  return ORA_OK;
+}
+
+int ora_rhs(const ora_problem* P, const double* w, double* r, double* theta,
+            unsigned char* nflags, unsigned char* iflags, double* forcing_out) {
+  ora_problem Q;
+  double* plane;
+  int st = with_inflow_plane(P, &Q, &plane);
   if (!st) st = rhs_core(&Q, w, r, theta, nflags, iflags, forcing_out);
-  free(psi); free(plane);
+  free(plane);
   return st;
 }
 
@@ -1299,6 +1311,46 @@ int ora_stats(const ora_problem* P, const double* w, double* acc) {
   return ORA_OK;
 }
 
+/* Mean fields from the accumulated sums acc[16][ny][nx] of `samples`
+ * states: with m = sums / (samples nz), or the x sums (i ascending) divided
+ * by samples nz nx when average_x, out[16][ny][nx] (or [16][ny]) holds the
+ * Reynolds mean density, the Favre mean velocities, the Favre stresses
+ * R11, R22, R33, R12, u and its rms, T, the Favre mean T, the rms of T,
+ * p and its rms, and the rms of rho; the rms values from the second
+ * moments, clipped at zero (Favre average: rho-weighted mean; Favre
+ * stress: rho-weighted mean of the product of the fluctuations about the
+ * Favre means). */
+int ora_stats_means(const ora_problem* P, const double* acc, long samples, int average_x,
+                    double* out) {
+  if (samples <= 0) return ORA_EINVAL;
+  const int nx = P->nx, ny = P->ny;
+  const size_t plane = (size_t)nx * ny;
+  const int ncol = average_x ? ny : nx * ny;
+  const double cnt = (double)samples * P->nz * (average_x ? nx : 1);
+  for (int c = 0; c < ncol; ++c) {
+    double m[16];
+    for (int q = 0; q < 16; ++q) {
+      double s = 0.0;
+      if (average_x)
+        for (int i = 0; i < nx; ++i) s += acc[(size_t)q * plane + (size_t)c * nx + i];
+      else
+        s = acc[(size_t)q * plane + (size_t)c];
+      m[q] = s / cnt;
+    }
+    const double rho = m[0];
+    const double uf = m[1] / rho, vf = m[2] / rho, wf = m[3] / rho;
+    const double o[16] = {rho, uf, vf, wf,
+                          m[4] / rho - uf * uf, m[5] / rho - vf * vf, m[6] / rho - wf * wf,
+                          m[7] / rho - uf * vf,
+                          m[8], sqrt(fmax(m[9] - m[8] * m[8], 0.0)),
+                          m[10], m[11] / rho, sqrt(fmax(m[12] - m[10] * m[10], 0.0)),
+                          m[13], sqrt(fmax(m[14] - m[13] * m[13], 0.0)),
+                          sqrt(fmax(m[15] - rho * rho, 0.0))};
+    for (int q = 0; q < 16; ++q) out[(size_t)q * ncol + c] = o[q];
+  }
+  return ORA_OK;
+}
+
 int ora_num_threads(void) {
   int n = 1;
 #ifdef _OPENMP
@@ -1317,6 +1369,14 @@ int ora_num_threads(void) {
 int ora_iface_flux(const ora_problem* P, const double* w, int d, double* out) {
   int st = validate(P);
   if (st) return st;
+  if (P->bc_kind[0] == BC_DF_INFLOW && !P->df_plane) {
+    ora_problem Q;
+    double* plane;
+    st = with_inflow_plane(P, &Q, &plane);
+    if (!st) st = ora_iface_flux(&Q, w, d, out);
+    free(plane);
+    return st;
+  }
   work_t a;
   if (work_alloc(P, &a)) return ORA_ENOMEM;
   st = prepare(P, w, &a);
@@ -1352,17 +1412,11 @@ int ora_ghosts_y(const ora_problem* P, const double* w, int face, double* out, i
   if (st) return st;
   if (face != 2 && face != 3) return ORA_EINVAL;
   if (P->bc_kind[0] == BC_DF_INFLOW && !P->df_plane) {
-    /* digital-filter inflow without a plane: the initial plane (key 0), as
-     * for the right-hand side */
-    size_t np = (size_t)P->nz * P->ny;
-    double* psi = malloc(3 * np * sizeof(double));
-    double* plane = malloc(5 * np * sizeof(double));
-    if (!psi || !plane) { free(psi); free(plane); return ORA_ENOMEM; }
-    ora_problem Q = *P;
-    st = ora_df_update(P, 0, 0.0, 1, psi, plane, NULL);
-    Q.df_plane = plane;
+    ora_problem Q;
+    double* plane;
+    st = with_inflow_plane(P, &Q, &plane);
     if (!st) st = ora_ghosts_y(&Q, w, face, out, hw_out);
-    free(psi); free(plane);
+    free(plane);
     return st;
   }
   work_t a;
@@ -1389,6 +1443,14 @@ int ora_lf_alpha(const ora_problem* P, const double* w, int d, int i, int j, int
                  double* alpha) {
   int st = validate(P);
   if (st) return st;
+  if (P->bc_kind[0] == BC_DF_INFLOW && !P->df_plane) {
+    ora_problem Q;
+    double* plane;
+    st = with_inflow_plane(P, &Q, &plane);
+    if (!st) st = ora_lf_alpha(&Q, w, d, i, j, k, alpha);
+    free(plane);
+    return st;
+  }
   if (d < 0 || d > 2 || i < 0 || i >= P->nx || j < 0 || j >= P->ny || k < 0 || k >= P->nz)
     return ORA_EINVAL;
   work_t a;

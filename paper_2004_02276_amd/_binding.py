@@ -19,6 +19,8 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -
 CDNS_FP64, CDNS_FP32_FLUX = 0, 1
 PHASES = ["dt", "ghosts", "sensor", "iflags", "weno", "rhs", "force", "rk"]
 NSTAT = 16  # running-statistics products (CDNS_NSTAT)
+MEAN_NAMES = ["rho", "u_favre", "v_favre", "w_favre", "R11", "R22", "R33", "R12", "u", "u_rms",
+              "T", "T_favre", "T_rms", "p", "p_rms", "rho_rms"]  # CDNS_MN_* order
 NDIAG_DEV = 10  # slots of cdns_diagnostics_noalloc's output (CDNS_NDIAG_DEV)
 DIAG_DEV_NAMES = ["mass", "mom_x", "mom_y", "mom_z", "energy", "kinetic", "rho_min", "p_min",
                   "mach_max", "nonfinite"]
@@ -31,7 +33,7 @@ EXPORTED = [
     "cdns_rhs", "cdns_rk_step", "cdns_advance_n", "cdns_diagnostics",
     "cdns_diagnostics_noalloc", "cdns_export_sensor",
     "cdns_export_iface_flux", "cdns_time_phases", "cdns_stats_accumulate", "cdns_stats_export",
-    "cdns_stats_reset",
+    "cdns_stats_reset", "cdns_stats_means",
     "cdns_last_error", "cdns_destroy", "cdns_batch_create", "cdns_batch_workspace_bytes",
     "cdns_batch_attach", "cdns_batch_detach", "cdns_batch_set_step", "cdns_batch_step",
     "cdns_batch_destroy",
@@ -127,6 +129,8 @@ def load() -> ctypes.CDLL:
     lib.cdns_stats_export.restype = i32
     lib.cdns_stats_reset.argtypes = [vp]
     lib.cdns_stats_reset.restype = i32
+    lib.cdns_stats_means.argtypes = [vp, i32, dp]
+    lib.cdns_stats_means.restype = i32
     lib.cdns_last_error.argtypes = [vp]
     lib.cdns_last_error.restype = ctypes.c_char_p
     lib.cdns_destroy.argtypes = [vp]

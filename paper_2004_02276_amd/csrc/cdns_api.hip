@@ -805,6 +805,17 @@ cdns_status cdns_stats_export(cdns_ctx* c, double* host_out, int64_t* samples) {
   return CDNS_OK;
 }
 
+cdns_status cdns_stats_means(cdns_ctx* c, int32_t average_x, double* out_dev) {
+  if (!c) return CDNS_EINVAL;
+  if (!out_dev) return fail(c, CDNS_EINVAL, "null output");
+  if (c->stat_samples <= 0) return fail(c, CDNS_EINVAL, "no statistics accumulated");
+  const Desc& D = c->D;
+  const double count = (double)c->stat_samples * D.nz * (average_x ? D.nx : 1);
+  hipError_t e = cdns::launch_stats_means(D, average_x != 0, count, out_dev, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "statistics means");
+  return CDNS_OK;
+}
+
 cdns_status cdns_stats_reset(cdns_ctx* c) {
   if (!c) return CDNS_EINVAL;
   const Desc& D = c->D;

@@ -116,6 +116,9 @@ hipError_t launch_count_iface(const Desc& D, bool reset, hipStream_t st);  // sc
 hipError_t launch_df(const Desc& D, bool initial, hipStream_t st);
 constexpr int kNStat = 16;  // running-statistics products (CDNS_NSTAT)
 hipError_t launch_stats(const Desc& D, hipStream_t st);
+// mean fields [kNStat][ny][nx] (or [kNStat][ny] averaged along x) from the
+// accumulated sums, count = samples * nz (* nx when averaged)
+hipError_t launch_stats_means(const Desc& D, bool avg, double count, double* out, hipStream_t st);
 hipError_t launch_export_iface(const Desc& D, int dir, double* out, hipStream_t st);
 bool rhs_tile_supported(int tx, int ty);
 int rhs_blocks(const Desc& D);

@@ -2102,6 +2102,47 @@ __global__ void k_stats(Desc D) {
   for (int q = 0; q < kNStat; ++q) D.stats[(size_t)q * plane + (size_t)t] += acc[q];
 }
 
+// Mean fields from the accumulated sums S (count samples x nz, times nx
+// when averaged along x, the x sums taken i ascending): with m = S/count,
+// rho, Favre means m(rho u_i)/rho, Favre stresses m(rho u_i u_j)/rho -
+// u~_i u~_j (11, 22, 33, 12), u, u_rms, T, T~ = m(rho T)/rho, T_rms, p,
+// p_rms, rho_rms (rms from the second moments, clipped at zero).  One
+// thread per output column (j, i), or per row j when averaged.
+__global__ void k_stats_means(Desc D, int avg, double count, double* __restrict__ out) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long ncol = avg ? (long long)D.ny : (long long)D.nx * D.ny;
+  if (t >= ncol) return;
+  const size_t plane = (size_t)D.nx * D.ny;
+  double m[kNStat];
+#pragma unroll
+  for (int q = 0; q < kNStat; ++q) {
+    double s = 0.0;
+    if (avg) {
+      for (int i = 0; i < D.nx; ++i) s += D.stats[(size_t)q * plane + (size_t)t * D.nx + i];
+    } else {
+      s = D.stats[(size_t)q * plane + (size_t)t];
+    }
+    m[q] = s / count;
+  }
+  const double rho = m[0], ir = 1.0 / rho;
+  const double uf = m[1] * ir, vf = m[2] * ir, wf = m[3] * ir;
+  auto rms = [](double sq, double mean) { return sqrt(fmax(sq - mean * mean, 0.0)); };
+  const double o[kNStat] = {rho, uf, vf, wf,
+                            m[4] * ir - uf * uf, m[5] * ir - vf * vf, m[6] * ir - wf * wf,
+                            m[7] * ir - uf * vf,
+                            m[8], rms(m[9], m[8]), m[10], m[11] * ir, rms(m[12], m[10]),
+                            m[13], rms(m[14], m[13]), rms(m[15], rho)};
+  const size_t stride = (size_t)ncol;
+#pragma unroll
+  for (int q = 0; q < kNStat; ++q) out[(size_t)q * stride + (size_t)t] = o[q];
+}
+
+hipError_t launch_stats_means(const Desc& D, bool avg, double count, double* out, hipStream_t st) {
+  const long long ncol = avg ? (long long)D.ny : (long long)D.nx * D.ny;
+  k_stats_means<<<nblk(ncol, 128), 128, 0, st>>>(D, avg ? 1 : 0, count, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_stats(const Desc& D, hipStream_t st) {
   k_stats<<<nblk((long long)D.nx * D.ny, 256), 256, 0, st>>>(D);
   return hipGetLastError();

@@ -200,27 +200,21 @@ class Solver:
         return out, int(n.value)
 
     def stats(self, average_x: bool = False) -> Dict:
-        """Mean fields from the running statistics: spanwise (and, with
-        average_x, streamwise) Reynolds means, Favre means rho u_i/rho,
-        Favre stresses R_ij = rho u_i u_j/rho - u~_i u~_j (ij = 11, 22, 33,
-        12), rms of u, T, p and rho; arrays over (y, x) or over y."""
-        S, n = self.stats_raw()
-        if n == 0:
-            raise ValueError("no statistics accumulated")
-        cnt = n * self.pr.nz
-        if average_x:
-            S = S.sum(axis=2)
-            cnt *= self.pr.nx
-        m = S / cnt
-        rho = m[0]
-        uf, vf, wf = m[1] / rho, m[2] / rho, m[3] / rho
-        var = lambda sq, mean: np.maximum(sq - mean * mean, 0.0)
-        return {"samples": n, "rho": rho, "u_favre": uf, "v_favre": vf, "w_favre": wf,
-                "R11": m[4] / rho - uf * uf, "R22": m[5] / rho - vf * vf,
-                "R33": m[6] / rho - wf * wf, "R12": m[7] / rho - uf * vf,
-                "u": m[8], "u_rms": np.sqrt(var(m[9], m[8])), "T": m[10], "T_favre": m[11] / rho,
-                "T_rms": np.sqrt(var(m[12], m[10])), "p": m[13], "p_rms": np.sqrt(var(m[14], m[13])),
-                "rho_rms": np.sqrt(var(m[15], rho))}
+        """Mean fields from the running statistics (computed by the library,
+        cdns_stats_means): spanwise (and, with average_x, streamwise)
+        Reynolds and Favre means, Favre stresses R11, R22, R33, R12, rms of
+        u, T, p and rho; arrays over (y, x), or over y with average_x."""
+        t = self.torch
+        shp = (B.NSTAT, self.pr.ny) if average_x else (B.NSTAT, self.pr.ny, self.pr.nx)
+        out = t.empty(shp, dtype=t.float64, device=self.device)
+        B.check(self.lib, self.ctx,
+                self.lib.cdns_stats_means(self.ctx, int(bool(average_x)), out.data_ptr()),
+                "cdns_stats_means")
+        self.stream.synchronize()
+        host = out.cpu().numpy()
+        res = {name: host[q] for q, name in enumerate(B.MEAN_NAMES)}
+        res["samples"] = self.stats_raw()[1]
+        return res
 
     def export_iface_flux(self, d: int):
         t = self.torch

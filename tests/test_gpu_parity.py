@@ -370,10 +370,23 @@ def test_running_statistics_match_oracle(torch_cuda):
         s.advance(5, dt_fixed=dt)
         w = oracle.advance(P.with_state(pr, w), 5, dt_fixed=dt)
     g, n = s.stats_raw()
-    st = s.stats(average_x=True)
+    means = {avg: s.stats(average_x=avg) for avg in (False, True)}
     s.close()
     assert n == 3
     err = np.abs(g - acc).max(axis=(1, 2)) / np.maximum(np.abs(acc).max(axis=(1, 2)), 1e-300)
     say(f"    max rel err {err.max():.2e}")
     assert err.max() <= 1e-12
-    assert st["rho"].shape == (pr.ny,) and np.all(st["u_rms"] >= 0)
+    # mean fields derived by the library against the oracle's from its own sums
+    for avg, mg in means.items():
+        mo = oracle.stats_means(pr, acc, 3, average_x=avg)
+        assert mg["samples"] == 3 and mg["rho"].shape == mo["rho"].shape
+        worst = 0.0
+        for k, ref in mo.items():
+            scale = max(np.abs(ref).max(), 1e-300)
+            # rms values are square roots of second-moment differences: their
+            # rounding is ~ sqrt(eps) of the field scale where they are small
+            tol = 1e-7 if k.endswith("_rms") else 1e-10
+            e = np.abs(mg[k] - ref).max() / scale
+            worst = max(worst, e if tol < 1e-9 else 0.0)
+            assert e <= tol, (avg, k, e)
+        say(f"    means (average_x={avg}) max rel err {worst:.2e}")

@@ -39,3 +39,39 @@ def test_stats_closed_form():
     # accumulation adds
     acc2 = oracle.stats(pr, w, acc.copy())
     np.testing.assert_allclose(acc2, 2 * acc, rtol=1e-15)
+
+
+def test_stats_means_closed_form_with_density_fluctuations():
+    """Favre and Reynolds means differ when density and velocity fluctuate
+    together: rho = r0 (1 + b s), u = U + a s, v = c s with s = sin(2 pi m z /
+    L_z) over full periods (mean of s 0, of s^2 1/2, of s^3 0), uniform p.
+    Then <rho> = r0, Favre u~ = U + a b/2, R11 = <rho u u>/<rho> - u~^2 =
+    a^2 (1/2 - b^2/4), R12 = a c (1/2 - b^2/4), u_rms = a/sqrt 2, rho_rms =
+    r0 b/sqrt 2, p_rms = 0; the x average of x-independent fields equals
+    the field."""
+    pr = P.small_channel(12, 10, 16)
+    nz, ny, nx = pr.nz, pr.ny, pr.nx
+    z = np.arange(nz) * (pr.lz / nz)
+    s = np.sin(2 * np.pi * 2 * z / pr.lz)[:, None, None] * np.ones((nz, ny, nx))
+    r0, b, a, c, U = 1.2, 0.3, 0.25, -0.1, 0.8
+    rho = r0 * (1 + b * s)
+    u = U + a * s
+    v = c * s
+    p = np.full((nz, ny, nx), pr.R_gas)
+    w = P.conserved_from_primitive(rho, u, v, np.zeros_like(u), p, pr.gamma)
+    acc = oracle.stats(pr, w)
+    acc = oracle.stats(pr, w, acc)            # two samples of the same state
+    for avg in (False, True):
+        mn = oracle.stats_means(pr, acc, 2, average_x=avg)
+        f = 1.0 / 2 - b * b / 4
+        checks = {"rho": r0, "u_favre": U + a * b / 2, "v_favre": c * b / 2, "R11": a * a * f,
+                  "R22": c * c * f, "R12": a * c * f, "R33": 0.0, "u": U,
+                  "u_rms": a / np.sqrt(2), "rho_rms": r0 * b / np.sqrt(2), "p": pr.R_gas}
+        for k, v_ in checks.items():
+            np.testing.assert_allclose(mn[k], v_, rtol=1e-12, atol=1e-12, err_msg=k)
+        # a zero variance from the difference of second moments: sqrt of rounding
+        assert np.abs(mn["p_rms"]).max() <= 1e-7 * pr.R_gas
+        assert mn["rho"].shape == ((ny,) if avg else (ny, nx))
+    # T = p/(rho R): rho T = p/R is uniform, so the Favre mean of T is 1/r0
+    mn = oracle.stats_means(pr, acc, 2)
+    np.testing.assert_allclose(mn["T_favre"], 1.0 / r0, rtol=1e-12)
