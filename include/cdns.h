@@ -181,6 +181,15 @@ cdns_status cdns_create(const cdns_grid* grid, const cdns_phys* phys, int32_t pr
 cdns_status cdns_set_bc(cdns_ctx* ctx, int32_t face, int32_t kind, const double* params,
                         int64_t nparams);
 
+/* Debugging hook: fills every double-precision work region of the
+ * workspace that the stepping path writes before reading it (stage states,
+ * residual registers, shock-capturing fluxes, sensor values, ghost planes,
+ * inflow-generator fields, reduction partials) with NaN, so that a read of
+ * memory no kernel has written shows up as a NaN in the results.  The
+ * digital-filter inflow's initial plane is regenerated.  Synchronises;
+ * CDNS_EBUSY while attached to a batch. */
+cdns_status cdns_poison_workspace(cdns_ctx* ctx);
+
 /* Tile shape of the fused right-hand-side kernel: (tile_x, tile_y) must be
  * one of the compiled variants (64x4, 32x8, 64x2, 128x2, 64x8), kz >= 1
  * planes per block.  Results are bitwise independent of the choice except

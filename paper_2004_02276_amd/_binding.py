@@ -29,7 +29,7 @@ NOALLOC_MAX_POINTS = 33554432  # CDNS_NOALLOC_MAX_POINTS
 EXPORTED = [
     "cdns_version", "cdns_workspace_bytes", "cdns_create", "cdns_set_bc", "cdns_set_tiling",
     "cdns_set_scheme", "cdns_set_state", "cdns_get_state", "cdns_export_flags",
-    "cdns_import_flags",
+    "cdns_import_flags", "cdns_poison_workspace",
     "cdns_rhs", "cdns_rk_step", "cdns_advance_n", "cdns_diagnostics",
     "cdns_diagnostics_noalloc", "cdns_export_sensor",
     "cdns_export_iface_flux", "cdns_time_phases", "cdns_stats_accumulate", "cdns_stats_export",
@@ -94,6 +94,8 @@ def load() -> ctypes.CDLL:
     lib.cdns_create.restype = i32
     lib.cdns_set_bc.argtypes = [vp, i32, i32, ctypes.POINTER(f64), i64]
     lib.cdns_set_bc.restype = i32
+    lib.cdns_poison_workspace.argtypes = [vp]
+    lib.cdns_poison_workspace.restype = i32
     lib.cdns_set_tiling.argtypes = [vp, i32, i32, i32]
     lib.cdns_set_tiling.restype = i32
     lib.cdns_set_scheme.argtypes = [vp, i32, i32]

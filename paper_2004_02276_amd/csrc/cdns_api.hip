@@ -394,6 +394,44 @@ static void df_derive(int ny, const double* p, std::vector<double>& out) {
   }
 }
 
+cdns_status cdns_poison_workspace(cdns_ctx* c) {
+  if (!c) return CDNS_EINVAL;
+  if (c->batch_refs > 0) return fail(c, CDNS_EBUSY, "context attached to a batch");
+  const Desc& D = c->D;
+  cdns_grid g{};
+  g.nx = D.nx;
+  g.ny = D.ny;
+  g.nz = D.nz;
+  const Layout L = layout_of(&g);
+  // every double-precision work region the stepping path must write before
+  // it reads (0xFF bytes are a NaN in every double)
+  const size_t N = (size_t)D.N, nz = D.nz, ny = D.ny;
+  const size_t regions[][2] = {
+      {L.w1, 5 * N * sizeof(double)},
+      {L.w2, 5 * N * sizeof(double)},
+      {L.ra, 5 * N * sizeof(double)},
+      {L.rb, 5 * N * sizeof(double)},
+      {L.theta, N * sizeof(double)},
+      {L.fw, 3 * 5 * N * sizeof(double)},
+      {L.gx, 2 * 5 * cdns::kHalo * nz * ny * sizeof(double)},
+      {L.gy, 2 * 5 * cdns::kHalo * nz * (size_t)D.nxg * sizeof(double)},
+      {L.df, 2 * 3 * nz * ny * sizeof(double)},
+      {L.part, L.part_cap * sizeof(double)},
+      {L.red, 2 * cdns::kRedBlocks * sizeof(double)},
+      {L.redd, (size_t)cdns::DG_COUNT * cdns::kRedBlocks * sizeof(double)},
+      {L.diag, cdns::DG_COUNT * sizeof(double)}};
+  hipError_t e = hipSuccess;
+  for (const auto& r : regions)
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + r[0], 0xFF, r[1], c->stream);
+  // the inflow generator's state is set up with the boundary: again
+  if (e == hipSuccess && D.bc[0] == cdns::BC_DF_INFLOW) e = cdns::launch_df(D, true, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "workspace poisoning");
+  c->last_rhs_valid = false;
+  invalidate_graph(c);
+  return CDNS_OK;
+}
+
 cdns_status cdns_set_bc(cdns_ctx* c, int32_t face, int32_t kind, const double* params,
                         int64_t nparams) {
   if (!c) return CDNS_EINVAL;

@@ -107,6 +107,12 @@ class Solver:
                 "cdns_import_flags")
         self.stream.synchronize()
 
+    def poison_workspace(self) -> None:
+        """Fill the work regions of the workspace with NaN (debugging: reads
+        of memory no kernel has written then show up in the results)."""
+        B.check(self.lib, self.ctx, self.lib.cdns_poison_workspace(self.ctx),
+                "cdns_poison_workspace")
+
     # ------------------------------------------------------------ operations
     def set_tiling(self, tile_x: int, tile_y: int, kz: int) -> None:
         B.check(self.lib, self.ctx, self.lib.cdns_set_tiling(self.ctx, tile_x, tile_y, kz),
