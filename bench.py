@@ -47,24 +47,29 @@ STEP_BYTES_PER_PT_FORCED = 448.0
 RHS_RK_BYTES_PER_PT = 400.0 / 3.0
 RHS_RK_SPLIT_BYTES_PER_PT = 120.0
 # FP64 operations of one shock-capturing interface flux in the kernel's
-# formulation (k_weno: weno_flux, weno3/5/7, half_sum), counted from the
+# formulation (weno_node, weno_flux, weno3/5/7, half_sum), counted from the
 # source with a fused multiply-add as two, a reciprocal or square root as
 # one, comparisons and absolute values as none; by WENO order 2r-1:
-#  - Roe average of nodes i, i+1 (two reciprocals, pressures, enthalpies,
-#    square roots, weighted means) and the eigenvector constants: 65;
-#  - per stencil node (2r of them): primitives, pressure, sound speed 15,
-#    projection of the state on the left eigenvectors 21, projection of the
-#    Euler flux from it (u_n L w + p L(0, 1, 0, 0, u_n)) 15, eigenvalue
-#    bounds 2: 53;
+#  - the quantities of a node along the direction (reciprocal of the
+#    density, velocities, pressure, sound speed: 15), which every node needs
+#    once per direction, so one node's worth per interface: 15;
+#  - Roe average of nodes i, i+1 from their quantities (reciprocal
+#    densities, tangential velocities, enthalpies, square roots, weighted
+#    means) and the eigenvector constants: 47;
+#  - per stencil node (2r of them): projection of the state on the left
+#    eigenvectors 21, projection of the Euler flux from it
+#    (u_n L w + p L(0, 1, 0, 0, u_n)) 15, eigenvalue bounds 2: 38;
 #  - per characteristic field (5): Lax-Friedrichs splitting 2 (2r - 1) x 2,
-#    two reconstructions (WENO3 18, WENO5 62, WENO7 146 each), the half
+#    two reconstructions (WENO3 18, WENO5 65, WENO7 146 each), the half
 #    sum of the two with one reciprocal 7;
 #  - back-projection on the right eigenvectors: 26.
-# WENO5: 65 + 6 x 53 + 5 x (20 + 124 + 7) + 26 = 1164.
-WENO_FLOPS_BY_ORDER = {3: 578.0, 5: 1164.0, 7: 2150.0}
+# WENO5: 15 + 47 + 6 x 38 + 5 x (20 + 130 + 7) + 26 = 1101.  (The kernel
+# converts each stencil node of every interface, 2r per interface: a node's
+# quantities are computed by each of the 2r interfaces that reach it.)
+WENO_FLOPS_BY_ORDER = {3: 515.0, 5: 1101.0, 7: 2027.0}
 # Hash of the source region the count was taken from (weno_source_hash());
 # a CPU test fails when that code changes, so the count cannot go stale.
-WENO_FLOPS_SOURCE_HASH = "1f3e37daafbc24b4"
+WENO_FLOPS_SOURCE_HASH = "9b65bd50cf83e1ab"
 WENO_FLOPS_PER_IFACE = WENO_FLOPS_BY_ORDER[5]
 
 

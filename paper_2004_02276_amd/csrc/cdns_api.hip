@@ -43,7 +43,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t metric, bcp, w1, w2, ra, rb, nflag, slot, theta, fw, list, count, gx, gy, df, stats, part, red,
+  size_t metric, bcp, w1, w2, ra, rb, nflag, slot, theta, fw, list, count, sync, gx, gy, df, stats, part, red,
       redd, scal, status, diag, total;
   size_t bcp_cap, part_cap;
 };
@@ -82,6 +82,7 @@ Layout layout_of(const cdns_grid* g) {
   L.fw = take(3 * 5 * N * sizeof(double));
   L.list = take(3 * N * sizeof(int));
   L.count = take(4 * sizeof(unsigned));
+  L.sync = take(4 * sizeof(unsigned long long));
   L.gx = take(2 * 5 * cdns::kHalo * nz * ny * sizeof(double));
   L.gy = take(2 * 5 * cdns::kHalo * nz * nxg * sizeof(double));
   L.df = take(2 * 3 * nz * ny * sizeof(double));
@@ -144,16 +145,20 @@ void default_tiling(Desc& D) {
 // Enqueue the right-hand-side phases of one stage (ghosts .. forcing sum).
 // keep_flags: use the node flags already in place (imported) instead of
 // running the sensor.
+// with_dt: the sensor also reduces the step's time-step bounds and the step
+// is set right after it (first stage of a step, dt_in_sensor(D)).
 hipError_t enqueue_rhs_phases(const Desc& D, int stage, bool export_theta, hipStream_t st,
-                              bool keep_flags = false, bool fuse_rk = false) {
+                              bool keep_flags = false, bool fuse_rk = false,
+                              bool with_dt = false) {
   hipError_t e;
   // list counters: reset by the sensor kernel in hybrid mode, else here
   if ((D.sensor_mode == 2 || keep_flags) && (e = cdns::launch_stage_begin(D, st)) != hipSuccess)
     return e;
   if ((e = cdns::launch_ghosts(D, stage, st)) != hipSuccess) return e;
   if (D.sensor_mode == 1 && !keep_flags &&
-      (e = cdns::launch_sensor(D, stage, export_theta, st)) != hipSuccess)
+      (e = cdns::launch_sensor(D, stage, export_theta, st, with_dt)) != hipSuccess)
     return e;
+  if (with_dt && (e = cdns::launch_dt_max(D, st)) != hipSuccess) return e;
   if (D.sensor_mode > 0) {
     if ((e = cdns::launch_iflags(D, st)) != hipSuccess) return e;
     if ((e = cdns::launch_weno(D, stage, st)) != hipSuccess) return e;
@@ -165,12 +170,16 @@ hipError_t enqueue_rhs_phases(const Desc& D, int stage, bool export_theta, hipSt
 
 hipError_t enqueue_step(const Desc& D, hipStream_t st) {
   hipError_t e;
-  if ((e = cdns::launch_dt(D, st)) != hipSuccess) return e;
+  // the time step: reduced by the first stage's sensor, or by its own kernels
+  const bool dt_sen = cdns::dt_in_sensor(D);
+  if (!dt_sen && (e = cdns::launch_dt(D, st)) != hipSuccess) return e;
   // inflow plane of this step (needs the step's dt and counter)
   if (D.bc[0] == cdns::BC_DF_INFLOW && (e = cdns::launch_df(D, false, st)) != hipSuccess) return e;
   const bool fuse = cdns::rk_fused(D);  // update inside the right-hand-side pass
   for (int stage = 0; stage < 3; ++stage) {
-    if ((e = enqueue_rhs_phases(D, stage, false, st, false, fuse)) != hipSuccess) return e;
+    if ((e = enqueue_rhs_phases(D, stage, false, st, false, fuse, dt_sen && stage == 0)) !=
+        hipSuccess)
+      return e;
     if (!fuse) e = cdns::launch_rk(D, stage, st);
     else if (D.forcing) e = cdns::launch_rk_forced(D, stage, st);
     if (e != hipSuccess) return e;
@@ -292,6 +301,7 @@ cdns_status cdns_create(const cdns_grid* grid, const cdns_phys* phys, int32_t pr
     D.slot[d] = (int*)(ws + L.slot) + (size_t)d * D.N;
   }
   D.count = (unsigned*)(ws + L.count);
+  D.dtmax = (unsigned long long*)(ws + L.sync);
   const size_t gxs = (size_t)5 * cdns::kHalo * nz * ny;
   const size_t gys = (size_t)5 * cdns::kHalo * nz * D.nxg;
   D.gx[0] = (double*)(ws + L.gx);
@@ -321,6 +331,7 @@ cdns_status cdns_create(const cdns_grid* grid, const cdns_phys* phys, int32_t pr
       (e = hipMemcpyAsync(metric + 3 * ny, c->h_iye2.data(), ny * sizeof(double),
                           hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
       (e = hipMemsetAsync(ws + L.count, 0, align_up(4 * sizeof(unsigned)), c->stream)) != hipSuccess ||
+      (e = hipMemsetAsync(ws + L.sync, 0, 4 * sizeof(unsigned long long), c->stream)) != hipSuccess ||
       (e = hipMemsetAsync(ws + L.scal, 0, cdns::SC_COUNT * sizeof(double), c->stream)) != hipSuccess ||
       (e = hipMemsetAsync(ws + L.status, 0, 4 * sizeof(unsigned), c->stream)) != hipSuccess ||
       (e = hipMemsetAsync(ws + L.slot, 0xFF, 3 * D.N * sizeof(int), c->stream)) != hipSuccess ||
@@ -774,8 +785,9 @@ cdns_status cdns_time_phases(cdns_ctx* c, int32_t nsteps, double cfl, double dt_
     e = hipEventRecord(r.b, st);
   };
   if (D.sensor_mode > 0) e = cdns::launch_count_iface(D, true, st);
+  const bool dt_sen = cdns::dt_in_sensor(D);
   for (int step = 0; step < nsteps && e == hipSuccess; ++step) {
-    timed(CDNS_PH_DT, [&] { return cdns::launch_dt(D, st); });
+    if (!dt_sen) timed(CDNS_PH_DT, [&] { return cdns::launch_dt(D, st); });
     if (D.bc[0] == cdns::BC_DF_INFLOW)
       timed(CDNS_PH_GHOSTS, [&] { return cdns::launch_df(D, false, st); });
     for (int stage = 0; stage < 3; ++stage) {
@@ -783,7 +795,9 @@ cdns_status cdns_time_phases(cdns_ctx* c, int32_t nsteps, double cfl, double dt_
       if (cdns::ghosts_needed(D))
         timed(CDNS_PH_GHOSTS, [&] { return cdns::launch_ghosts(D, stage, st); });
       if (D.sensor_mode == 1)
-        timed(CDNS_PH_SENSOR, [&] { return cdns::launch_sensor(D, stage, false, st); });
+        timed(CDNS_PH_SENSOR,
+              [&] { return cdns::launch_sensor(D, stage, false, st, dt_sen && stage == 0); });
+      if (dt_sen && stage == 0) timed(CDNS_PH_DT, [&] { return cdns::launch_dt_max(D, st); });
       if (D.sensor_mode > 0) {
         timed(CDNS_PH_IFLAGS, [&] { return cdns::launch_iflags(D, st); });
         timed(CDNS_PH_WENO, [&] { return cdns::launch_weno(D, stage, st); });

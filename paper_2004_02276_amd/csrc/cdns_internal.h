@@ -75,6 +75,9 @@ struct Desc {
   double* redd;                   // [DG_COUNT*kRedBlocks] diagnostics partials
   double* scal;                   // [SC_COUNT]
   unsigned* status;               // [1]
+  unsigned long long* dtmax;      // [2] largest convective and viscous time-step bounds of
+                                  // the step as ordered bit patterns (non-negative doubles),
+                                  // zero between steps
   double* diag;                   // [DG_COUNT]
   // launch geometry of the fused right-hand-side kernel
   int tile_x, tile_y, kz, tiles_x, tiles_y, zchunks;
@@ -86,7 +89,13 @@ struct Desc {
 hipError_t launch_stage_begin(const Desc& D, hipStream_t st);
 bool ghosts_needed(const Desc& D);  // does launch_ghosts launch anything
 hipError_t launch_ghosts(const Desc& D, int stage, hipStream_t st);
-hipError_t launch_sensor(const Desc& D, int stage, bool export_theta, hipStream_t st);
+// with_dt: the first stage of a step, whose sensor also reduces the time-step
+// bounds (dt_in_sensor(D)); launch_dt_max then sets the step (they replace
+// launch_dt)
+hipError_t launch_sensor(const Desc& D, int stage, bool export_theta, hipStream_t st,
+                         bool with_dt = false);
+bool dt_in_sensor(const Desc& D);
+hipError_t launch_dt_max(const Desc& D, hipStream_t st);
 hipError_t launch_iflags(const Desc& D, hipStream_t st);
 hipError_t launch_weno(const Desc& D, int stage, hipStream_t st);
 // fuse_rk: the RK update of the stage in the same pass (rk_fused(D) only)

@@ -397,6 +397,12 @@ __device__ __forceinline__ void wflux(const PV<F>* nd, F f[5]) {
   else wall_flux<F, DIR, L>(nd, f);
 }
 
+// The shock-capturing flux code below (reconstructions, node quantities,
+// flux) is evaluated without automatic contraction and with its fused
+// multiply-adds written out, so that every kernel that runs it (single
+// instances, batched instances) computes the same bits whatever the code
+// around it.
+
 // WENO5-JS reconstruction at i+1/2 from v_{i-2..i+2}.  The argument `eps4`
 // is four times the regulariser: the callers pass twice the split fluxes
 // (the factor 1/2 of the splitting is applied once to the sum), and
@@ -405,23 +411,25 @@ __device__ __forceinline__ void wflux(const PV<F>* nd, F f[5]) {
 // The reconstruction is num / den; the caller divides.
 template <typename F>
 __device__ __forceinline__ void weno5(F vm2, F vm1, F v0, F vp1, F vp2, F eps4, F& num, F& den) {
+#pragma clang fp contract(off)
   // candidate reconstructions, times 6 (the 1/6 is applied with the weights)
-  const F q0 = F(2) * vm2 - F(7) * vm1 + F(11) * v0;
-  const F q1 = -vm1 + F(5) * v0 + F(2) * vp1;
-  const F q2 = F(2) * v0 + F(5) * vp1 - vp2;
-  const F d0 = vm2 - F(2) * vm1 + v0, e0 = vm2 - F(4) * vm1 + F(3) * v0;
-  const F d1 = vm1 - F(2) * v0 + vp1, e1 = vm1 - vp1;
-  const F d2 = v0 - F(2) * vp1 + vp2, e2 = F(3) * v0 - F(4) * vp1 + vp2;
-  const F s0 = eps4 + F(13.0 / 12.0) * d0 * d0 + F(0.25) * e0 * e0;
-  const F s1 = eps4 + F(13.0 / 12.0) * d1 * d1 + F(0.25) * e1 * e1;
-  const F s2 = eps4 + F(13.0 / 12.0) * d2 * d2 + F(0.25) * e2 * e2;
+  const F q0 = fma(F(11), v0, fma(F(-7), vm1, F(2) * vm2));
+  const F q1 = fma(F(2), vp1, fma(F(5), v0, -vm1));
+  const F q2 = fma(F(5), vp1, fma(F(2), v0, -vp2));
+  const F d0 = fma(F(-2), vm1, vm2 + v0), e0 = fma(F(3), v0, fma(F(-4), vm1, vm2));
+  const F d1 = fma(F(-2), v0, vm1 + vp1), e1 = vm1 - vp1;
+  const F d2 = fma(F(-2), vp1, v0 + vp2), e2 = fma(F(3), v0, fma(F(-4), vp1, vp2));
+  const F c13 = F(13.0 / 12.0), c14 = F(0.25);
+  const F s0 = fma(c13 * d0, d0, fma(c14 * e0, e0, eps4));
+  const F s1 = fma(c13 * d1, d1, fma(c14 * e1, e1, eps4));
+  const F s2 = fma(c13 * d2, d2, fma(c14 * e2, e2, eps4));
   // weights d_k/(eps+beta_k)^2 normalised, with numerator and denominator
   // multiplied by 10 times the product of the three squares (d = 0.1, 0.6,
   // 0.3 become 1, 6, 3): a = (t1 t2, 6 t0 t2, 3 t0 t1), one reciprocal
   const F t0 = s0 * s0, t1 = s1 * s1, t2 = s2 * s2;
   const F P = t1 * t2, B = F(3) * t1, C = F(6) * t2;
-  num = P * q0 + t0 * (C * q1 + B * q2);
-  den = F(6) * (P + t0 * (C + B));
+  num = fma(P, q0, t0 * fma(C, q1, B * q2));
+  den = F(6) * fma(t0, C + B, P);
 }
 
 // WENO3-JS (two candidate stencils, linear weights 1/3, 2/3) at i+1/2 from
@@ -429,13 +437,14 @@ __device__ __forceinline__ void weno5(F vm2, F vm1, F v0, F vp1, F vp2, F eps4, 
 // multiplied by 3 t0 t1 (a = (t1, 2 t0)) and the candidates by 2.
 template <typename F>
 __device__ __forceinline__ void weno3(F vm1, F v0, F vp1, F eps4, F& num, F& den) {
-  const F q0 = F(3) * v0 - vm1;
+#pragma clang fp contract(off)
+  const F q0 = fma(F(3), v0, -vm1);
   const F q1 = v0 + vp1;
   const F d0 = v0 - vm1, d1 = vp1 - v0;
-  const F s0 = eps4 + d0 * d0, s1 = eps4 + d1 * d1;
+  const F s0 = fma(d0, d0, eps4), s1 = fma(d1, d1, eps4);
   const F t0 = s0 * s0, t1 = s1 * s1;
-  num = t1 * q0 + F(2) * t0 * q1;
-  den = F(2) * (t1 + F(2) * t0);
+  num = fma(t1, q0, (F(2) * t0) * q1);
+  den = F(2) * fma(F(2), t0, t1);
 }
 
 // WENO7-JS (four candidate stencils, linear weights (1, 12, 18, 4)/35) at
@@ -447,29 +456,31 @@ __device__ __forceinline__ void weno3(F vm1, F v0, F vp1, F eps4, F& num, F& den
 // reciprocal each (a product form would overflow in FP32).
 template <typename F>
 __device__ __forceinline__ void weno7(const F* v, F eps4, F& num, F& den) {
+#pragma clang fp contract(off)
   const F a = v[0], b = v[1], d = v[2], e = v[3], f = v[4], g = v[5], h = v[6];
-  const F q0 = F(-3) * a + F(13) * b - F(23) * d + F(25) * e;
-  const F q1 = b - F(5) * d + F(13) * e + F(3) * f;
-  const F q2 = -d + F(7) * e + F(7) * f - g;
-  const F q3 = F(3) * e + F(13) * f - F(5) * g + h;
+  const F q0 = fma(F(25), e, fma(F(-23), d, fma(F(13), b, F(-3) * a)));
+  const F q1 = fma(F(3), f, fma(F(13), e, fma(F(-5), d, b)));
+  const F q2 = fma(F(7), f, fma(F(7), e, -d)) - g;
+  const F q3 = fma(F(3), e, fma(F(13), f, fma(F(-5), g, h)));
   const F c240 = F(1.0 / 240.0);
-  const F b0 = c240 * (a * (F(547) * a - F(3882) * b + F(4642) * d - F(1854) * e) +
-                       b * (F(7043) * b - F(17246) * d + F(7042) * e) +
-                       d * (F(11003) * d - F(9402) * e) + F(2107) * e * e);
-  const F b1 = c240 * (b * (F(267) * b - F(1642) * d + F(1602) * e - F(494) * f) +
-                       d * (F(2843) * d - F(5966) * e + F(1922) * f) +
-                       e * (F(3443) * e - F(2522) * f) + F(547) * f * f);
-  const F b2 = c240 * (d * (F(547) * d - F(2522) * e + F(1922) * f - F(494) * g) +
-                       e * (F(3443) * e - F(5966) * f + F(1602) * g) +
-                       f * (F(2843) * f - F(1642) * g) + F(267) * g * g);
-  const F b3 = c240 * (e * (F(2107) * e - F(9402) * f + F(7042) * g - F(1854) * h) +
-                       f * (F(11003) * f - F(17246) * g + F(4642) * h) +
-                       g * (F(7043) * g - F(3882) * h) + F(547) * h * h);
+  // sum of x_k times a linear form, the last term a square
+  const F b0 = c240 * fma(a, fma(F(-1854), e, fma(F(4642), d, fma(F(-3882), b, F(547) * a))),
+                          fma(b, fma(F(7042), e, fma(F(-17246), d, F(7043) * b)),
+                              fma(d, fma(F(-9402), e, F(11003) * d), (F(2107) * e) * e)));
+  const F b1 = c240 * fma(b, fma(F(-494), f, fma(F(1602), e, fma(F(-1642), d, F(267) * b))),
+                          fma(d, fma(F(1922), f, fma(F(-5966), e, F(2843) * d)),
+                              fma(e, fma(F(-2522), f, F(3443) * e), (F(547) * f) * f)));
+  const F b2 = c240 * fma(d, fma(F(-494), g, fma(F(1922), f, fma(F(-2522), e, F(547) * d))),
+                          fma(e, fma(F(1602), g, fma(F(-5966), f, F(3443) * e)),
+                              fma(f, fma(F(-1642), g, F(2843) * f), (F(267) * g) * g)));
+  const F b3 = c240 * fma(e, fma(F(-1854), h, fma(F(7042), g, fma(F(-9402), f, F(2107) * e))),
+                          fma(f, fma(F(4642), h, fma(F(-17246), g, F(11003) * f)),
+                              fma(g, fma(F(-3882), h, F(7043) * g), (F(547) * h) * h)));
   const F s0 = eps4 + b0, s1 = eps4 + b1, s2 = eps4 + b2, s3 = eps4 + b3;
   const F w0 = wrcp<F>(s0 * s0), w1 = F(12) * wrcp<F>(s1 * s1);
   const F w2 = F(18) * wrcp<F>(s2 * s2), w3 = F(4) * wrcp<F>(s3 * s3);
-  num = w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3;
-  den = F(12) * (w0 + w1 + w2 + w3);
+  num = fma(w0, q0, fma(w1, q1, fma(w2, q2, w3 * q3)));
+  den = F(12) * (((w0 + w1) + w2) + w3);
 }
 
 // Reconstruction of order 2R-1 at i+1/2 from v[0..2R-2] = v_{i-R+1..i+R-1},
@@ -487,51 +498,70 @@ __device__ __forceinline__ void wrec(const F* v, F eps4, F& num, F& den) {
 // product stays far inside the FP64 range; FP32 takes one reciprocal each.
 template <typename F>
 __device__ __forceinline__ F half_sum(F np, F dp, F nm, F dm) {
-  if constexpr (sizeof(F) == 8) return (np * dm + nm * dp) * wrcp<F>(F(2) * (dp * dm));
-  else return F(0.5) * (np * wrcp<F>(dp) + nm * wrcp<F>(dm));
+#pragma clang fp contract(off)
+  if constexpr (sizeof(F) == 8) return fma(np, dm, nm * dp) * wrcp<F>(F(2) * (dp * dm));
+  else return F(0.5) * fma(np, wrcp<F>(dp), nm * wrcp<F>(dm));
 }
 
-// Lax-Friedrichs split characteristic WENO flux of order 2R-1 at interface
-// i+1/2 along DIR from the conserved states of the 2R nodes i-R+1..i+R
-// (stencil index s = 0..2R-1, Sec. 2.1).  Eigenvectors at the Roe average
-// of nodes i, i+1; splitting constant per field from the largest
-// |eigenvalue| over the stencil.
-template <typename F, int DIR, int R, typename Loader>
-__device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5]) {
-  constexpr int NS = 2 * R;
+// Quantities of one stencil node of the shock-capturing flux along DIR: the
+// conserved state in the permuted order (rho, m_n, m_t1, m_t2, E), the
+// normal velocity, the pressure (gamma-1)(E - m.u/2) and the sound speed.
+template <typename F>
+struct WNode {
+  F r, mn, m1, m2, E, un, p, c;
+};
+
+template <typename F, int DIR>
+__device__ __forceinline__ void weno_node(const Desc& D, const double q[5], WNode<F>& n) {
+#pragma clang fp contract(off)
   constexpr int PN = 1 + DIR, P1 = 1 + (DIR + 1) % 3, P2 = 1 + (DIR + 2) % 3;
   const F gm1 = (F)D.gm1, gam = (F)D.gamma;
   const F hgm1 = F(0.5) * gm1;
-  // pressure from the momentum and the velocity: (gamma-1)(E - m.u/2)
-  auto press = [&](F E, F m0, F u0, F m1, F u1, F m2, F u2) {
-    return gm1 * E - hgm1 * (m0 * u0 + m1 * u1 + m2 * u2);
-  };
+  n.r = (F)q[0];
+  n.mn = (F)q[PN];
+  n.m1 = (F)q[P1];
+  n.m2 = (F)q[P2];
+  n.E = (F)q[4];
+  const F ir = wrcp<F>(n.r);
+  n.un = n.mn * ir;
+  const F t1 = n.m1 * ir, t2 = n.m2 * ir;
+  n.p = fma(-hgm1, fma(n.mn, n.un, fma(n.m1, t1, n.m2 * t2)), gm1 * n.E);
+  n.c = wsqrt<F>((gam * n.p) * ir);
+}
+
+// Lax-Friedrichs split characteristic WENO flux of order 2R-1 at interface
+// i+1/2 along DIR from the 2R nodes i-R+1..i+R (stencil index s = 0..2R-1,
+// node(s, n) gives node s's quantities; Sec. 2.1).  Eigenvectors at the
+// Roe average of nodes i, i+1; splitting constant per field from the
+// largest |eigenvalue| over the stencil.
+template <typename F, int DIR, int R, typename NodeGet>
+__device__ __forceinline__ void weno_flux(const Desc& D, NodeGet&& node, F out[5]) {
+#pragma clang fp contract(off)
+  constexpr int NS = 2 * R;
+  constexpr int PN = 1 + DIR, P1 = 1 + (DIR + 1) % 3, P2 = 1 + (DIR + 2) % 3;
+  const F gm1 = (F)D.gm1;
   // Roe average of nodes i (s=R-1) and i+1 (s=R)
   F ur, vr, wr, Hr;
   {
-    double qa[5], qb[5];
-    get(R - 1, qa);
-    get(R, qb);
-    const F ra = (F)qa[0], rb = (F)qb[0];
-    const F ira = wrcp<F>(ra), irb = wrcp<F>(rb);
-    const F una = (F)qa[PN] * ira, t1a = (F)qa[P1] * ira, t2a = (F)qa[P2] * ira;
-    const F unb = (F)qb[PN] * irb, t1b = (F)qb[P1] * irb, t2b = (F)qb[P2] * irb;
-    const F Ea = (F)qa[4], Eb = (F)qb[4];
-    const F pa = press(Ea, (F)qa[PN], una, (F)qa[P1], t1a, (F)qa[P2], t2a);
-    const F pb = press(Eb, (F)qb[PN], unb, (F)qb[P1], t1b, (F)qb[P2], t2b);
-    const F Ha = (Ea + pa) * ira, Hb = (Eb + pb) * irb;
-    const F sl = wsqrt<F>(ra), sr = wsqrt<F>(rb);
+    WNode<F> a, b;
+    node(R - 1, a);
+    node(R, b);
+    const F ira = wrcp<F>(a.r), irb = wrcp<F>(b.r);
+    const F t1a = a.m1 * ira, t2a = a.m2 * ira;
+    const F t1b = b.m1 * irb, t2b = b.m2 * irb;
+    const F Ha = (a.E + a.p) * ira, Hb = (b.E + b.p) * irb;
+    const F sl = wsqrt<F>(a.r), sr = wsqrt<F>(b.r);
     const F iw = wrcp<F>(sl + sr);
-    ur = (sl * una + sr * unb) * iw;
-    vr = (sl * t1a + sr * t1b) * iw;
-    wr = (sl * t2a + sr * t2b) * iw;
-    Hr = (sl * Ha + sr * Hb) * iw;
+    ur = fma(sl, a.un, sr * b.un) * iw;
+    vr = fma(sl, t1a, sr * t1b) * iw;
+    wr = fma(sl, t2a, sr * t2b) * iw;
+    Hr = fma(sl, Ha, sr * Hb) * iw;
   }
-  const F q2 = ur * ur + vr * vr + wr * wr;
-  const F cr = wsqrt<F>(gm1 * (Hr - F(0.5) * q2));
+  const F q2 = fma(ur, ur, fma(vr, vr, wr * wr));
+  const F cr = wsqrt<F>(gm1 * fma(F(-0.5), q2, Hr));
   const F ic = wrcp<F>(cr);
-  const F b1 = gm1 * ic * ic;
-  const F b2 = F(0.5) * q2 * b1;
+  const F b1 = (gm1 * ic) * ic;
+  const F b2 = (F(0.5) * q2) * b1;
   // Projection on the left eigenvectors (permuted order rho, m_n, m_t1,
   // m_t2, E).  With X = b2 q0 - b1 (u q1 + v q2 + w q3) + b1 q4 and
   // Y = (u q0 - q1)/c the rows are: (X + Y)/2, q0 - X, q2 - v q0,
@@ -539,12 +569,13 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
   // (evaluated with X/2 and Y/2, which saves the two halvings)
   const F hb1 = F(0.5) * b1, hb2 = F(0.5) * b2, hic = F(0.5) * ic;
   auto project = [&](const F* q, F out[5]) {
-    const F Xh = hb2 * q[0] - hb1 * (ur * q[1] + vr * q[2] + wr * q[3]) + hb1 * q[4];
-    const F Yh = (ur * q[0] - q[1]) * hic;
+    const F m = fma(ur, q[1], fma(vr, q[2], wr * q[3]));
+    const F Xh = fma(hb1, q[4], fma(-hb1, m, hb2 * q[0]));
+    const F Yh = fma(ur, q[0], -q[1]) * hic;
     out[0] = Xh + Yh;
-    out[1] = q[0] - F(2) * Xh;
-    out[2] = q[2] - vr * q[0];
-    out[3] = q[3] - wr * q[0];
+    out[1] = fma(F(-2), Xh, q[0]);
+    out[2] = fma(-vr, q[0], q[2]);
+    out[3] = fma(-wr, q[0], q[3]);
     out[4] = Xh - Yh;
   };
   // stencil nodes: physical flux, eigenvalue bounds, characteristic projections
@@ -552,25 +583,20 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
   F am0 = F(0), am1 = F(0), am4 = F(0);
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    double qd[5];
-    get(s, qd);
-    const F r = (F)qd[0];
-    const F ir = wrcp<F>(r);
-    const F mn = (F)qd[PN], m1 = (F)qd[P1], m2 = (F)qd[P2], E = (F)qd[4];
-    const F un = mn * ir, t1 = m1 * ir, t2 = m2 * ir;
-    const F p = press(E, mn, un, m1, t1, m2, t2);
-    const F c = wsqrt<F>(gam * p * ir);
-    const F wq[5] = {r, mn, m1, m2, E};
+    WNode<F> nd;
+    node(s, nd);
+    const F un = nd.un, p = nd.p, c = nd.c;
+    const F wq[5] = {nd.r, nd.mn, nd.m1, nd.m2, nd.E};
     project(wq, v[s]);
     // the flux is f = u_n w + p (0, 1, 0, 0, u_n), so its projection is
     // u_n (L w) + p L(0, 1, 0, 0, u_n), whose rows are p (X + Y, -2 X,
     // 0, 0, X - Y) with X = b1 (u_n - u)/2 and Y = -1/(2c)
     const F pX = p * (hb1 * (un - ur)), pY = p * hic;
-    g[s][0] = un * v[s][0] + (pX - pY);
-    g[s][1] = un * v[s][1] - F(2) * pX;
+    g[s][0] = fma(un, v[s][0], pX - pY);
+    g[s][1] = fma(F(-2), pX, un * v[s][1]);
     g[s][2] = un * v[s][2];
     g[s][3] = un * v[s][3];
-    g[s][4] = un * v[s][4] + (pX + pY);
+    g[s][4] = fma(un, v[s][4], pX + pY);
     am0 = fmax(am0, fabs(un - c));
     am1 = fmax(am1, fabs(un));
     am4 = fmax(am4, fabs(un + c));
@@ -585,8 +611,8 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
     F vp[NS - 1], vm[NS - 1];
 #pragma unroll
     for (int t = 0; t < NS - 1; ++t) {
-      vp[t] = g[t][k] + a * v[t][k];                    // i-R+1..i+R-1
-      vm[t] = g[NS - 1 - t][k] - a * v[NS - 1 - t][k];  // i+R..i-R+2 (mirrored)
+      vp[t] = fma(a, v[t][k], g[t][k]);                    // i-R+1..i+R-1
+      vm[t] = fma(-a, v[NS - 1 - t][k], g[NS - 1 - t][k]);  // i+R..i-R+2 (mirrored)
     }
     F np, dp, nm, dm;
     wrec<F, R>(vp, eps4, np, dp);
@@ -594,12 +620,14 @@ __device__ __forceinline__ void weno_flux(const Desc& D, Loader&& get, F out[5])
     gh[k] = half_sum<F>(np, dp, nm, dm);
   }
   // right eigenvectors applied to the reconstructed characteristic flux
-  const F f0 = gh[0] + gh[1] + gh[4];
-  const F f1 = (ur - cr) * gh[0] + ur * gh[1] + (ur + cr) * gh[4];
-  const F f2 = vr * (gh[0] + gh[1] + gh[4]) + gh[2];
-  const F f3 = wr * (gh[0] + gh[1] + gh[4]) + gh[3];
-  const F f4 = (Hr - ur * cr) * gh[0] + F(0.5) * q2 * gh[1] + vr * gh[2] + wr * gh[3] +
-               (Hr + ur * cr) * gh[4];
+  const F sg = (gh[0] + gh[1]) + gh[4];
+  const F urc = ur * cr;
+  const F f0 = sg;
+  const F f1 = fma(ur - cr, gh[0], fma(ur, gh[1], (ur + cr) * gh[4]));
+  const F f2 = fma(vr, sg, gh[2]);
+  const F f3 = fma(wr, sg, gh[3]);
+  const F f4 = fma(Hr - urc, gh[0],
+                   fma(F(0.5) * q2, gh[1], fma(vr, gh[2], fma(wr, gh[3], (Hr + urc) * gh[4]))));
   out[0] = f0;
   out[PN] = f1;
   out[P1] = f2;
@@ -828,6 +856,50 @@ __global__ void k_ghost_y(Desc D, int stage) {
   if (t < 2LL * D.nz * D.nxg) ghost_y_body(D, D.win[stage], t);
 }
 
+// ------------------------------------------------------------------ time-step bounds
+// Largest convective and viscous time-step bounds of one node (conserved
+// state q at row j), folded into cm and vm.  Evaluated without contraction,
+// so that every kernel that takes the bound (the reduction kernel, the first
+// stage's sensor, the batched kernels) gets the same bits for a node and the
+// maxima, which do not depend on the order of the nodes, agree exactly.
+__device__ __forceinline__ void dt_node(const Desc& D, const double q[5], int j, double& cm,
+                                        double& vm) {
+#pragma clang fp contract(off)
+  const double r = q[0], ir = 1.0 / r;
+  const double u = q[1] * ir, v = q[2] * ir, ww = q[3] * ir;
+  const double T = (q[4] * ir - 0.5 * (u * u + v * v + ww * ww)) * D.icv;
+  const double p = r * D.R * T;
+  const double c = sqrt(D.gamma * p * ir);
+  const double dy = D.deta * D.y_eta[j];
+  const double conv = (fabs(u) + c) * D.idx + (fabs(v) + c) / dy + (fabs(ww) + c) * D.idz;
+  cm = fmax(cm, conv);
+  if (D.viscous) {
+    const double t = T * D.iTref;
+    const double mu = D.muc * t * sqrt(t) / (t + D.S);
+    const double vis = D.vfac * (mu * ir) * (D.idx2 + 1.0 / (dy * dy) + D.idz2);
+    vm = fmax(vm, vis);
+  }
+}
+
+// Time step of the step from the largest bounds (CFL and viscous limits),
+// or the fixed step; advances the step's time and counter.
+__device__ __forceinline__ void dt_set(const Desc& D, double cm, double vm) {
+  double dt;
+  if (D.dt_fixed > 0.0) {
+    dt = D.dt_fixed;
+  } else {
+    dt = 1.0 / cm;
+    if (D.viscous && vm > 0.0) {
+      const double dv = 2.5 / (D.rho2 * vm);
+      if (dv < dt) dt = dv;
+    }
+    dt *= D.cfl;
+  }
+  D.scal[SC_DT] = dt;
+  D.scal[SC_TIME] += dt;
+  D.scal[SC_STEP] += 1.0;
+}
+
 // ------------------------------------------------------------------ sensor
 // Ducros sensor (eq. sensor), FP64, operations in the order of the
 // definition and without contraction, so that the flag decision is
@@ -846,8 +918,11 @@ int sensor_tiles(const Desc& D) {
          ((D.nz + kSenKz - 1) / kSenKz);
 }
 
+// DT: the tile also folds its nodes' time-step bounds into cm and vm (the
+// step's first stage, whose input is the state the step starts from).
+template <bool DT = false>
 __device__ void sensor_tile(const Desc& D, const double* __restrict__ w, int lb, SenSmem& S,
-                            bool export_theta) {
+                            bool export_theta, double* cm = nullptr, double* vm = nullptr) {
   constexpr int LX = kSenTX + 4;
   const int stx = (D.nx + kSenTX - 1) / kSenTX, sty = (D.ny + kSenTY - 1) / kSenTY;
   const int txi = lb % stx, rem = lb / stx;
@@ -905,15 +980,36 @@ __device__ void sensor_tile(const Desc& D, const double* __restrict__ w, int lb,
       }
     }
   };
-  double qc[4], qh[HPS][4];
+  // own column: (rho, rho u, rho v, rho w), and rho E for the time step
+  constexpr int NQC = DT ? 5 : 4;
+  auto fetch_col = [&](int plane, double q[NQC]) {
+    if (valid) {
+      const size_t b = nidx(D, i, j, wrap1(plane, D.nz));
+#pragma unroll
+      for (int m = 0; m < NQC; ++m) q[m] = w[(size_t)m * N + b];
+    } else {
+      double qq[5];
+      load_node(D, w, i, j, plane, qq);
+#pragma unroll
+      for (int m = 0; m < NQC; ++m) q[m] = qq[m];
+    }
+  };
+  const bool dt_on = DT && valid && !(D.dt_fixed > 0.0);
+  auto bound = [&](int plane, const double q[NQC]) {
+    if constexpr (DT) {
+      if (dt_on && plane >= kb && plane < ke) dt_node(D, q, j, *cm, *vm);
+    }
+  };
+  double qc[NQC], qh[HPS][4];
 #pragma unroll
   for (int sl = 0; sl < 4; ++sl) {
-    fetch(i, j, kb - 2 + sl, valid, qc);
+    fetch_col(kb - 2 + sl, qc);
     vel(qc, U[sl], V[sl], W[sl]);
+    bound(kb - 2 + sl, qc);
   }
   // the loads of plane c+1 (own column c+3, halo c+1) are issued during
   // plane c, before its closing barrier
-  fetch(i, j, kb + 2, valid, qc);
+  fetch_col(kb + 2, qc);
   fetch_halo(kb, qh);
   for (int c = kb; c < ke; ++c) {
     vel(qc, U[4], V[4], W[4]);
@@ -933,8 +1029,10 @@ __device__ void sensor_tile(const Desc& D, const double* __restrict__ w, int lb,
         S.v[2][ly][lx] = ww;
       }
     }
+    // (after the halo conversion, when its registers are free)
+    bound(c + 2, qc);
     if (c + 1 < ke) {
-      fetch(i, j, c + 3, valid, qc);
+      fetch_col(c + 3, qc);
       fetch_halo(c + 1, qh);
     }
     __syncthreads();
@@ -971,12 +1069,38 @@ __device__ void sensor_tile(const Desc& D, const double* __restrict__ w, int lb,
   }
 }
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_sensor(Desc D, int stage, int export_theta) {
+// DT (first stage of a step): the kernel also folds the nodes' time-step
+// bounds into D.dtmax, one atomic maximum per wave on the bit patterns
+// (ordered like the values for non-negative doubles, so the result is the
+// exact maximum whatever the order); k_dt_max turns them into the step.
+template <bool DT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DT ? 3 : 4))) k_sensor(Desc D, int stage, int export_theta) {
   __shared__ SenSmem S;
   // the list counters of this stage start at zero (the previous stage's
   // lists were consumed before this kernel starts)
   if (blockIdx.x == 0 && threadIdx.x < 4) D.count[threadIdx.x] = 0u;
-  sensor_tile(D, D.win[stage], xcd_swizzle_blk(blockIdx.x, gridDim.x), S, export_theta != 0);
+  double cm = 0.0, vm = 0.0;
+  sensor_tile<DT>(D, D.win[stage], xcd_swizzle_blk(blockIdx.x, gridDim.x), S, export_theta != 0,
+                  &cm, &vm);
+  if constexpr (DT) {
+    __shared__ double red[2][4];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      cm = fmax(cm, __shfl_xor(cm, off));
+      vm = fmax(vm, __shfl_xor(vm, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      red[0][threadIdx.x >> 6] = cm;
+      red[1][threadIdx.x >> 6] = vm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      cm = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
+      vm = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
+      atomicMax(&D.dtmax[0], (unsigned long long)__double_as_longlong(cm));
+      atomicMax(&D.dtmax[1], (unsigned long long)__double_as_longlong(vm));
+    }
+  }
 }
 
 // ------------------------------------------------------------------ interface flags + lists
@@ -1199,12 +1323,9 @@ __device__ __forceinline__ void weno_entry(const Desc& D, const double* __restri
                 qn[s]);
     }
   }
-  auto get = [&](int s, double q[5]) {
-#pragma unroll
-    for (int m = 0; m < 5; ++m) q[m] = qn[s][m];
-  };
+  auto node = [&](int s, WNode<F>& nd) { weno_node<F, DIR>(D, qn[s], nd); };
   F f[5];
-  weno_flux<F, DIR, R>(D, get, f);
+  weno_flux<F, DIR, R>(D, node, f);
   double* out = D.Fw[DIR];
 #pragma unroll
   for (int m = 0; m < 5; ++m) out[(size_t)m * D.N + e] = (double)f[m];
@@ -1234,6 +1355,50 @@ __global__ void __launch_bounds__(256) k_weno(Desc D, const double* __restrict__
     else if (dir == 1) weno_entry<F, 1, R>(D, w, n, e);
     else weno_entry<F, 2, R>(D, w, n, e);
   }
+}
+
+// ------------------------------------------------------------------ reductions
+template <int NT>
+__device__ double block_sum(double v, double* sm) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < NT / 64; ++q) t += sm[q];
+  __syncthreads();
+  return t;
+}
+
+template <int NT>
+__device__ double block_max(double v, double* sm) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off));
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = sm[0];
+  if (threadIdx.x == 0)
+    for (int q = 1; q < NT / 64; ++q) t = fmax(t, sm[q]);
+  __syncthreads();
+  return t;
+}
+
+template <int NT>
+__device__ double block_min(double v, double* sm) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_down(v, off));
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = sm[0];
+  if (threadIdx.x == 0)
+    for (int q = 1; q < NT / 64; ++q) t = fmin(t, sm[q]);
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ void force_body(const Desc& D, double* sm) {
+  double v = 0.0;
+  for (int q = threadIdx.x; q < D.npart; q += 256) v += D.part[q];
+  const double t = block_sum<256>(v, sm);
+  if (threadIdx.x == 0) D.scal[SC_FORCE] = -t / D.vol_den;
 }
 
 // ------------------------------------------------------------------ fused right-hand side
@@ -1719,50 +1884,6 @@ k_rhs(Desc D, const double* __restrict__ w, double* __restrict__ R, int rk_stage
   rhs_body<F, TX, TY, VISC_ON, L, RKM>(D, w, R, lb, S, rk_stage);
 }
 
-// ------------------------------------------------------------------ reductions
-template <int NT>
-__device__ double block_sum(double v, double* sm) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
-  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0)
-    for (int q = 0; q < NT / 64; ++q) t += sm[q];
-  __syncthreads();
-  return t;
-}
-
-template <int NT>
-__device__ double block_max(double v, double* sm) {
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off));
-  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double t = sm[0];
-  if (threadIdx.x == 0)
-    for (int q = 1; q < NT / 64; ++q) t = fmax(t, sm[q]);
-  __syncthreads();
-  return t;
-}
-
-template <int NT>
-__device__ double block_min(double v, double* sm) {
-  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_down(v, off));
-  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double t = sm[0];
-  if (threadIdx.x == 0)
-    for (int q = 1; q < NT / 64; ++q) t = fmin(t, sm[q]);
-  __syncthreads();
-  return t;
-}
-
-__device__ __forceinline__ void force_body(const Desc& D, double* sm) {
-  double v = 0.0;
-  for (int q = threadIdx.x; q < D.npart; q += 256) v += D.part[q];
-  const double t = block_sum<256>(v, sm);
-  if (threadIdx.x == 0) D.scal[SC_FORCE] = -t / D.vol_den;
-}
-
 __global__ void __launch_bounds__(256) k_force(Desc D) {
   __shared__ double sm[4];
   force_body(D, sm);
@@ -1924,20 +2045,10 @@ __device__ __forceinline__ void dt_part_body(const Desc& D, int b, int nb, doubl
   double cm = 0.0, vm = 0.0;
   for (long long n = (long long)b * 256 + threadIdx.x; n < D.N; n += (long long)nb * 256) {
     const int j = (int)((n / D.nx) % D.ny);
-    const double r = w[n], ir = 1.0 / r;
-    const double u = w[N + n] * ir, v = w[2 * N + n] * ir, ww = w[3 * N + n] * ir;
-    const double T = (w[4 * N + n] * ir - 0.5 * (u * u + v * v + ww * ww)) * D.icv;
-    const double p = r * D.R * T;
-    const double c = sqrt(D.gamma * p * ir);
-    const double dy = D.deta * D.y_eta[j];
-    const double conv = (fabs(u) + c) * D.idx + (fabs(v) + c) / dy + (fabs(ww) + c) * D.idz;
-    cm = fmax(cm, conv);
-    if (D.viscous) {
-      const double t = T * D.iTref;
-      const double mu = D.muc * t * sqrt(t) / (t + D.S);
-      const double vis = D.vfac * (mu * ir) * (D.idx2 + 1.0 / (dy * dy) + D.idz2);
-      vm = fmax(vm, vis);
-    }
+    double q[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) q[m] = w[m * N + n];
+    dt_node(D, q, j, cm, vm);
   }
   cm = block_max<256>(cm, sm);
   vm = block_max<256>(vm, sm);
@@ -1953,34 +2064,37 @@ __global__ void __launch_bounds__(256) k_dt_part(Desc D) {
 }
 
 __device__ __forceinline__ void dt_final_body(const Desc& D, int nb, double* sm) {
-  double dt;
-  if (D.dt_fixed > 0.0) {
-    dt = D.dt_fixed;
-  } else {
-    double cm = 0.0, vm = 0.0;
+  double cm = 0.0, vm = 0.0;
+  if (!(D.dt_fixed > 0.0)) {
     for (int q = threadIdx.x; q < nb; q += 256) {
       cm = fmax(cm, D.red[2 * q]);
       vm = fmax(vm, D.red[2 * q + 1]);
     }
     cm = block_max<256>(cm, sm);
     vm = block_max<256>(vm, sm);
-    dt = 1.0 / cm;
-    if (D.viscous && vm > 0.0) {
-      const double dv = 2.5 / (D.rho2 * vm);
-      if (dv < dt) dt = dv;
-    }
-    dt *= D.cfl;
   }
-  if (threadIdx.x == 0) {
-    D.scal[SC_DT] = dt;
-    D.scal[SC_TIME] += dt;
-    D.scal[SC_STEP] += 1.0;
-  }
+  if (threadIdx.x == 0) dt_set(D, cm, vm);
 }
 
 __global__ void __launch_bounds__(256) k_dt_final(Desc D, int nb) {
   __shared__ double sm[4];
   dt_final_body(D, nb, sm);
+}
+
+// The step's time step from the maxima the first stage's sensor folded into
+// D.dtmax, which are cleared for the next step.
+__global__ void k_dt_max(Desc D) {
+  if (threadIdx.x != 0) return;
+  const double cm = __longlong_as_double((long long)D.dtmax[0]);
+  const double vm = __longlong_as_double((long long)D.dtmax[1]);
+  dt_set(D, cm, vm);
+  D.dtmax[0] = 0ull;
+  D.dtmax[1] = 0ull;
+}
+
+hipError_t launch_dt_max(const Desc& D, hipStream_t st) {
+  k_dt_max<<<1, 64, 0, st>>>(D);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ diagnostics
@@ -2160,10 +2274,13 @@ hipError_t launch_ghosts(const Desc& D, int stage, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_sensor(const Desc& D, int stage, bool export_theta, hipStream_t st) {
-  k_sensor<<<sensor_tiles(D), 256, 0, st>>>(D, stage, export_theta ? 1 : 0);
+hipError_t launch_sensor(const Desc& D, int stage, bool export_theta, hipStream_t st, bool with_dt) {
+  if (with_dt) k_sensor<true><<<sensor_tiles(D), 256, 0, st>>>(D, stage, export_theta ? 1 : 0);
+  else k_sensor<false><<<sensor_tiles(D), 256, 0, st>>>(D, stage, export_theta ? 1 : 0);
   return hipGetLastError();
 }
+
+bool dt_in_sensor(const Desc& D) { return D.sensor_mode == 1 && D.bc[0] != BC_DF_INFLOW; }
 
 __global__ void k_export_iflags(Desc D, uint8_t* __restrict__ out) {
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2454,7 +2571,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                                                   const BatchTable* __restrict__ T, int stage) {
   __shared__ SenSmem S;
   BATCH_FOR(WK_SEN)
-  if (D.sensor_mode == 1) sensor_tile(D, D.win[stage], local, S, false);
+  if (D.sensor_mode == 1) sensor_tile<false>(D, D.win[stage], local, S, false);
   BATCH_END
 }
 
