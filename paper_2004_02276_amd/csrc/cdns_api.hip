@@ -145,8 +145,8 @@ void default_tiling(Desc& D) {
 // Enqueue the right-hand-side phases of one stage (ghosts .. forcing sum).
 // keep_flags: use the node flags already in place (imported) instead of
 // running the sensor.
-// with_dt: the sensor also reduces the step's time-step bounds and the step
-// is set right after it (first stage of a step, dt_in_sensor(D)).
+// with_dt: the sensor also reduces the step's time-step bounds and the flag
+// kernel sets the step (first stage of a step, dt_in_sensor(D)).
 hipError_t enqueue_rhs_phases(const Desc& D, int stage, bool export_theta, hipStream_t st,
                               bool keep_flags = false, bool fuse_rk = false,
                               bool with_dt = false) {
@@ -158,9 +158,8 @@ hipError_t enqueue_rhs_phases(const Desc& D, int stage, bool export_theta, hipSt
   if (D.sensor_mode == 1 && !keep_flags &&
       (e = cdns::launch_sensor(D, stage, export_theta, st, with_dt)) != hipSuccess)
     return e;
-  if (with_dt && (e = cdns::launch_dt_max(D, st)) != hipSuccess) return e;
   if (D.sensor_mode > 0) {
-    if ((e = cdns::launch_iflags(D, st)) != hipSuccess) return e;
+    if ((e = cdns::launch_iflags(D, st, with_dt)) != hipSuccess) return e;
     if ((e = cdns::launch_weno(D, stage, st)) != hipSuccess) return e;
   }
   if ((e = cdns::launch_rhs(D, stage, st, fuse_rk)) != hipSuccess) return e;
@@ -168,9 +167,10 @@ hipError_t enqueue_rhs_phases(const Desc& D, int stage, bool export_theta, hipSt
   return hipSuccess;
 }
 
+// One RK step; the time step is reduced by the first stage's sensor, or by
+// its own kernels.
 hipError_t enqueue_step(const Desc& D, hipStream_t st) {
   hipError_t e;
-  // the time step: reduced by the first stage's sensor, or by its own kernels
   const bool dt_sen = cdns::dt_in_sensor(D);
   if (!dt_sen && (e = cdns::launch_dt(D, st)) != hipSuccess) return e;
   // inflow plane of this step (needs the step's dt and counter)
@@ -797,9 +797,9 @@ cdns_status cdns_time_phases(cdns_ctx* c, int32_t nsteps, double cfl, double dt_
       if (D.sensor_mode == 1)
         timed(CDNS_PH_SENSOR,
               [&] { return cdns::launch_sensor(D, stage, false, st, dt_sen && stage == 0); });
-      if (dt_sen && stage == 0) timed(CDNS_PH_DT, [&] { return cdns::launch_dt_max(D, st); });
       if (D.sensor_mode > 0) {
-        timed(CDNS_PH_IFLAGS, [&] { return cdns::launch_iflags(D, st); });
+        timed(CDNS_PH_IFLAGS,
+              [&] { return cdns::launch_iflags(D, st, dt_sen && stage == 0); });
         timed(CDNS_PH_WENO, [&] { return cdns::launch_weno(D, stage, st); });
         if (e == hipSuccess) e = cdns::launch_count_iface(D, false, st);  // outside the events
       }

@@ -90,13 +90,13 @@ hipError_t launch_stage_begin(const Desc& D, hipStream_t st);
 bool ghosts_needed(const Desc& D);  // does launch_ghosts launch anything
 hipError_t launch_ghosts(const Desc& D, int stage, hipStream_t st);
 // with_dt: the first stage of a step, whose sensor also reduces the time-step
-// bounds (dt_in_sensor(D)); launch_dt_max then sets the step (they replace
-// launch_dt)
+// bounds (dt_in_sensor(D)); the stage's launch_iflags(set_dt) then sets the
+// step (they replace launch_dt)
 hipError_t launch_sensor(const Desc& D, int stage, bool export_theta, hipStream_t st,
                          bool with_dt = false);
 bool dt_in_sensor(const Desc& D);
-hipError_t launch_dt_max(const Desc& D, hipStream_t st);
-hipError_t launch_iflags(const Desc& D, hipStream_t st);
+// set_dt: also set the step's time step from the first stage's sensor maxima
+hipError_t launch_iflags(const Desc& D, hipStream_t st, bool set_dt = false);
 hipError_t launch_weno(const Desc& D, int stage, hipStream_t st);
 // fuse_rk: the RK update of the stage in the same pass (rk_fused(D) only)
 hipError_t launch_rhs(const Desc& D, int stage, hipStream_t st, bool fuse_rk = false);

@@ -90,6 +90,7 @@ __device__ __forceinline__ int nidx32(const Desc& D, int i, int j, int k) {
 
 __device__ __forceinline__ void from_prim(const Desc& D, double r, double u, double v, double w,
                                           double p, double q[5]) {
+#pragma clang fp contract(off)
   q[0] = r;
   q[1] = r * u;
   q[2] = r * v;
@@ -100,9 +101,11 @@ __device__ __forceinline__ void from_prim(const Desc& D, double r, double u, dou
 // Ghost node of a staggered wall (y face `side`) from its mirror image qm:
 // velocity reversed, pressure copied, temperature 2 T_w - T (isothermal) or
 // T (adiabatic).  A non-positive ghost temperature is reported in the
-// status word.
+// status word.  Without contraction, so that its bits do not depend on the
+// kernel that evaluates it (single and batched ghost fills).
 __device__ __forceinline__ void wall_ghost(const Desc& D, int kind, int side, const double qm[5],
                                            double q[5]) {
+#pragma clang fp contract(off)
   const double rr = qm[0], ir = 1.0 / rr;
   const double u = qm[1] * ir, v = qm[2] * ir, ww = qm[3] * ir;
   const double T = (qm[4] * ir - 0.5 * (u * u + v * v + ww * ww)) * D.icv;
@@ -1070,9 +1073,10 @@ __device__ void sensor_tile(const Desc& D, const double* __restrict__ w, int lb,
 }
 
 // DT (first stage of a step): the kernel also folds the nodes' time-step
-// bounds into D.dtmax, one atomic maximum per wave on the bit patterns
+// bounds into D.dtmax, one atomic maximum per block on the bit patterns
 // (ordered like the values for non-negative doubles, so the result is the
-// exact maximum whatever the order); k_dt_max turns them into the step.
+// exact maximum whatever the order); the stage's k_iflags turns them into
+// the step.
 template <bool DT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DT ? 3 : 4))) k_sensor(Desc D, int stage, int export_theta) {
   __shared__ SenSmem S;
@@ -1199,6 +1203,16 @@ __device__ __forceinline__ void iface_masks_row(const Desc& D, int n0, int i0, i
 // reading the list touches consecutive nodes in consecutive lanes.
 constexpr int kIflagsPer = 16;
 
+// The step's time step from the maxima the first stage's sensor folded into
+// D.dtmax, which are cleared for the next step (one thread).
+__device__ __forceinline__ void dt_from_max(const Desc& D) {
+  const double cm = __longlong_as_double((long long)D.dtmax[0]);
+  const double vm = __longlong_as_double((long long)D.dtmax[1]);
+  dt_set(D, cm, vm);
+  D.dtmax[0] = 0ull;
+  D.dtmax[1] = 0ull;
+}
+
 template <int L>
 __device__ __forceinline__ void iflags_body(const Desc& D, long long blk) {
   __shared__ unsigned sm[4];
@@ -1286,8 +1300,14 @@ __device__ __forceinline__ void iflags_body(const Desc& D, long long blk) {
   __syncthreads();
 }
 
+// set_dt (first stage of a step whose sensor reduced the time-step bounds):
+// one thread also sets the step's time step, which no earlier kernel of the
+// stage reads.
 template <int L>
-__global__ void __launch_bounds__(256) k_iflags(Desc D) { iflags_body<L>(D, blockIdx.x); }
+__global__ void __launch_bounds__(256) k_iflags(Desc D, int set_dt) {
+  if (set_dt && blockIdx.x == 0 && threadIdx.x == 0) dt_from_max(D);
+  iflags_body<L>(D, blockIdx.x);
+}
 
 // ------------------------------------------------------------------ WENO on lists
 template <typename F, int DIR, int R>
@@ -1394,11 +1414,24 @@ __device__ double block_min(double v, double* sm) {
   return t;
 }
 
-__device__ __forceinline__ void force_body(const Desc& D, double* sm) {
+// Bulk force from the fused kernel's per-block partial sums of R_rhou dV,
+// reduced by one wave without barriers: lane l sums partials l, l+64, ...
+// in order, then a butterfly of exchanges adds the lanes' sums.  Each step
+// adds the same two values in every lane of a pair (x + y and y + x are the
+// same number), so every lane, wave and kernel gets the same bits.
+__device__ __forceinline__ double force_wave(const Desc& D) {
+  const int lane = threadIdx.x & 63;
   double v = 0.0;
-  for (int q = threadIdx.x; q < D.npart; q += 256) v += D.part[q];
-  const double t = block_sum<256>(v, sm);
-  if (threadIdx.x == 0) D.scal[SC_FORCE] = -t / D.vol_den;
+  for (int q = lane; q < D.npart; q += 64) v += D.part[q];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return -v / D.vol_den;
+}
+
+__device__ __forceinline__ void force_body(const Desc& D, double* sm) {
+  (void)sm;
+  const double f = force_wave(D);
+  if (threadIdx.x == 0) D.scal[SC_FORCE] = f;
 }
 
 // ------------------------------------------------------------------ fused right-hand side
@@ -1982,7 +2015,7 @@ __global__ void __launch_bounds__(256) k_rk(Desc D, int stage) {
 // step's flux kernel and by the diagnostics.
 template <int stage>
 __device__ __forceinline__ void rk_forced_block_s(const Desc& D, long long blk) {
-  const double f = D.scal[SC_FORCE];
+  const double f = D.scal[SC_FORCE];  // reduced by the forcing kernel
   const double alpha = stage == 0 ? 0.0 : (stage == 1 ? -17.0 / 60.0 : -5.0 / 12.0);
   const double beta = stage == 0 ? 8.0 / 15.0 : (stage == 1 ? 5.0 / 12.0 : 3.0 / 4.0);
   const double* __restrict__ w = D.win[stage];
@@ -2081,21 +2114,6 @@ __global__ void __launch_bounds__(256) k_dt_final(Desc D, int nb) {
   dt_final_body(D, nb, sm);
 }
 
-// The step's time step from the maxima the first stage's sensor folded into
-// D.dtmax, which are cleared for the next step.
-__global__ void k_dt_max(Desc D) {
-  if (threadIdx.x != 0) return;
-  const double cm = __longlong_as_double((long long)D.dtmax[0]);
-  const double vm = __longlong_as_double((long long)D.dtmax[1]);
-  dt_set(D, cm, vm);
-  D.dtmax[0] = 0ull;
-  D.dtmax[1] = 0ull;
-}
-
-hipError_t launch_dt_max(const Desc& D, hipStream_t st) {
-  k_dt_max<<<1, 64, 0, st>>>(D);
-  return hipGetLastError();
-}
 
 // ------------------------------------------------------------------ diagnostics
 // Per-block partials of the volume integrals and extrema of the state w,
@@ -2319,11 +2337,12 @@ hipError_t launch_export_iface(const Desc& D, int dir, double* out, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_iflags(const Desc& D, hipStream_t st) {
+hipError_t launch_iflags(const Desc& D, hipStream_t st, bool set_dt) {
   const unsigned nb = nblk(D.N, 256 * kIflagsPer);
-  if (D.cl == 1) k_iflags<1><<<nb, 256, 0, st>>>(D);
-  else if (D.cl == 3) k_iflags<3><<<nb, 256, 0, st>>>(D);
-  else k_iflags<2><<<nb, 256, 0, st>>>(D);
+  const int sd = set_dt ? 1 : 0;
+  if (D.cl == 1) k_iflags<1><<<nb, 256, 0, st>>>(D, sd);
+  else if (D.cl == 3) k_iflags<3><<<nb, 256, 0, st>>>(D, sd);
+  else k_iflags<2><<<nb, 256, 0, st>>>(D, sd);
   return hipGetLastError();
 }
 
