@@ -410,8 +410,10 @@ __device__ __forceinline__ void wflux(const PV<F>* nd, F f[5]) {
 // is four times the regulariser: the callers pass twice the split fluxes
 // (the factor 1/2 of the splitting is applied once to the sum), and
 // scaling the inputs by 2 scales the smoothness indicators by exactly 4,
-// so the weights are those of the unscaled reconstruction.
-// The reconstruction is num / den; the caller divides.
+// so the weights are those of the unscaled reconstruction.  The indicators
+// are formed times 12/13 (d^2 + (3/13) e^2 + (12/13) eps): a common factor
+// of the three cancels in the normalised weights.  The reconstruction is
+// num / (6 den); the caller divides (half_sum folds the 6).
 template <typename F>
 __device__ __forceinline__ void weno5(F vm2, F vm1, F v0, F vp1, F vp2, F eps4, F& num, F& den) {
 #pragma clang fp contract(off)
@@ -422,22 +424,23 @@ __device__ __forceinline__ void weno5(F vm2, F vm1, F v0, F vp1, F vp2, F eps4, 
   const F d0 = fma(F(-2), vm1, vm2 + v0), e0 = fma(F(3), v0, fma(F(-4), vm1, vm2));
   const F d1 = fma(F(-2), v0, vm1 + vp1), e1 = vm1 - vp1;
   const F d2 = fma(F(-2), vp1, v0 + vp2), e2 = fma(F(3), v0, fma(F(-4), vp1, vp2));
-  const F c13 = F(13.0 / 12.0), c14 = F(0.25);
-  const F s0 = fma(c13 * d0, d0, fma(c14 * e0, e0, eps4));
-  const F s1 = fma(c13 * d1, d1, fma(c14 * e1, e1, eps4));
-  const F s2 = fma(c13 * d2, d2, fma(c14 * e2, e2, eps4));
+  const F c3 = F(3.0 / 13.0), ce = F(12.0 / 13.0) * eps4;
+  const F s0 = fma(d0, d0, fma(c3 * e0, e0, ce));
+  const F s1 = fma(d1, d1, fma(c3 * e1, e1, ce));
+  const F s2 = fma(d2, d2, fma(c3 * e2, e2, ce));
   // weights d_k/(eps+beta_k)^2 normalised, with numerator and denominator
   // multiplied by 10 times the product of the three squares (d = 0.1, 0.6,
   // 0.3 become 1, 6, 3): a = (t1 t2, 6 t0 t2, 3 t0 t1), one reciprocal
   const F t0 = s0 * s0, t1 = s1 * s1, t2 = s2 * s2;
   const F P = t1 * t2, B = F(3) * t1, C = F(6) * t2;
   num = fma(P, q0, t0 * fma(C, q1, B * q2));
-  den = F(6) * fma(t0, C + B, P);
+  den = fma(t0, C + B, P);
 }
 
 // WENO3-JS (two candidate stencils, linear weights 1/3, 2/3) at i+1/2 from
 // v_{i-1..i+1}, same input scaling as weno5; numerator and denominator are
-// multiplied by 3 t0 t1 (a = (t1, 2 t0)) and the candidates by 2.
+// multiplied by 3 t0 t1 (a = (t1, 2 t0)) and the candidates by 2: the
+// reconstruction is num / (2 den).
 template <typename F>
 __device__ __forceinline__ void weno3(F vm1, F v0, F vp1, F eps4, F& num, F& den) {
 #pragma clang fp contract(off)
@@ -447,16 +450,18 @@ __device__ __forceinline__ void weno3(F vm1, F v0, F vp1, F eps4, F& num, F& den
   const F s0 = fma(d0, d0, eps4), s1 = fma(d1, d1, eps4);
   const F t0 = s0 * s0, t1 = s1 * s1;
   num = fma(t1, q0, (F(2) * t0) * q1);
-  den = F(2) * fma(F(2), t0, t1);
+  den = fma(F(2), t0, t1);
 }
 
 // WENO7-JS (four candidate stencils, linear weights (1, 12, 18, 4)/35) at
 // i+1/2 from v[0..6] = v_{i-3..i+3}, same input scaling as weno5.  The
 // smoothness indicators are Balsara and Shu's quadratic forms divided by
 // 240 (which makes them the integrals of the squared derivatives of the
-// candidate polynomials over the cell, as for the other orders); the
-// candidates are multiplied by 12 and the weights formed with one
-// reciprocal each (a product form would overflow in FP32).
+// candidate polynomials over the cell, as for the other orders), here
+// formed times 240 with the regulariser likewise (the common factor cancels
+// in the normalised weights); the candidates are multiplied by 12 and the
+// weights formed with one reciprocal each (a product form would overflow in
+// FP32).  The reconstruction is num / (12 den).
 template <typename F>
 __device__ __forceinline__ void weno7(const F* v, F eps4, F& num, F& den) {
 #pragma clang fp contract(off)
@@ -465,45 +470,49 @@ __device__ __forceinline__ void weno7(const F* v, F eps4, F& num, F& den) {
   const F q1 = fma(F(3), f, fma(F(13), e, fma(F(-5), d, b)));
   const F q2 = fma(F(7), f, fma(F(7), e, -d)) - g;
   const F q3 = fma(F(3), e, fma(F(13), f, fma(F(-5), g, h)));
-  const F c240 = F(1.0 / 240.0);
   // sum of x_k times a linear form, the last term a square
-  const F b0 = c240 * fma(a, fma(F(-1854), e, fma(F(4642), d, fma(F(-3882), b, F(547) * a))),
-                          fma(b, fma(F(7042), e, fma(F(-17246), d, F(7043) * b)),
-                              fma(d, fma(F(-9402), e, F(11003) * d), (F(2107) * e) * e)));
-  const F b1 = c240 * fma(b, fma(F(-494), f, fma(F(1602), e, fma(F(-1642), d, F(267) * b))),
-                          fma(d, fma(F(1922), f, fma(F(-5966), e, F(2843) * d)),
-                              fma(e, fma(F(-2522), f, F(3443) * e), (F(547) * f) * f)));
-  const F b2 = c240 * fma(d, fma(F(-494), g, fma(F(1922), f, fma(F(-2522), e, F(547) * d))),
-                          fma(e, fma(F(1602), g, fma(F(-5966), f, F(3443) * e)),
-                              fma(f, fma(F(-1642), g, F(2843) * f), (F(267) * g) * g)));
-  const F b3 = c240 * fma(e, fma(F(-1854), h, fma(F(7042), g, fma(F(-9402), f, F(2107) * e))),
-                          fma(f, fma(F(4642), h, fma(F(-17246), g, F(11003) * f)),
-                              fma(g, fma(F(-3882), h, F(7043) * g), (F(547) * h) * h)));
-  const F s0 = eps4 + b0, s1 = eps4 + b1, s2 = eps4 + b2, s3 = eps4 + b3;
+  const F b0 = fma(a, fma(F(-1854), e, fma(F(4642), d, fma(F(-3882), b, F(547) * a))),
+                   fma(b, fma(F(7042), e, fma(F(-17246), d, F(7043) * b)),
+                       fma(d, fma(F(-9402), e, F(11003) * d), (F(2107) * e) * e)));
+  const F b1 = fma(b, fma(F(-494), f, fma(F(1602), e, fma(F(-1642), d, F(267) * b))),
+                   fma(d, fma(F(1922), f, fma(F(-5966), e, F(2843) * d)),
+                       fma(e, fma(F(-2522), f, F(3443) * e), (F(547) * f) * f)));
+  const F b2 = fma(d, fma(F(-494), g, fma(F(1922), f, fma(F(-2522), e, F(547) * d))),
+                   fma(e, fma(F(1602), g, fma(F(-5966), f, F(3443) * e)),
+                       fma(f, fma(F(-1642), g, F(2843) * f), (F(267) * g) * g)));
+  const F b3 = fma(e, fma(F(-1854), h, fma(F(7042), g, fma(F(-9402), f, F(2107) * e))),
+                   fma(f, fma(F(4642), h, fma(F(-17246), g, F(11003) * f)),
+                       fma(g, fma(F(-3882), h, F(7043) * g), (F(547) * h) * h)));
+  const F e240 = F(240) * eps4;
+  const F s0 = e240 + b0, s1 = e240 + b1, s2 = e240 + b2, s3 = e240 + b3;
   const F w0 = wrcp<F>(s0 * s0), w1 = F(12) * wrcp<F>(s1 * s1);
   const F w2 = F(18) * wrcp<F>(s2 * s2), w3 = F(4) * wrcp<F>(s3 * s3);
   num = fma(w0, q0, fma(w1, q1, fma(w2, q2, w3 * q3)));
-  den = F(12) * (((w0 + w1) + w2) + w3);
+  den = ((w0 + w1) + w2) + w3;
 }
 
 // Reconstruction of order 2R-1 at i+1/2 from v[0..2R-2] = v_{i-R+1..i+R-1},
-// as num / den.
+// as num / (wden<R>() den).
 template <typename F, int R>
 __device__ __forceinline__ void wrec(const F* v, F eps4, F& num, F& den) {
   if constexpr (R == 2) weno3<F>(v[0], v[1], v[2], eps4, num, den);
   else if constexpr (R == 3) weno5<F>(v[0], v[1], v[2], v[3], v[4], eps4, num, den);
   else weno7<F>(v, eps4, num, den);
 }
+template <int R>
+__host__ __device__ constexpr double wden() { return R == 2 ? 2.0 : (R == 3 ? 6.0 : 12.0); }
 
-// Half the sum of the two reconstructions np/dp + nm/dm.  In FP64 with one
-// reciprocal, (np dm + nm dp) / (2 dp dm): the denominators are products of
-// up to four squared indicators (each at least the regulariser), so their
-// product stays far inside the FP64 range; FP32 takes one reciprocal each.
-template <typename F>
+// Half the sum of the two reconstructions np/(c dp) + nm/(c dm), c =
+// wden<R>().  In FP64 with one reciprocal, (np dm + nm dp) / (2 c dp dm):
+// the denominators are products of up to four squared indicators (each at
+// least the regulariser), so their product stays far inside the FP64
+// range; FP32 takes one reciprocal each.
+template <typename F, int R>
 __device__ __forceinline__ F half_sum(F np, F dp, F nm, F dm) {
 #pragma clang fp contract(off)
-  if constexpr (sizeof(F) == 8) return fma(np, dm, nm * dp) * wrcp<F>(F(2) * (dp * dm));
-  else return F(0.5) * fma(np, wrcp<F>(dp), nm * wrcp<F>(dm));
+  if constexpr (sizeof(F) == 8)
+    return fma(np, dm, nm * dp) * wrcp<F>(F(2.0 * wden<R>()) * (dp * dm));
+  else return F(0.5 / wden<R>()) * fma(np, wrcp<F>(dp), nm * wrcp<F>(dm));
 }
 
 // Quantities of one stencil node of the shock-capturing flux along DIR: the
@@ -620,7 +629,7 @@ __device__ __forceinline__ void weno_flux(const Desc& D, NodeGet&& node, F out[5
     F np, dp, nm, dm;
     wrec<F, R>(vp, eps4, np, dp);
     wrec<F, R>(vm, eps4, nm, dm);
-    gh[k] = half_sum<F>(np, dp, nm, dm);
+    gh[k] = half_sum<F, R>(np, dp, nm, dm);
   }
   // right eigenvectors applied to the reconstructed characteristic flux
   const F sg = (gh[0] + gh[1]) + gh[4];

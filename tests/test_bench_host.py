@@ -47,6 +47,6 @@ def test_weno_flop_count_belongs_to_the_current_code():
     assert bench.weno_source_hash() == bench.WENO_FLOPS_SOURCE_HASH
     # totals from their parts: one node's quantities, Roe and constants, the
     # stencil nodes' projections, 5 fields, back-projection
-    assert bench.WENO_FLOPS_BY_ORDER[5] == 15 + 47 + 6 * 38 + 5 * (2 * 5 * 2 + 2 * 65 + 7) + 26
-    assert bench.WENO_FLOPS_BY_ORDER[3] == 15 + 47 + 4 * 38 + 5 * (2 * 3 * 2 + 2 * 18 + 7) + 26
-    assert bench.WENO_FLOPS_BY_ORDER[7] == 15 + 47 + 8 * 38 + 5 * (2 * 7 * 2 + 2 * 146 + 7) + 26
+    assert bench.WENO_FLOPS_BY_ORDER[5] == 15 + 47 + 6 * 38 + 5 * (2 * 5 * 2 + 2 * 61 + 7) + 26
+    assert bench.WENO_FLOPS_BY_ORDER[3] == 15 + 47 + 4 * 38 + 5 * (2 * 3 * 2 + 2 * 17 + 7) + 26
+    assert bench.WENO_FLOPS_BY_ORDER[7] == 15 + 47 + 8 * 38 + 5 * (2 * 7 * 2 + 2 * 141 + 7) + 26
