@@ -921,8 +921,10 @@ __device__ __forceinline__ void dt_set(const Desc& D, double cm, double vm) {
 // velocities for planes c-2..c+2 in registers.
 constexpr int kSenTX = 64, kSenTY = 4, kSenKz = 16;
 
+// two plane buffers, used alternately: a plane's staging never waits for
+// the previous plane's readers (one barrier per plane)
 struct SenSmem {
-  double v[3][kSenTY + 4][kSenTX + 4];
+  double v[2][3][kSenTY + 4][kSenTX + 4];
 };
 
 int sensor_tiles(const Desc& D) {
@@ -1024,10 +1026,14 @@ __device__ void sensor_tile(const Desc& D, const double* __restrict__ w, int lb,
   fetch_col(kb + 2, qc);
   fetch_halo(kb, qh);
   for (int c = kb; c < ke; ++c) {
+    // this plane's buffer was last read in plane c-2, which every thread
+    // finished before passing plane c-1's barrier: no barrier before the
+    // writes
+    double(&V3)[3][kSenTY + 4][kSenTX + 4] = S.v[(c - kb) & 1];
     vel(qc, U[4], V[4], W[4]);
-    S.v[0][ty + 2][tx + 2] = U[2];
-    S.v[1][ty + 2][tx + 2] = V[2];
-    S.v[2][ty + 2][tx + 2] = W[2];
+    V3[0][ty + 2][tx + 2] = U[2];
+    V3[1][ty + 2][tx + 2] = V[2];
+    V3[2][ty + 2][tx + 2] = W[2];
 #pragma unroll
     for (int r = 0; r < HPS; ++r) {
       const int h = tid + r * 256;
@@ -1036,9 +1042,9 @@ __device__ void sensor_tile(const Desc& D, const double* __restrict__ w, int lb,
         halo_pos(h, lx, ly);
         double u, v, ww;
         vel(qh[r], u, v, ww);
-        S.v[0][ly][lx] = u;
-        S.v[1][ly][lx] = v;
-        S.v[2][ly][lx] = ww;
+        V3[0][ly][lx] = u;
+        V3[1][ly][lx] = v;
+        V3[2][ly][lx] = ww;
       }
     }
     // (after the halo conversion, when its registers are free)
@@ -1054,10 +1060,10 @@ __device__ void sensor_tile(const Desc& D, const double* __restrict__ w, int lb,
       double g[3][3];
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        g[q][0] = D.idx * (CA1 * (S.v[q][ly][lx + 1] - S.v[q][ly][lx - 1]) +
-                           CA2 * (S.v[q][ly][lx + 2] - S.v[q][ly][lx - 2]));
-        g[q][1] = iy * (CA1 * (S.v[q][ly + 1][lx] - S.v[q][ly - 1][lx]) +
-                        CA2 * (S.v[q][ly + 2][lx] - S.v[q][ly - 2][lx]));
+        g[q][0] = D.idx * (CA1 * (V3[q][ly][lx + 1] - V3[q][ly][lx - 1]) +
+                           CA2 * (V3[q][ly][lx + 2] - V3[q][ly][lx - 2]));
+        g[q][1] = iy * (CA1 * (V3[q][ly + 1][lx] - V3[q][ly - 1][lx]) +
+                        CA2 * (V3[q][ly + 2][lx] - V3[q][ly - 2][lx]));
       }
       g[0][2] = D.idz * (CA1 * (U[3] - U[1]) + CA2 * (U[4] - U[0]));
       g[1][2] = D.idz * (CA1 * (V[3] - V[1]) + CA2 * (V[4] - V[0]));
@@ -1071,7 +1077,6 @@ __device__ void sensor_tile(const Desc& D, const double* __restrict__ w, int lb,
       D.nflag[n] = th > D.theta_star ? 1 : 0;
       if (export_theta) D.theta[n] = th;
     }
-    __syncthreads();
 #pragma unroll
     for (int sl = 0; sl < 4; ++sl) {
       U[sl] = U[sl + 1];
@@ -1079,6 +1084,7 @@ __device__ void sensor_tile(const Desc& D, const double* __restrict__ w, int lb,
       W[sl] = W[sl + 1];
     }
   }
+  __syncthreads();  // the buffers are free for the block's next tile
 }
 
 // DT (first stage of a step): the kernel also folds the nodes' time-step
