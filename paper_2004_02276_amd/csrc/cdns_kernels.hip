@@ -935,7 +935,7 @@ int sensor_tiles(const Desc& D) {
 // DT: the tile also folds its nodes' time-step bounds into cm and vm (the
 // step's first stage, whose input is the state the step starts from).
 template <bool DT = false>
-__device__ void sensor_tile(const Desc& D, const double* __restrict__ w, int lb, SenSmem& S,
+__device__ __forceinline__ void sensor_tile(const Desc& D, const double* __restrict__ w, int lb, SenSmem& S,
                             bool export_theta, double* cm = nullptr, double* vm = nullptr) {
   constexpr int LX = kSenTX + 4;
   const int stx = (D.nx + kSenTX - 1) / kSenTX, sty = (D.ny + kSenTY - 1) / kSenTY;
