@@ -919,7 +919,15 @@ __device__ __forceinline__ void dt_set(const Desc& D, double cm, double vm) {
 // 2.5-D tiling: a 64x4 tile of velocities with a 2-node cross-shaped halo
 // is staged in LDS plane by plane; each thread keeps its own column's
 // velocities for planes c-2..c+2 in registers.
-constexpr int kSenTX = 64, kSenTY = 4, kSenKz = 16;
+constexpr int kSenTX = 64, kSenTY = 4;
+
+// z planes per sensor block: 16, or 32 where that still leaves at least
+// 2,048 blocks (eight per CU), which halves the share of the four planes
+// each block loads only to fill its z window
+__host__ __device__ inline int sensor_kz(const Desc& D) {
+  const int t = ((D.nx + kSenTX - 1) / kSenTX) * ((D.ny + kSenTY - 1) / kSenTY);
+  return t * ((D.nz + 31) / 32) >= 2048 ? 32 : 16;
+}
 
 // two plane buffers, used alternately: a plane's staging never waits for
 // the previous plane's readers (one barrier per plane)
@@ -929,7 +937,7 @@ struct SenSmem {
 
 int sensor_tiles(const Desc& D) {
   return ((D.nx + kSenTX - 1) / kSenTX) * ((D.ny + kSenTY - 1) / kSenTY) *
-         ((D.nz + kSenKz - 1) / kSenKz);
+         ((D.nz + sensor_kz(D) - 1) / sensor_kz(D));
 }
 
 // DT: the tile also folds its nodes' time-step bounds into cm and vm (the
@@ -942,7 +950,8 @@ __device__ __forceinline__ void sensor_tile(const Desc& D, const double* __restr
   const int txi = lb % stx, rem = lb / stx;
   const int tyi = rem % sty, zc = rem / sty;
   const int i0 = txi * kSenTX, j0 = tyi * kSenTY;
-  const int kb = zc * kSenKz, ke = min(kb + kSenKz, D.nz);
+  const int kz = sensor_kz(D);
+  const int kb = zc * kz, ke = min(kb + kz, D.nz);
   const int tid = threadIdx.x, tx = tid % kSenTX, ty = tid / kSenTX;
   const int i = i0 + tx, j = j0 + ty;
   const bool valid = i < D.nx && j < D.ny;
