@@ -149,24 +149,40 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(pr):
+def _oracle_rate(pr, budget_s=10.0, max_steps=30):
+    """Oracle steps of the full workload from its seeded initial field for
+    about budget_s seconds: (Mpoint-RK-steps/s, steps, seconds)."""
     import oracle
-    oracle.build(force=False)
     w = pr.w0
-    nthreads = oracle.num_threads()
     steps = 0
     t0 = time.perf_counter()
     while True:
         w = oracle.advance(pr, 1, w=w, cfl=pr.cfl)
         steps += 1
         el = time.perf_counter() - t0
-        if el > 10.0 or steps >= 30:  # about 10 s of the host cores
+        if el > budget_s or steps >= max_steps:
             break
-    rate = pr.npts * steps / el / 1e6
-    return {"value": rate, "unit": "Mpoint-RK-steps/s", "cores": nthreads, "kind": "oracle",
-            "cpu": cpu_model(),
-            "sample": f"{steps} RK3 step(s) of the full {pr.name} workload from the same seeded "
-                      f"initial field, {el:.1f} s wall"}
+    return pr.npts * steps / el / 1e6, steps, el
+
+
+def cpu_baseline(pr, single_thread=False):
+    import oracle
+    oracle.build(force=False)
+    nthreads = oracle.num_threads()
+    rate, steps, el = _oracle_rate(pr)  # about 10 s of the host cores
+    out = {"value": rate, "unit": "Mpoint-RK-steps/s", "cores": nthreads, "kind": "oracle",
+           "cpu": cpu_model(),
+           "sample": f"{steps} RK3 step(s) of the full {pr.name} workload from the same seeded "
+                     f"initial field, {el:.1f} s wall"}
+    if single_thread:
+        prev = oracle.set_threads(1)
+        try:
+            r1, s1, e1 = _oracle_rate(pr)
+        finally:
+            oracle.set_threads(prev)
+        out["single_thread"] = {"value": r1, "cores": 1,
+                                "sample": f"{s1} RK3 step(s), {e1:.1f} s wall"}
+    return out
 
 
 def main():
@@ -288,7 +304,7 @@ def main():
     }
     s.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pr)
+        out["cpu_baseline"] = cpu_baseline(pr, single_thread=(args.workload == "tgv"))
     print(json.dumps(out), flush=True)
 
 

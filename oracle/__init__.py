@@ -115,6 +115,8 @@ def _load():
         lib.ora_iface_flux.restype = ctypes.c_int
         lib.ora_num_threads.argtypes = []
         lib.ora_num_threads.restype = ctypes.c_int
+        lib.ora_set_threads.argtypes = [ctypes.c_int]
+        lib.ora_set_threads.restype = ctypes.c_int
         lib.ora_stats.argtypes = [pp, dp, dp]
         lib.ora_stats.restype = ctypes.c_int
         lib.ora_stats_means.argtypes = [pp, dp, ctypes.c_long, ctypes.c_int, dp]
@@ -345,6 +347,12 @@ def lf_alpha(pr, d: int, i: int, j: int, k: int, w: Optional[np.ndarray] = None)
 
 def num_threads() -> int:
     return _load().ora_num_threads()
+
+
+def set_threads(n: int) -> int:
+    """Thread count of the oracle's parallel loops from now on (timing only:
+    results do not depend on it); returns the previous count."""
+    return int(_load().ora_set_threads(int(n)))
 
 
 def splitmix64(seed: int, n: int) -> int:

@@ -1363,6 +1363,19 @@ int ora_num_threads(void) {
   return n;
 }
 
+/* Thread count of the following parallel loops (n >= 1; a no-op without
+ * OpenMP); returns the previous count.  For timing only: every result is
+ * independent of the thread count. */
+int ora_set_threads(int n) {
+  int prev = ora_num_threads();
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+  return prev;
+}
+
 /* Test hook: the interface fluxes of direction d exactly as used by the
  * right-hand side (central, shock-capturing or wall), interface i+1/2
  * stored at node i, layout out[5][nz][ny][nx]. */

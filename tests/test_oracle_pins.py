@@ -540,3 +540,19 @@ def test_invalid_configurations_are_rejected():
     w0[0, 1, 2, 3] = -1.0
     with pytest.raises(oracle.OracleError):
         oracle.rhs(P.with_state(pr, w0))
+
+
+def test_results_do_not_depend_on_the_thread_count():
+    # the oracle's parallel loops write disjoint outputs and reduce only with
+    # a bitwise or, so a state after several steps is the same bit for bit
+    # on one thread and on all of them
+    pr = P.decaying_turbulence(12, mach=0.5, re=500.0, seed=3)
+    prev = oracle.set_threads(1)
+    try:
+        assert oracle.num_threads() == 1
+        w1 = oracle.advance(pr, 3, cfl=pr.cfl)
+    finally:
+        oracle.set_threads(prev)
+    assert oracle.num_threads() == prev
+    wn = oracle.advance(pr, 3, cfl=pr.cfl)
+    assert np.array_equal(w1, wn)
