@@ -149,6 +149,23 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Practical HBM rate on this GPU: a device-to-device copy of nbytes,
+    (read + written bytes) / mean time of reps copies, GB/s."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def _oracle_rate(pr, budget_s=10.0, max_steps=30):
     """Oracle steps of the full workload from its seeded initial field for
     about budget_s seconds: (Mpoint-RK-steps/s, steps, seconds)."""
@@ -218,6 +235,7 @@ def main():
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
+    copy_gbs = copy_bandwidth(torch)
     pr = getattr(P, WORKLOADS[args.workload][0])()
     pr = dataclasses.replace(pr, central_order=args.central_order, weno_order=args.weno_order)
     # counter-based traffic figures were taken with the default scheme
@@ -301,6 +319,7 @@ def main():
         "weno_frac_last_stage": d["weno_frac"],
         "weno_interfaces_per_step": n_iface_total / args.steps,
         "roofline": roof,
+        "hbm_copy_GBps": copy_gbs,
     }
     s.close()
     if not args.no_cpu_baseline:
