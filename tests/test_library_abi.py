@@ -47,6 +47,23 @@ def test_workspace_size_is_host_only_and_validates():
     assert lib.cdns_workspace_bytes(ctypes.byref(g), 7) == 0
 
 
+def test_workspace_size_at_the_largest_grid():
+    # node indices are 32-bit inside the kernels: a grid of 2^31 nodes or
+    # more is rejected, one just below is sized (its workspace, 100 GB and
+    # more, is then a matter for the device's memory)
+    from paper_2004_02276_amd import _binding as B
+    lib = B.load()
+    dp = ctypes.POINTER(ctypes.c_double)
+    ye = np.full(1024, 2.0)
+    yee = np.zeros(1024)
+    g_max = B.Grid(2047, 1024, 1024, 1.0, 1.0, ye.ctypes.data_as(dp), yee.ctypes.data_as(dp))
+    n = lib.cdns_workspace_bytes(ctypes.byref(g_max), 0)
+    N = 2047 * 1024 * 1024
+    assert N < 2 ** 31 and n > 5 * N * 8 * 4 and n % 256 == 0
+    g_over = B.Grid(2048, 1024, 1024, 1.0, 1.0, ye.ctypes.data_as(dp), yee.ctypes.data_as(dp))
+    assert lib.cdns_workspace_bytes(ctypes.byref(g_over), 0) == 0
+
+
 def test_create_rejects_bad_arguments_before_touching_the_device():
     from paper_2004_02276_amd import _binding as B
     lib = B.load()
