@@ -234,10 +234,15 @@ cdns_status cdns_rhs(cdns_ctx* ctx, const double* w_dev, double* r_dev);
 
 /* One RK3 step of the state.  dt_fixed > 0 sets the step; otherwise
  * dt = cfl * min(1/max sum_d (|u_d|+c)/dx_d, 2.5/max[max(4/3,gamma/Pr)
- * (mu/rho)(16/3) sum_d dx_d^-2]) is computed on the device from w^n.
- * Without bulk forcing and in the default 64x4 tiling, each stage's update
- * is done by the right-hand-side kernel as it finishes a point (the same
- * rounding as the separate update kernel used otherwise). */
+ * (mu/rho) s2 sum_d dx_d^-2]) is computed on the device from w^n, s2 the
+ * largest magnitude of the central second-derivative symbol (16/3 at
+ * fourth order); with the hybrid sensor (and no digital-filter inflow) the
+ * first stage's sensor kernel reduces the two maxima.  In the default 64x4
+ * tiling each stage's update is done by the right-hand-side kernel as it
+ * finishes a point (the same rounding as the separate update kernel used
+ * otherwise): the whole update without bulk forcing; with forcing the
+ * rho, rho v and rho w components, rho u and rho E following in an update
+ * kernel once the force is reduced. */
 cdns_status cdns_rk_step(cdns_ctx* ctx, double cfl, double dt_fixed);
 
 /* n RK3 steps, replayed from one captured HIP graph per step. */
@@ -333,7 +338,10 @@ cdns_status cdns_export_iface_flux(cdns_ctx* ctx, int32_t dir, double* out_dev);
  * launches timed, weno_ifaces_out (may be NULL) the total number of
  * shock-capturing interfaces (all directions) processed by the timed WENO
  * launches.  Where the update runs inside the right-hand-side kernel (see
- * cdns_rk_step), CDNS_PH_RHS covers both and CDNS_PH_RK has no launches.
+ * cdns_rk_step), CDNS_PH_RHS covers both and CDNS_PH_RK times only the
+ * completion of a forced update; where the first stage's sensor reduces
+ * the time-step bounds, CDNS_PH_SENSOR covers both and CDNS_PH_DT has no
+ * launches.
  * Advances the state like cdns_rk_step; synchronises. */
 enum { CDNS_PH_DT = 0, CDNS_PH_GHOSTS, CDNS_PH_SENSOR, CDNS_PH_IFLAGS, CDNS_PH_WENO,
        CDNS_PH_RHS, CDNS_PH_FORCE, CDNS_PH_RK, CDNS_NPHASES };
