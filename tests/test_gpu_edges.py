@@ -151,3 +151,26 @@ def test_uniform_state_has_zero_rhs(torch_cuda, mode):
             f"(p/dx {scale:.1e})")
         assert np.abs(r_o).max() <= 1e-12 * scale
         assert np.abs(r_g).max() <= 1e-12 * scale
+
+
+def test_time_step_same_from_sensor_and_from_its_own_pass(torch_cuda):
+    """The CFL time step equals the oracle's, and is the same bit for bit
+    whether the first stage's sensor reduces the bounds (hybrid sensor) or
+    the separate reduction does (shock capturing everywhere, sensor off):
+    both evaluate every node's bound with the same arithmetic and take
+    exact maxima."""
+    from paper_2004_02276_amd import Solver
+    say("[dt paths]")
+    for make in (lambda m: P.decaying_turbulence(24, mach=0.5, re=800.0, seed=11, sensor_mode=m),
+                 lambda m: dataclasses.replace(P.small_channel(24, 20, 12), sensor_mode=m)):
+        dts = []
+        for mode in (P.SENSOR_HYBRID, P.SENSOR_WENO_ALL, P.SENSOR_OFF):
+            pr = make(mode)
+            s = Solver(pr)
+            s.rk_step(cfl=0.8)
+            dts.append(s.diagnostics()["dt"])
+            s.close()
+        dt_o = oracle.dt(pr, cfl=0.8)
+        say(f"    {pr.name}: gpu {dts[0]:.17e} oracle {dt_o:.17e}")
+        assert dts[0] == dts[1] == dts[2], dts
+        assert abs(dts[0] - dt_o) <= 1e-12 * dt_o
