@@ -118,7 +118,8 @@ def weno_source_hash():
 
 
 def load_traffic(kernel, workload, steps, warmup):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    """HBM bytes per launch from committed rocprofv3 counter runs (one entry,
+    or a list of entries for several workloads, per kernel), if they were
     taken on the current kernel source, this workload and this step window
     (the channel's shock-capturing share decays over the run, so the bytes
     per launch depend on which steps are timed); else None."""
@@ -128,12 +129,15 @@ def load_traffic(kernel, workload, steps, warmup):
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    ent = t.get(kernel)
-    if (not ent or ent.get("source_hash") != kernel_source_hash() or
-            ent.get("workload") != workload or ent.get("steps") != steps or
-            ent.get("warmup") != warmup):
-        return None
-    return ent.get("hbm_bytes_per_launch")
+    ents = t.get(kernel) or []
+    if isinstance(ents, dict):  # one workload
+        ents = [ents]
+    h = kernel_source_hash()
+    for ent in ents:
+        if (ent.get("source_hash") == h and ent.get("workload") == workload and
+                ent.get("steps") == steps and ent.get("warmup") == warmup):
+            return ent.get("hbm_bytes_per_launch")
+    return None
 
 
 def cpu_model():

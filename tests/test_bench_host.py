@@ -23,6 +23,21 @@ def test_traffic_keyed_to_source_and_workload(monkeypatch):
     assert bench.load_traffic("k_weno", ent["workload"], st, wu) is None  # other source
 
 
+def test_traffic_entries_per_workload(tmp_path, monkeypatch):
+    """A kernel may carry one entry per workload (a list)."""
+    t = {"k_rhs": [{"source_hash": "a" * 16, "workload": "channel", "steps": 20, "warmup": 5,
+                    "hbm_bytes_per_launch": 1},
+                   {"source_hash": "a" * 16, "workload": "sbli", "steps": 20, "warmup": 5,
+                    "hbm_bytes_per_launch": 2}]}
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(t))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "a" * 16)
+    assert bench.load_traffic("k_rhs", "channel", 20, 5) == 1
+    assert bench.load_traffic("k_rhs", "sbli", 20, 5) == 2
+    assert bench.load_traffic("k_rhs", "bl", 20, 5) is None
+
+
 def test_source_hash_ignores_comments(tmp_path, monkeypatch):
     src = os.path.join(bench.ROOT, "paper_2004_02276_amd", "csrc", "cdns_kernels.hip")
     h0 = bench.kernel_source_hash()
