@@ -13,6 +13,7 @@
   interface (decaying turbulence at turbulent Mach 1).
 * The FP32-flux mode's stepping error against the FP64 oracle.
 """
+import os
 import sys
 import time
 
@@ -215,6 +216,74 @@ def test_full_size_channel_100_steps(torch_cuda):
     linf = [v["linf_rel"] for v in rep["fp32flux"].values()]
     assert max(l2) <= 1e-3 and max(linf) <= 0.2
     assert max(v["linf_rel"] for v in rep["fp64"].values()) <= STATE_TOL
+
+
+def _precision_fixture():
+    """Reference values of the oracle for the precision-mode workload
+    (written by tests/golden/make_precision_samples.py)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "channel512x256x256_100steps_oracle.txt")
+    if not os.path.exists(path):
+        pytest.skip("reference file not written (tests/golden/make_precision_samples.py)")
+    head, rows = {}, []
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#"):
+                continue
+            t = line.split()
+            if t[0] in ("dt", "steps", "max_abs", "l2_samples"):
+                head[t[0]] = [float(x) for x in t[1:]]
+            else:
+                rows.append([float(x) for x in t])
+    a = np.array(rows)
+    return (head["dt"][0], int(head["steps"][0]), np.array(head["max_abs"]),
+            np.array(head["l2_samples"]), a[:, :3].astype(np.int64), a[:, 3:].T)
+
+
+def test_precision_mode_at_its_size_against_oracle_samples(torch_cuda):
+    """Precision mode at its own size: the channel at 512x256x256 (33.5 M
+    points) over 100 RK steps at the fixed CFL-0.8 step of the initial
+    field, the FP64 and the FP32-flux paths against the FP64 oracle at
+    1,024 seeded sample nodes.  Relative errors per field (conserved and u,
+    T, p): the largest sampled difference over the field's largest
+    magnitude in the whole domain, and the sampled L2 ratio.  FP64 within
+    the state tolerance; FP32-flux bounded as at 256x128x128."""
+    import json
+    from paper_2004_02276_amd import Solver
+    dt, steps, max_abs, l2_ref, kji, w_ref = _precision_fixture()
+    pr = P.channel(512, 256, 256)
+    assert pr.w0.shape == (5, 256, 256, 512)
+    say(f"[precision] {pr.name}, {steps} steps at dt {dt:.6e}, {kji.shape[0]} samples")
+    k, j, i = kji[:, 0], kji[:, 1], kji[:, 2]
+
+    def derived(w):
+        cv = pr.R_gas / (pr.gamma - 1.0)
+        r = w[0]
+        ke = 0.5 * (w[1] ** 2 + w[2] ** 2 + w[3] ** 2) / r ** 2
+        T = (w[4] / r - ke) / cv
+        return np.stack([w[1] / r, T, r * pr.R_gas * T])
+
+    names = ["rho", "rho_u", "rho_v", "rho_w", "rho_E", "u", "T", "p"]
+    ref = np.concatenate([w_ref, derived(w_ref)])
+    rep = {}
+    for name, prec in (("fp64", 0), ("fp32flux", 1)):
+        s = Solver(pr, precision=prec)
+        s.advance(steps, dt_fixed=dt)
+        ws = s.get_state()[:, k, j, i]
+        d = s.diagnostics()
+        s.close()
+        assert d["step"] == steps
+        got = np.concatenate([ws, derived(ws)])
+        diff = got - ref
+        rep[name] = {nm: {"linf_rel": float(np.abs(diff[m]).max() / max_abs[m]),
+                          "l2_rel": float(np.linalg.norm(diff[m]) / l2_ref[m])}
+                     for m, nm in enumerate(names)}
+    say("    precision vs oracle samples " + json.dumps({"workload": pr.name, "steps": steps,
+                                                         "samples": int(kji.shape[0]),
+                                                         "vs_oracle": rep}))
+    assert max(v["linf_rel"] for v in rep["fp64"].values()) <= STATE_TOL
+    assert max(v["l2_rel"] for v in rep["fp32flux"].values()) <= 1e-3
+    assert max(v["linf_rel"] for v in rep["fp32flux"].values()) <= 0.2
 
 
 def test_half_resolution_sbli_200_steps(torch_cuda):
