@@ -1224,7 +1224,9 @@ __device__ __forceinline__ void iface_masks_row(const Desc& D, int n0, int i0, i
 // the block's segment; each thread owns kIflagsPer consecutive nodes, the
 // block stages its entries in LDS and writes the segment with coalesced
 // stores, so the segment is in node order and the shock-capturing kernel
-// reading the list touches consecutive nodes in consecutive lanes.
+// reading the list touches consecutive nodes in consecutive lanes; the
+// per-node list positions go through LDS too and leave as the block's
+// contiguous range.
 constexpr int kIflagsPer = 16;
 
 // The step's time step from the maxima the first stage's sensor folded into
@@ -1242,6 +1244,7 @@ __device__ __forceinline__ void iflags_body(const Desc& D, long long blk) {
   __shared__ unsigned sm[4];
   __shared__ unsigned base[3];
   __shared__ uint16_t seg[3][256 * kIflagsPer];  // entries as offsets from the block start
+  __shared__ int4 sst[256 * kIflagsPer / 4];      // the block's slots of one direction
   const int N = (int)D.N;  // below 2^31 (checked at creation)
   const int nb = (int)blk * (256 * kIflagsPer);
   const int n0 = nb + (int)threadIdx.x * kIflagsPer;
@@ -1310,15 +1313,21 @@ __device__ __forceinline__ void iflags_body(const Desc& D, long long blk) {
     int p = (int)(base[d] + off[d]);
 #pragma unroll
     for (int r = 0; r < kIflagsPer; ++r) sl[r] = ((msk[d] >> r) & 1u) ? p++ : -1;
-    if (n0 + kIflagsPer <= N) {  // n0 is 16-aligned: four 128-bit stores
-      int4* o4 = reinterpret_cast<int4*>(D.slot[d] + n0);
+    // staged in LDS, then stored as the block's contiguous range (each
+    // wave instruction writes 1 KiB of consecutive slots)
+    if (d > 0) __syncthreads();  // the previous direction's slots are read
 #pragma unroll
-      for (int q = 0; q < kIflagsPer / 4; ++q)
-        o4[q] = make_int4(sl[4 * q], sl[4 * q + 1], sl[4 * q + 2], sl[4 * q + 3]);
+    for (int q = 0; q < kIflagsPer / 4; ++q)
+      sst[threadIdx.x * (kIflagsPer / 4) + q] =
+          make_int4(sl[4 * q], sl[4 * q + 1], sl[4 * q + 2], sl[4 * q + 3]);
+    __syncthreads();
+    if (nb + 256 * kIflagsPer <= N) {
+      int4* o4 = reinterpret_cast<int4*>(D.slot[d] + nb);
+#pragma unroll
+      for (int q = 0; q < kIflagsPer / 4; ++q) o4[threadIdx.x + 256 * q] = sst[threadIdx.x + 256 * q];
     } else {
-#pragma unroll
-      for (int r = 0; r < kIflagsPer; ++r)
-        if (n0 + r < N) D.slot[d][n0 + r] = sl[r];
+      const int* si = reinterpret_cast<const int*>(sst);
+      for (int e = threadIdx.x; nb + e < N; e += 256) D.slot[d][nb + e] = si[e];
     }
   }
   __syncthreads();
