@@ -9,10 +9,13 @@ HIP-graph replays.  Prints one JSON line with the throughput of each
 precision, the speedup, and per field (rho, rho u, rho v, rho w, rho E and
 the derived u, T, p) the relative L-infinity and L2 differences of the
 FP32-flux state from the FP64 state.  The comparison of both precisions
-with the FP64 oracle after 100 steps is done at 256x128x128 by the GPU test
-tests/test_gpu_configs.py::test_full_size_channel_100_steps (the oracle
-takes about two minutes of host time there; at this size it would take
-about fifteen), which prints the same per-field report against the oracle.
+with the FP64 oracle after 100 steps is done by GPU tests: at 256x128x128
+over the whole field (tests/test_gpu_configs.py::
+test_full_size_channel_100_steps, the oracle taking about two minutes of
+host time), and at this size on 1,024 seeded sample nodes against the
+oracle's reference values, written once by
+tests/golden/make_precision_samples.py (about 80 minutes on 8 host
+threads; test_precision_mode_at_its_size_against_oracle_samples).
 """
 import argparse
 import json
