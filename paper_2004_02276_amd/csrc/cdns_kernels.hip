@@ -1132,16 +1132,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DT ? 3
 }
 
 // ------------------------------------------------------------------ interface flags + lists
+// Node flag at (i, j, k), each index within one period of its range (the
+// callers reach at most L <= 3 nodes beyond a face and every dimension is
+// at least 4), so the periodic images need no integer division.
 __device__ __forceinline__ uint8_t node_flag(const Desc& D, int i, int j, int k) {
   if (i < 0 || i >= D.nx) {
     if (!D.per_x) return 0;
-    i = wrapi(i, D.nx);
+    i = wrap1(i, D.nx);
   }
   if (j < 0 || j >= D.ny) {
     if (!D.per_y) return 0;
-    j = wrapi(j, D.ny);
+    j = wrap1(j, D.ny);
   }
-  k = wrapi(k, D.nz);
+  k = wrap1(k, D.nz);
   return D.nflag[nidx(D, i, j, k)];
 }
 
