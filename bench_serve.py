@@ -36,6 +36,9 @@ def main():
     ap.add_argument("--skip-serial", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip tuning kz per size class (use the cached or heuristic value)")
+    ap.add_argument("--batch-kz", type=int, default=32,
+                    help="z planes per fused-kernel block in batch mode (0: the per-instance "
+                         "tuned or heuristic value, as in serial mode)")
     ap.add_argument("--max-chunk", type=int, default=8,
                     help="batch steps replayed between host checks at most")
     args = ap.parse_args()
@@ -68,14 +71,18 @@ def main():
               f"{tuned}", file=sys.stderr, flush=True)
     kz_for = lambda pr: tuned.get(autotune.size_class(pr),
                                   autotune.lookup(pr, 0, fixed_tile=tile)[2])
+    # the per-class values are tuned on one instance alone, where small
+    # instances need shallow z chunks to fill the GPU; in a batch the
+    # residents fill it together, and deep chunks re-read fewer halo planes
+    batch_kz_for = (lambda pr: min(args.batch_kz, pr.nz)) if args.batch_kz > 0 else kz_for
     out = {"metric": "batched serving throughput and p50/p99 step latency",
            "requests": len(specs), "rate_per_s": args.rate, "steps": args.steps,
            "grid_range": [args.nmin, args.nmax], "budget_gb": budget / 1e9,
            "total_mpoint_steps": sum(s.n ** 3 * s.nsteps for s in specs) / 1e6,
-           "tuned_kz": tuned, "max_chunk": args.max_chunk}
+           "tuned_kz": tuned, "batch_kz": args.batch_kz, "max_chunk": args.max_chunk}
     for mode in (["batch"] if args.skip_serial else ["batch", "serial"]):
-        srv = Server(P.request_problem, budget, max_slots=64, tiling=tile, kz_for=kz_for,
-                     max_chunk=args.max_chunk)
+        srv = Server(P.request_problem, budget, max_slots=64, tiling=tile,
+                     kz_for=batch_kz_for if mode == "batch" else kz_for, max_chunk=args.max_chunk)
         rep = srv.run(specs, mode=mode, prebuilt=prebuilt)
         rep.pop("results")
         out[mode] = rep
